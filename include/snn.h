@@ -1,0 +1,212 @@
+/*
+ * snn.h -- C ABI of the MI355X clock-driven spiking-network simulator.
+ *
+ * The library simulates the work-queue pipeline of Bautembach et al., "Faster and
+ * Simpler SNN Simulation with Work Queues" (IJCNN 2020), Sec. III-A, Fig. 1: per step,
+ * Update Neurons emits a queue of spikes S_t; a FIFO of per-step queues delays them by
+ * d >= 1 steps (Sec. III-A.1, "non-instantaneous connections"); Receive Spikes
+ * delivers each dequeued spike over its neuron's out-edges; optionally Update
+ * Synapses applies STDP driven by S_{t-d} (pre) and S_t (post).  The network is built
+ * on the device from a seed (Init stage; adjacency generation of Sec. III-A.2, Fig. 2).
+ *
+ * Conventions
+ *  - Every call returns snn_status: SNN_OK (0) or a negative error code.  No C++
+ *    exception crosses this interface.  snn_last_error() returns a message for the
+ *    last failing call on the calling thread (storage owned by the library, valid
+ *    until the next call on that thread).
+ *  - snn_network is opaque; the library owns it and every device buffer it holds.
+ *    The caller owns every host array passed in or out.  Host arrays are read or
+ *    written before the call returns.
+ *  - Device work is issued on the stream given at build time (a hipStream_t passed as
+ *    void*; NULL makes the library create its own stream).  snn_step/snn_run are
+ *    asynchronous; every call that returns host data synchronises that stream first.
+ *  - Neuron ids are global: population k holds ids [off_k, off_k + size_k) with
+ *    populations laid out in the order given.
+ *  - Units: ms, mV, Hz.  Synaptic input is accumulated as int32 fixed point in units
+ *    of 2^-16 mV ("Q16"), so the order in which spikes are delivered cannot change a
+ *    result.
+ *  - Not thread-safe per network: calls on one network must not overlap.
+ */
+#ifndef SNN_H
+#define SNN_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t snn_status;
+#define SNN_OK 0
+#define SNN_E_INVALID (-1)  /* bad argument or parameter combination */
+#define SNN_E_OOM (-2)      /* device or host allocation failed */
+#define SNN_E_HIP (-3)      /* a HIP runtime call or kernel launch failed */
+#define SNN_E_OVERFLOW (-4) /* caller buffer too small; the required size is returned */
+#define SNN_E_STATE (-5)    /* call not valid in the network's current state */
+
+#define SNN_PROJ_ER 0u        /* each ordered pair (i, j), j != i, independently w.p. p */
+#define SNN_PROJ_FIXED_OUT 1u /* every source has exactly k distinct targets (Fig. 2) */
+
+#define SNN_DELIVERY_AUTO 0u   /* choose by the autotuner */
+#define SNN_DELIVERY_ATOMIC 1u /* wavefront(s) per spike, int32 atomics in global memory */
+#define SNN_DELIVERY_TILED 2u  /* per (target tile, step) workgroup, int32 atomics in LDS */
+
+typedef struct {
+    uint32_t size;       /* neurons in the population (>= 1) */
+    uint32_t excitatory; /* informational */
+} snn_population;
+
+typedef struct {
+    uint32_t from;    /* source population */
+    uint32_t to;      /* first target population */
+    uint32_t kind;    /* SNN_PROJ_ER or SNN_PROJ_FIXED_OUT */
+    uint32_t k;       /* out-degree (SNN_PROJ_FIXED_OUT) */
+    double p;         /* connection probability (SNN_PROJ_ER) */
+    double w_mV;      /* initial synaptic weight, |w| < 2^15 mV */
+    uint32_t plastic; /* STDP on this projection (at most one per source population) */
+    uint32_t to_span; /* targets are populations [to, to + to_span); 0 means 1 */
+} snn_projection;
+
+typedef struct {
+    double dt_ms;          /* time step (> 0) */
+    uint32_t delay_steps;  /* synaptic delay d >= 1 in steps (Sec. III-A.1) */
+    uint32_t n_ext;        /* virtual Poisson inputs per neuron (0: no drive) */
+    double tau_m_ms;       /* membrane time constant */
+    double v_rest_mV;      /* resting potential */
+    double v_bg_mV;        /* constant background drive added to the rest potential */
+    double v_th_mV;        /* threshold (spike when V >= V_th) */
+    double v_reset_mV;     /* reset potential */
+    double t_ref_ms;       /* absolute refractory period */
+    double v0_lo_mV;       /* initial V uniform in [v0_lo, v0_hi) */
+    double v0_hi_mV;
+    double rate_ext_hz;    /* rate of each virtual input */
+    double w_ext_mV;       /* weight of each virtual input */
+    double tau_plus_ms;    /* STDP potentiation trace time constant */
+    double tau_minus_ms;   /* STDP depression trace time constant */
+    double a_plus;         /* potentiation step per unit trace (mV) */
+    double a_minus;        /* depression step per unit trace (mV) */
+    double w_max_mV;       /* plastic weights are clipped to [0, w_max] */
+    uint64_t seed;         /* key of every counter-based random stream */
+    uint32_t raster_steps; /* spike-raster ring capacity in steps (0: 1024) */
+    uint32_t window;       /* max steps per update launch (0: auto, <= delay) */
+    uint32_t delivery;     /* SNN_DELIVERY_* */
+    uint32_t tiles;        /* target tiles of the tiled delivery (0: auto) */
+} snn_params;
+
+/* Optional device-memory provider (e.g. a framework's caching allocator).  alloc
+ * returns NULL on failure; memory must be usable on the build stream. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, size_t bytes, void *stream, void *ctx);
+    void *ctx;
+} snn_allocator;
+
+typedef struct snn_network snn_network;
+
+typedef struct {
+    uint32_t n;             /* neurons */
+    uint32_t delay;         /* d */
+    uint32_t queue_slots;   /* spike queues held by the FIFO ring */
+    uint32_t input_buffers; /* Q16 input accumulators, one per pending arrival step */
+    uint32_t window;        /* steps advanced per update launch */
+    uint32_t delivery;      /* SNN_DELIVERY_ATOMIC or SNN_DELIVERY_TILED */
+    uint32_t tiles;         /* target tiles (tiled delivery) */
+    uint32_t plastic;       /* 1 if any projection is plastic (FP32 weights) */
+    uint32_t raster_steps;  /* raster ring capacity */
+    uint32_t raster_words;  /* uint64 words per raster row = ceil(n / 64) */
+    uint32_t table_len;     /* entries of the drive's inverse-CDF table */
+    uint32_t pad_;
+    uint64_t nnz;           /* synapses */
+    uint64_t t;             /* steps simulated */
+    uint64_t events;        /* synaptic events delivered (sum of out-degrees of delivered spikes) */
+    uint64_t touches;       /* plastic synapse updates */
+    uint64_t device_bytes;  /* device memory held */
+} snn_info;
+
+/* Host views for reading or writing the dynamic state; NULL members are skipped.
+ * Sizes: v, ref, x_pre, x_post: n; input: input_buffers * n (buffer b holds the
+ * Q16 input of the steps u with u mod input_buffers == b); queue: queue_slots * n;
+ * queue_len: queue_slots; w_f32: nnz (plastic networks only). */
+typedef struct {
+    float *v;
+    int32_t *ref;
+    int32_t *input;
+    float *x_pre;
+    float *x_post;
+    int32_t *queue;
+    uint32_t *queue_len;
+    float *w_f32;
+} snn_state;
+
+/* Accumulated device time of each kernel kind while profiling is on (hipEvents
+ * around every launch on the network's stream). */
+typedef struct {
+    double update_ms, deliver_ms, stdp_ms;
+    uint64_t update_launches, deliver_launches, stdp_launches;
+    uint64_t deliver_events;  /* events delivered by the timed delivery launches */
+    uint64_t deliver_spikes;  /* spikes dequeued by the timed delivery launches */
+} snn_profile;
+
+/* Build a network: validate, allocate, generate the synapses on the device from the
+ * seed, initialise neurons (Init stage of Sec. III-A.1).  pops/proj are read only.
+ * Errors: SNN_E_INVALID (parameters), SNN_E_OOM, SNN_E_HIP.  On success *out owns
+ * all device memory; release it with snn_destroy. */
+snn_status snn_build_network(const snn_params *prm, const snn_population *pops, uint32_t n_pops,
+                             const snn_projection *proj, uint32_t n_proj,
+                             const snn_allocator *alloc, void *stream, snn_network **out);
+
+/* Advance one step t -> t+1 (Fig. 1: update neurons, FIFO, [update synapses],
+ * receive spikes).  Asynchronous. */
+snn_status snn_step(snn_network *net);
+
+/* Advance n_steps steps; launches are grouped into windows of up to `window` steps
+ * and replayed from a captured HIP graph where possible.  Asynchronous. */
+snn_status snn_run(snn_network *net, uint32_t n_steps);
+
+/* Spikes of steps [t_begin, t_end) as (step, id) pairs sorted by step then id.
+ * Returns SNN_E_INVALID if the range is not held by the raster ring, and
+ * SNN_E_OVERFLOW with *n_spikes = required count if capacity is too small. */
+snn_status snn_get_raster(snn_network *net, uint64_t t_begin, uint64_t t_end, uint32_t *steps,
+                          uint32_t *ids, uint64_t capacity, uint64_t *n_spikes);
+
+/* Raw raster rows: words[(t - t_begin) * raster_words + i / 64] bit (i % 64) is set iff
+ * neuron i spiked at step t.  words holds (t_end - t_begin) * raster_words uint64. */
+snn_status snn_get_raster_bits(snn_network *net, uint64_t t_begin, uint64_t t_end,
+                               uint64_t *words);
+
+snn_status snn_get_info(snn_network *net, snn_info *info);
+snn_status snn_get_state(snn_network *net, const snn_state *state);
+snn_status snn_set_state(snn_network *net, const snn_state *state);
+
+/* Synapses of one source neuron: its sorted targets and weights (Q16 for static
+ * networks, FP32 for plastic ones; either pointer may be NULL).  SNN_E_OVERFLOW with
+ * *len = row length if cap is too small. */
+snn_status snn_get_row(snn_network *net, uint32_t i, int32_t *col, int32_t *w_q16, float *w_f32,
+                       uint64_t cap, uint64_t *len);
+
+/* The whole CSR: row_ptr[n+1], col[nnz] and the weights (either may be NULL). */
+snn_status snn_get_synapses(snn_network *net, uint64_t *row_ptr, int32_t *col, int32_t *w_q16,
+                            float *w_f32);
+
+/* The drive's inverse-CDF table (table_len entries, 2^32 marks the last). */
+snn_status snn_get_drive_table(snn_network *net, uint64_t *table, uint32_t cap);
+
+snn_status snn_set_profiling(snn_network *net, int32_t on);
+snn_status snn_get_profile(snn_network *net, snn_profile *prof);
+snn_status snn_reset_profile(snn_network *net);
+snn_status snn_sync(snn_network *net);
+
+/* Deliver a caller-given spike list (device array of ids) once with the network's
+ * delivery kernel into scratch accumulators, `reps` times, and return the average
+ * kernel time in ms (HIP events).  The network's own state is left unchanged.  Used
+ * to measure the delivery kernel alone at a chosen load. */
+snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_t n_ids,
+                             uint32_t reps, double *avg_ms, uint64_t *events);
+
+void snn_destroy(snn_network *net);
+const char *snn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,21 @@
+"""MI355X (gfx950) clock-driven spiking-network simulator built around work queues
+(Bautembach et al., "Faster and Simpler SNN Simulation with Work Queues").
+
+The simulation runs in hand-written HIP kernels behind the C ABI of include/snn.h
+(libsnn.so); `Network` is its Python binding.  `workloads` holds the synthetic
+network descriptions.
+"""
+__all__ = ["Network", "SnnError", "library_path"]
+
+
+def __getattr__(name):
+    if name == "Network":
+        from .network import Network
+        return Network
+    if name == "SnnError":
+        from ._lib import SnnError
+        return SnnError
+    if name == "library_path":
+        from ._lib import LIB_PATH
+        return LIB_PATH
+    raise AttributeError(name)

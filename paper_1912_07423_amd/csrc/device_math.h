@@ -1,0 +1,97 @@
+// device_math.h -- counter-based random numbers, the binary64 logarithm of the
+// spacing generator, and wavefront (64-lane) primitives for gfx950.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snn {
+
+constexpr uint32_t kStreamConn = 1u;
+constexpr uint32_t kStreamVinit = 2u;
+constexpr uint32_t kStreamPoisson = 3u;
+constexpr int kWave = 64;
+
+struct Words4 {
+  uint32_t w[4];
+};
+
+// Philox4x32-10 (Salmon et al., SC'11): per round, multiply words 0 and 2 by the two
+// Philox multipliers, recombine the high halves with words 1 and 3 and the round
+// key, keep the low halves; bump the key by the two Weyl constants.
+__device__ __forceinline__ Words4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  Words4 r;
+  r.w[0] = c0;
+  r.w[1] = c1;
+  r.w[2] = c2;
+  r.w[3] = c3;
+  return r;
+}
+
+// -ln(u), u in (0, 1], as a fixed sequence of IEEE binary64 operations: split
+// u = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh((m-1)/(m+1)) as
+// 2r * sum_{n<=11} z^n/(2n+1), z = r^2, by Horner with fused multiply-adds;
+// ln u = fma(e, ln 2, ln m).
+__device__ __forceinline__ double neg_log(double u) {
+  constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;
+  constexpr double kLn2 = 0x1.62e42fefa39efp-1;
+  int e = 0;
+  double m = frexp(u, &e);
+  if (m < kSqrtHalf) {
+    m = m + m;
+    e = e - 1;
+  }
+  const double r = (m - 1.0) / (m + 1.0);
+  const double z = r * r;
+  double acc = 1.0 / 23.0;
+#pragma unroll
+  for (int n = 10; n >= 0; --n) acc = fma(acc, z, 1.0 / (double)(2 * n + 1));
+  const double ln_m = (r + r) * acc;
+  return -fma((double)e, kLn2, ln_m);
+}
+
+// Gap of the spacing generator in 2^-24 fixed point from one 32-bit word.
+__device__ __forceinline__ uint64_t spacing_gap(uint32_t word) {
+  const double u = (double)((word >> 8) + 1u) * 0x1p-24;
+  return (uint64_t)(neg_log(u) * 16777216.0);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const T y = __shfl_up(x, d, kWave);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+  return x;
+}
+
+}  // namespace snn

@@ -1,0 +1,377 @@
+// generate.hip -- on-device network construction (the Init stage of Sec. III-A.1).
+//
+// Rows are built one wavefront per source neuron ("one warp per job", Sec. III-A.2):
+//  * ER projections: one Bernoulli(p) trial per ordered pair, as an integer compare of
+//    a Philox word against floor(p 2^32); a count pass sizes the rows, a fill pass
+//    regenerates the same words and compacts the hits in ascending target order.
+//  * fixed out-degree projections: the exponential-spacing generator of Fig. 2 with
+//    the gaps truncated to 2^-24 fixed point, so the prefix sum, normalisation,
+//    scaling, rounding and the +k step are exact integer arithmetic.
+#include "device_math.h"
+#include "snn_internal.h"
+
+namespace snn {
+namespace {
+
+constexpr int kGenBlock = 256;
+constexpr int kGenWavesPerBlock = kGenBlock / kWave;
+
+__device__ __forceinline__ uint32_t population_of(const GenArgs &g, uint32_t i) {
+  uint32_t a = 0;
+  while (i >= g.pop_off[a + 1]) ++a;
+  return a;
+}
+
+// Edge count of neuron i in an ER projection (whole wave participates).
+__device__ uint32_t er_count(const GenArgs &g, const GenProj &pj, uint32_t i) {
+  const uint32_t b_lo = pj.off >> 2, b_hi = (pj.off + pj.size - 1) >> 2;
+  uint32_t count = 0;
+  for (uint32_t b = b_lo + lane_id(); b <= b_hi; b += kWave) {
+    const Words4 r = philox(i, b, 0u, kStreamConn, g.key0, g.key1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t j = 4u * b + q;
+      count += (j >= pj.off && j < pj.off + pj.size && j != i && (uint64_t)r.w[q] < pj.thr) ? 1u : 0u;
+    }
+  }
+  return wave_sum(count);
+}
+
+__global__ __launch_bounds__(kGenBlock) void k_row_lengths(GenArgs g, uint32_t *len,
+                                                           uint32_t *plast_rel,
+                                                           uint32_t *plast_len) {
+  const uint32_t wave = blockIdx.x * kGenWavesPerBlock + threadIdx.x / kWave;
+  const uint32_t n_waves = gridDim.x * kGenWavesPerBlock;
+  for (uint32_t i = wave; i < g.n; i += n_waves) {
+    const uint32_t a = population_of(g, i);
+    uint32_t total = 0, prel = 0, plen = 0;
+    for (uint32_t q = g.pop_proj[a]; q < g.pop_proj[a + 1]; ++q) {
+      const GenProj pj = g.proj[q];
+      const uint32_t c = pj.kind == SNN_PROJ_ER ? er_count(g, pj, i) : pj.k;
+      if (pj.plastic) {
+        prel = total;
+        plen = c;
+      }
+      total += c;
+    }
+    if (lane_id() == 0) {
+      len[i] = total;
+      if (plast_rel) {
+        plast_rel[i] = prel;
+        plast_len[i] = plen;
+      }
+    }
+  }
+}
+
+// Writes the ER edges of neuron i from position pos on; returns the end position.
+__device__ uint64_t er_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint64_t pos,
+                            int32_t *col, int32_t *w_q16, float *w_f32) {
+  const uint32_t b_lo = pj.off >> 2, b_hi = (pj.off + pj.size - 1) >> 2;
+  const uint32_t n_iter = (b_hi - b_lo) / kWave + 1;
+  for (uint32_t it = 0; it < n_iter; ++it) {
+    const uint32_t b = b_lo + it * kWave + lane_id();
+    uint32_t hits = 0;
+    if (b <= b_hi) {
+      const Words4 r = philox(i, b, 0u, kStreamConn, g.key0, g.key1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t j = 4u * b + q;
+        if (j >= pj.off && j < pj.off + pj.size && j != i && (uint64_t)r.w[q] < pj.thr) hits |= 1u << q;
+      }
+    }
+    const uint32_t cnt = __popc(hits);
+    const uint32_t incl = wave_inclusive_scan(cnt);
+    uint64_t p = pos + (incl - cnt);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (hits & (1u << q)) {
+        col[p] = (int32_t)(4u * b + q);
+        if (w_q16) w_q16[p] = pj.w_q16;
+        if (w_f32) w_f32[p] = pj.w_f32;
+        ++p;
+      }
+    }
+    pos += __shfl(incl, kWave - 1, kWave);
+  }
+  return pos;
+}
+
+__device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint64_t pos,
+                           int32_t *col, int32_t *w_q16, float *w_f32) {
+  const uint32_t k_out = pj.k;
+  if (k_out == 0) return;
+  const uint32_t stream_word2 = 1u + pj.first_pop;
+  const uint32_t n_blocks = (k_out + 1 + 3) / 4;  // gaps 0..k_out
+  const uint32_t n_iter = (n_blocks + kWave - 1) / kWave;
+  // pass 1: total of the k_out + 1 gaps
+  uint64_t part = 0;
+  for (uint32_t b = lane_id(); b < n_blocks; b += kWave) {
+    const Words4 r = philox(i, b, stream_word2, kStreamConn, g.key0, g.key1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (4u * b + q <= k_out) part += spacing_gap(r.w[q]);
+  }
+  const uint64_t total = wave_sum(part);
+  const uint64_t two_total = 2u * total;
+  const uint32_t self_local = pj.self_in ? (i - pj.off) : 0xFFFFFFFFu;
+  // pass 2: running sum S_{k+1}, round-half-up of S_{k+1} * spare / total, + k
+  uint64_t carry = 0;
+  for (uint32_t it = 0; it < n_iter; ++it) {
+    const uint32_t b = it * kWave + lane_id();
+    uint64_t gap[4] = {0, 0, 0, 0};
+    if (b < n_blocks) {
+      const Words4 r = philox(i, b, stream_word2, kStreamConn, g.key0, g.key1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (4u * b + q <= k_out) gap[q] = spacing_gap(r.w[q]);
+    }
+    const uint64_t lane_total = gap[0] + gap[1] + gap[2] + gap[3];
+    const uint64_t incl = wave_inclusive_scan(lane_total);
+    uint64_t s = carry + (incl - lane_total);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t k = 4u * b + q;
+      s += gap[q];  // S_{k+1}
+      if (b < n_blocks && k < k_out) {
+        uint64_t x = k;
+        if (total != 0) x = (2u * s * pj.spare + total) / two_total + k;
+        uint32_t local = (uint32_t)x;
+        if (local >= self_local) local += 1;
+        const uint64_t p = pos + k;
+        col[p] = (int32_t)(pj.off + local);
+        if (w_q16) w_q16[p] = pj.w_q16;
+        if (w_f32) w_f32[p] = pj.w_f32;
+      }
+    }
+    carry += __shfl(incl, kWave - 1, kWave);
+  }
+}
+
+__global__ __launch_bounds__(kGenBlock) void k_fill_rows(GenArgs g, const uint64_t *row_ptr,
+                                                         int32_t *col, int32_t *w_q16,
+                                                         float *w_f32) {
+  const uint32_t wave = blockIdx.x * kGenWavesPerBlock + threadIdx.x / kWave;
+  const uint32_t n_waves = gridDim.x * kGenWavesPerBlock;
+  for (uint32_t i = wave; i < g.n; i += n_waves) {
+    const uint32_t a = population_of(g, i);
+    uint64_t pos = row_ptr[i];
+    for (uint32_t q = g.pop_proj[a]; q < g.pop_proj[a + 1]; ++q) {
+      const GenProj pj = g.proj[q];
+      if (pj.kind == SNN_PROJ_ER) {
+        pos = er_fill(g, pj, i, pos, col, w_q16, w_f32);
+      } else {
+        fixed_fill(g, pj, i, pos, col, w_q16, w_f32);
+        pos += pj.k;
+      }
+    }
+  }
+}
+
+// ---- exclusive scan of uint32 lengths into uint64 offsets (out has n + 1 entries) ----
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_blocks(const uint32_t *in, uint64_t *out,
+                                                            uint32_t n, uint64_t *block_sums) {
+  __shared__ uint64_t wave_tot[kScanBlock / kWave];
+  const uint32_t idx = blockIdx.x * kScanBlock + threadIdx.x;
+  const uint64_t x = idx < n ? in[idx] : 0u;
+  const uint64_t incl = wave_inclusive_scan(x);
+  const uint32_t w = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) wave_tot[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    const uint64_t t = lane_id() < kScanBlock / kWave ? wave_tot[lane_id()] : 0u;
+    const uint64_t ti = wave_inclusive_scan(t);
+    if (lane_id() < kScanBlock / kWave) wave_tot[lane_id()] = ti - t;
+    if (lane_id() == kScanBlock / kWave - 1) block_sums[blockIdx.x] = ti;
+  }
+  __syncthreads();
+  if (idx < n) out[idx] = wave_tot[w] + incl - x;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(uint64_t *block_sums, uint32_t n_blocks,
+                                                          uint64_t *out, uint32_t n) {
+  __shared__ uint64_t wave_tot[kScanBlock / kWave];
+  __shared__ uint64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < n_blocks; base += kScanBlock) {
+    const uint32_t idx = base + threadIdx.x;
+    const uint64_t x = idx < n_blocks ? block_sums[idx] : 0u;
+    const uint64_t incl = wave_inclusive_scan(x);
+    const uint32_t w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) wave_tot[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+      const uint64_t t = lane_id() < kScanBlock / kWave ? wave_tot[lane_id()] : 0u;
+      const uint64_t ti = wave_inclusive_scan(t);
+      if (lane_id() < kScanBlock / kWave) wave_tot[lane_id()] = ti - t;
+    }
+    __syncthreads();
+    const uint64_t excl = carry + wave_tot[w] + incl - x;
+    if (idx < n_blocks) block_sums[idx] = excl;
+    __syncthreads();
+    if (threadIdx.x == kScanBlock - 1) carry = excl + x;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_add(uint64_t *out, uint32_t n,
+                                                         const uint64_t *block_sums) {
+  const uint32_t idx = blockIdx.x * kScanBlock + threadIdx.x;
+  if (idx < n) out[idx] += block_sums[blockIdx.x];
+}
+
+// ---- transposed index of plastic edges (in-edges grouped by target) ----
+__global__ __launch_bounds__(kGenBlock) void k_count_in(const uint64_t *row_ptr, const int32_t *col,
+                                                        const uint32_t *plast_rel,
+                                                        const uint32_t *plast_len, uint32_t n,
+                                                        uint32_t *count) {
+  const uint32_t wave = blockIdx.x * kGenWavesPerBlock + threadIdx.x / kWave;
+  const uint32_t n_waves = gridDim.x * kGenWavesPerBlock;
+  for (uint32_t i = wave; i < n; i += n_waves) {
+    const uint64_t lo = row_ptr[i] + plast_rel[i];
+    for (uint32_t k = lane_id(); k < plast_len[i]; k += kWave) atomicAdd(&count[col[lo + k]], 1u);
+  }
+}
+
+__global__ __launch_bounds__(kGenBlock) void k_fill_in(const uint64_t *row_ptr, const int32_t *col,
+                                                       const uint32_t *plast_rel,
+                                                       const uint32_t *plast_len, uint32_t n,
+                                                       uint64_t *cursor, int32_t *in_src,
+                                                       uint32_t *in_edge) {
+  const uint32_t wave = blockIdx.x * kGenWavesPerBlock + threadIdx.x / kWave;
+  const uint32_t n_waves = gridDim.x * kGenWavesPerBlock;
+  for (uint32_t i = wave; i < n; i += n_waves) {
+    const uint64_t lo = row_ptr[i] + plast_rel[i];
+    for (uint32_t k = lane_id(); k < plast_len[i]; k += kWave) {
+      const uint64_t e = lo + k;
+      const uint64_t slot = atomicAdd((unsigned long long *)&cursor[col[e]], 1ull);
+      in_src[slot] = (int32_t)i;
+      in_edge[slot] = (uint32_t)e;
+    }
+  }
+}
+
+// ---- boundaries of the target tiles inside every (sorted) row ----
+__global__ __launch_bounds__(kGenBlock) void k_tile_offsets(const uint64_t *row_ptr,
+                                                            const int32_t *col, uint32_t n,
+                                                            uint32_t tiles, uint32_t tile_size,
+                                                            uint32_t *tile_off) {
+  const uint32_t wave = blockIdx.x * kGenWavesPerBlock + threadIdx.x / kWave;
+  const uint32_t n_waves = gridDim.x * kGenWavesPerBlock;
+  for (uint32_t i = wave; i < n; i += n_waves) {
+    const uint64_t lo = row_ptr[i], hi = row_ptr[i + 1];
+    for (uint32_t p = lane_id(); p <= tiles; p += kWave) {
+      uint64_t rel;
+      if (p == tiles) {
+        rel = hi - lo;
+      } else {
+        const int64_t bound = (int64_t)p * tile_size;
+        uint64_t a = lo, b = hi;  // first e in [lo, hi) with col[e] >= bound
+        while (a < b) {
+          const uint64_t m = (a + b) >> 1;
+          if ((int64_t)col[m] < bound) a = m + 1;
+          else b = m;
+        }
+        rel = a - lo;
+      }
+      tile_off[(uint64_t)i * (tiles + 1) + p] = (uint32_t)rel;
+    }
+  }
+}
+
+// V = lo + span * u, u = (word0 >> 8) 2^-24 of stream VINIT at block (i, 0, 0).
+__global__ __launch_bounds__(kGenBlock) void k_init_neurons(float *v, int32_t *ref, uint32_t n,
+                                                            uint32_t key0, uint32_t key1, float lo,
+                                                            float span) {
+  const uint32_t i = blockIdx.x * kGenBlock + threadIdx.x;
+  if (i >= n) return;
+  const Words4 r = philox(i, 0u, 0u, kStreamVinit, key0, key1);
+  const float u = (float)(r.w[0] >> 8) * 0x1p-24f;
+  const float prod = span * u;
+  v[i] = lo + prod;
+  ref[i] = 0;
+}
+
+__global__ __launch_bounds__(kGenBlock) void k_scatter_ids(const uint32_t *ids, uint32_t n_ids,
+                                                           int32_t *queue, uint32_t *qlen) {
+  const uint32_t k = blockIdx.x * kGenBlock + threadIdx.x;
+  if (k < n_ids) queue[k] = (int32_t)ids[k];
+  if (k == 0) qlen[0] = n_ids;
+}
+
+uint32_t row_grid(uint32_t n) {
+  const uint32_t blocks = (n + kGenWavesPerBlock - 1) / kGenWavesPerBlock;
+  return blocks < 8192u ? (blocks ? blocks : 1u) : 8192u;
+}
+
+}  // namespace
+
+hipError_t launch_row_lengths(const GenArgs &g, uint32_t *len, uint32_t *plast_rel,
+                              uint32_t *plast_len, hipStream_t s) {
+  k_row_lengths<<<row_grid(g.n), kGenBlock, 0, s>>>(g, len, plast_rel, plast_len);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_rows(const GenArgs &g, const uint64_t *row_ptr, int32_t *col,
+                            int32_t *w_q16, float *w_f32, hipStream_t s) {
+  k_fill_rows<<<row_grid(g.n), kGenBlock, 0, s>>>(g, row_ptr, col, w_q16, w_f32);
+  return hipGetLastError();
+}
+
+size_t scan_scratch_elems(uint32_t n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
+
+hipError_t launch_scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint32_t n,
+                                  uint64_t *block_sums, hipStream_t s) {
+  const uint32_t blocks = (n + kScanBlock - 1) / kScanBlock;
+  if (blocks == 0) {
+    k_scan_sums<<<1, kScanBlock, 0, s>>>(block_sums, 0, out, n);
+    return hipGetLastError();
+  }
+  k_scan_blocks<<<blocks, kScanBlock, 0, s>>>(in, out, n, block_sums);
+  k_scan_sums<<<1, kScanBlock, 0, s>>>(block_sums, blocks, out, n);
+  k_scan_add<<<blocks, kScanBlock, 0, s>>>(out, n, block_sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_in_edges(const uint64_t *row_ptr, const int32_t *col,
+                                 const uint32_t *plast_rel, const uint32_t *plast_len,
+                                 uint32_t n, uint32_t *count, hipStream_t s) {
+  k_count_in<<<row_grid(n), kGenBlock, 0, s>>>(row_ptr, col, plast_rel, plast_len, n, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_in_edges(const uint64_t *row_ptr, const int32_t *col,
+                                const uint32_t *plast_rel, const uint32_t *plast_len,
+                                uint32_t n, uint64_t *cursor, int32_t *in_src,
+                                uint32_t *in_edge, hipStream_t s) {
+  k_fill_in<<<row_grid(n), kGenBlock, 0, s>>>(row_ptr, col, plast_rel, plast_len, n, cursor,
+                                               in_src, in_edge);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_offsets(const uint64_t *row_ptr, const int32_t *col, uint32_t n,
+                               uint32_t tiles, uint32_t tile_size, uint32_t *tile_off,
+                               hipStream_t s) {
+  k_tile_offsets<<<row_grid(n), kGenBlock, 0, s>>>(row_ptr, col, n, tiles, tile_size, tile_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_neurons(float *v, int32_t *ref, uint32_t n, uint32_t key0, uint32_t key1,
+                               float lo, float span, hipStream_t s) {
+  k_init_neurons<<<(n + kGenBlock - 1) / kGenBlock, kGenBlock, 0, s>>>(v, ref, n, key0, key1, lo,
+                                                                     span);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_ids(const uint32_t *ids, uint32_t n_ids, int32_t *queue,
+                              uint32_t *qlen, hipStream_t s) {
+  const uint32_t blocks = n_ids ? (n_ids + kGenBlock - 1) / kGenBlock : 1u;
+  k_scatter_ids<<<blocks, kGenBlock, 0, s>>>(ids, n_ids, queue, qlen);
+  return hipGetLastError();
+}
+
+}  // namespace snn

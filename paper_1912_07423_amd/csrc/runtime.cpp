@@ -1,0 +1,895 @@
+// runtime.cpp -- host runtime behind the C ABI of include/snn.h: validation, derived
+// constants, device allocation, on-device network construction, the window schedule
+// of the step pipeline, HIP graph replay, profiling and state/raster readback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "snn_internal.h"
+
+namespace {
+
+thread_local std::string g_error;
+
+struct Failure {
+  snn_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(snn_status code, const std::string &msg) { throw Failure{code, msg}; }
+
+void check(hipError_t e, const char *what) {
+  if (e != hipSuccess) fail(SNN_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename F>
+snn_status guarded(F &&f) {
+  try {
+    f();
+    return SNN_OK;
+  } catch (const Failure &x) {
+    g_error = x.msg;
+    return x.code;
+  } catch (const std::bad_alloc &) {
+    g_error = "host allocation failed";
+    return SNN_E_OOM;
+  } catch (const std::exception &x) {
+    g_error = x.what();
+    return SNN_E_INVALID;
+  }
+}
+
+// ---- device memory --------------------------------------------------------------
+void *dev_alloc(snn_network *net, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  bytes = (bytes + 255) & ~(size_t)255;
+  void *p = nullptr;
+  if (net->has_alloc) {
+    p = net->alloc.alloc(bytes, (void *)net->stream, net->alloc.ctx);
+    if (!p) fail(SNN_E_OOM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
+  } else {
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(SNN_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  net->allocs.push_back({p, bytes});
+  net->device_bytes += bytes;
+  return p;
+}
+
+template <typename T>
+T *dev_array(snn_network *net, size_t count) {
+  return static_cast<T *>(dev_alloc(net, count * sizeof(T)));
+}
+
+void release(snn_network *net) {
+  if (net->stream) (void)hipStreamSynchronize(net->stream);
+  if (net->graph) (void)hipGraphExecDestroy(net->graph);
+  for (auto &a : net->allocs) {
+    if (net->has_alloc) net->alloc.free(a.p, a.bytes, (void *)net->stream, net->alloc.ctx);
+    else (void)hipFree(a.p);
+  }
+  net->allocs.clear();
+  for (auto &r : net->prof_pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  net->prof_pending.clear();
+  if (net->own_stream && net->stream) (void)hipStreamDestroy(net->stream);
+}
+
+// ---- definitions of the derived constants -----------------------------------------
+int32_t q16(double w_mV, const char *what) {
+  const double s = std::nearbyint(w_mV * 65536.0);
+  if (!(s > -2147483648.0 && s < 2147483647.0)) fail(SNN_E_INVALID, std::string(what) + " out of Q16 range");
+  return (int32_t)s;
+}
+
+// Inverse-CDF thresholds of Binomial(n, p): tbl[j] = floor(CDF(j) 2^32) until the
+// first index past the mean whose probability is below 2^-40 (or n), which gets 2^32.
+// pmf(0) = q^n by n multiplications; pmf(j) = pmf(j-1) (n-j+1) / j (p/q).
+uint32_t binomial_thresholds(uint32_t n, double p, uint64_t *tbl, uint32_t cap) {
+  const uint64_t kOne = 1ull << 32;
+  if (n == 0 || p <= 0.0) {
+    tbl[0] = kOne;
+    return 1;
+  }
+  if (p >= 1.0) {
+    if (n + 1 > cap) return 0;
+    std::fill(tbl, tbl + n, 0ull);
+    tbl[n] = kOne;
+    return n + 1;
+  }
+  const double q = 1.0 - p, ratio = p / q, mean = (double)n * p;
+  double pmf = 1.0;
+  for (uint32_t j = 0; j < n; ++j) pmf *= q;
+  if (!(pmf > 0.0)) return 0;
+  double cdf = pmf;
+  for (uint32_t j = 0;; ++j) {
+    if (j + 1 > cap) return 0;
+    if (j == n || ((double)j > mean && pmf < 0x1p-40)) {
+      tbl[j] = kOne;
+      return j + 1;
+    }
+    const double scaled = cdf * 4294967296.0;
+    tbl[j] = scaled >= 4294967296.0 ? kOne : (uint64_t)scaled;
+    pmf *= (double)(n - j);  // (n - (j+1) + 1)
+    pmf /= (double)(j + 1);
+    pmf *= ratio;
+    cdf += pmf;
+  }
+}
+
+void validate_and_derive(snn_network *net) {
+  const snn_params &p = net->prm;
+  if (!(p.dt_ms > 0.0)) fail(SNN_E_INVALID, "dt_ms must be > 0");
+  if (p.delay_steps < 1) fail(SNN_E_INVALID, "delay_steps must be >= 1");
+  if (!(p.tau_m_ms > 0.0)) fail(SNN_E_INVALID, "tau_m_ms must be > 0");
+  if (!(p.t_ref_ms >= 0.0)) fail(SNN_E_INVALID, "t_ref_ms must be >= 0");
+  if (net->pops.empty()) fail(SNN_E_INVALID, "no populations");
+  uint64_t n = 0;
+  net->pop_off.assign(1, 0u);
+  for (const auto &pop : net->pops) {
+    if (pop.size == 0) fail(SNN_E_INVALID, "empty population");
+    n += pop.size;
+    if (n >= (1ull << 31)) fail(SNN_E_INVALID, "too many neurons (>= 2^31)");
+    net->pop_off.push_back((uint32_t)n);
+  }
+  net->n = (uint32_t)n;
+  const uint32_t n_pops = (uint32_t)net->pops.size();
+  bool plastic = false;
+  for (size_t q = 0; q < net->proj.size(); ++q) {
+    const snn_projection &pj = net->proj[q];
+    const uint32_t span = pj.to_span ? pj.to_span : 1u;
+    if (pj.from >= n_pops || pj.to >= n_pops || span > n_pops - pj.to)
+      fail(SNN_E_INVALID, "projection " + std::to_string(q) + ": bad population index");
+    for (size_t r = 0; r < q; ++r) {
+      const snn_projection &o = net->proj[r];
+      const uint32_t os = o.to_span ? o.to_span : 1u;
+      if (o.from == pj.from && o.to < pj.to + span && pj.to < o.to + os)
+        fail(SNN_E_INVALID, "projections " + std::to_string(r) + " and " + std::to_string(q) +
+                                " overlap (same source, overlapping targets)");
+    }
+    (void)q16(pj.w_mV, "weight");
+    const uint64_t tsize = (uint64_t)net->pop_off[pj.to + span] - net->pop_off[pj.to];
+    const bool self_in = pj.from >= pj.to && pj.from < pj.to + span;
+    const uint64_t cand = tsize - (self_in ? 1u : 0u);
+    if (pj.kind == SNN_PROJ_ER) {
+      if (!(pj.p >= 0.0 && pj.p <= 1.0)) fail(SNN_E_INVALID, "ER probability outside [0, 1]");
+    } else if (pj.kind == SNN_PROJ_FIXED_OUT) {
+      if (pj.k > cand) fail(SNN_E_INVALID, "out-degree exceeds the number of candidate targets");
+      const uint64_t spare = cand - pj.k;
+      if (((uint64_t)pj.k + 1) * (2 * spare + 1) > (1ull << 35))
+        fail(SNN_E_INVALID, "out-degree x target range too large for exact 64-bit spacing");
+    } else {
+      fail(SNN_E_INVALID, "unknown projection kind");
+    }
+    if (pj.plastic) {
+      plastic = true;
+      for (size_t r = 0; r < net->proj.size(); ++r)
+        if (r != q && net->proj[r].plastic && net->proj[r].from == pj.from)
+          fail(SNN_E_INVALID, "at most one plastic projection per source population");
+    }
+  }
+  net->plastic = plastic;
+  net->delay = p.delay_steps;
+  net->alpha = (float)std::exp(-p.dt_ms / p.tau_m_ms);
+  net->v_inf = (float)(p.v_rest_mV + p.v_bg_mV);
+  net->v_th = (float)p.v_th_mV;
+  net->v_reset = (float)p.v_reset_mV;
+  const double rs = std::nearbyint(p.t_ref_ms / p.dt_ms);
+  if (rs > 1e9) fail(SNN_E_INVALID, "refractory period too long");
+  net->ref_steps = (int32_t)rs;
+  net->w_ext_q16 = q16(p.w_ext_mV, "w_ext");
+  if (plastic) {
+    if (!(p.tau_plus_ms > 0.0 && p.tau_minus_ms > 0.0)) fail(SNN_E_INVALID, "STDP time constants must be > 0");
+    if (!(p.w_max_mV >= 0.0)) fail(SNN_E_INVALID, "w_max must be >= 0");
+    net->beta_plus = (float)std::exp(-p.dt_ms / p.tau_plus_ms);
+    net->beta_minus = (float)std::exp(-p.dt_ms / p.tau_minus_ms);
+    net->a_plus = (float)p.a_plus;
+    net->a_minus = (float)p.a_minus;
+    net->w_max = (float)p.w_max_mV;
+  }
+  const double p_ext = (p.rate_ext_hz * p.dt_ms) / 1000.0;
+  if (p.n_ext > 0 && !(p_ext >= 0.0 && p_ext <= 1.0)) fail(SNN_E_INVALID, "drive rate x dt outside [0, 1]");
+  net->table_len = binomial_thresholds(p.n_ext, p_ext, net->table, snn::kTableCap);
+  if (net->table_len == 0) fail(SNN_E_INVALID, "drive distribution needs more than 256 table entries");
+  net->key0 = (uint32_t)p.seed;
+  net->key1 = (uint32_t)(p.seed >> 32);
+}
+
+// ---- schedule: window, FIFO sizes, delivery variant --------------------------------
+void choose_schedule(snn_network *net) {
+  const snn_params &p = net->prm;
+  if (net->plastic) {
+    // Synapses change every step and delivery must see Syn_{t+1}: deliver S_{t-d+1}
+    // at step t into a single accumulator (the paper's schedule).
+    net->window = 1;
+    net->n_inbuf = 1;
+    if (p.delivery == SNN_DELIVERY_TILED) fail(SNN_E_INVALID, "tiled delivery needs static weights");
+    net->delivery = SNN_DELIVERY_ATOMIC;
+  } else {
+    // Static weights: a spike of step e may be delivered any time between the updates
+    // of e and e + d; one accumulator per pending arrival step lets a window of up to
+    // d updates run in one launch, followed by one delivery launch for its queues.
+    net->n_inbuf = net->delay;
+    net->window = p.window ? std::min(p.window, net->delay) : net->delay;
+    net->delivery = p.delivery;
+  }
+  net->slots = std::max(net->delay + 2, 2 * net->window);
+  net->raster_cap = p.raster_steps ? p.raster_steps : 1024u;
+  net->words = (net->n + 63) / 64;
+}
+
+void choose_delivery(snn_network *net) {
+  if (net->delivery == SNN_DELIVERY_AUTO) {
+    const double deg = net->n ? (double)net->nnz / net->n : 0.0;
+    net->delivery = (net->n >= 16384 && deg >= 64.0) ? SNN_DELIVERY_TILED : SNN_DELIVERY_ATOMIC;
+  }
+  if (net->delivery == SNN_DELIVERY_TILED) {
+    constexpr uint32_t kMaxTile = 8192;  // 32 KB of LDS per workgroup
+    const uint32_t min_tiles = (net->n + kMaxTile - 1) / kMaxTile;
+    uint32_t tiles = net->prm.tiles;
+    if (!tiles) tiles = std::max(min_tiles, (512u + net->window - 1) / net->window);
+    tiles = std::min(std::max(tiles, min_tiles), std::max(1u, net->n / 64u));
+    tiles = std::max(tiles, min_tiles);
+    net->tiles = tiles;
+    net->tile_size = (net->n + tiles - 1) / tiles;
+    net->tiles = (net->n + net->tile_size - 1) / net->tile_size;
+    if (net->tile_size > kMaxTile) fail(SNN_E_INVALID, "tile too large for LDS");
+  } else if (net->delivery == SNN_DELIVERY_ATOMIC) {
+    net->tiles = 1;
+    net->tile_size = net->n;
+  } else {
+    fail(SNN_E_INVALID, "unknown delivery variant");
+  }
+}
+
+// ---- construction ----------------------------------------------------------------
+void build(snn_network *net) {
+  validate_and_derive(net);
+  choose_schedule(net);
+  hipStream_t s = net->stream;
+  const uint32_t n = net->n, n_pops = (uint32_t)net->pops.size();
+
+  // projections grouped by source population, sorted by first target population
+  std::vector<snn::GenProj> gp;
+  std::vector<uint32_t> pop_proj(n_pops + 1, 0);
+  for (uint32_t a = 0; a < n_pops; ++a) {
+    std::vector<const snn_projection *> mine;
+    for (const auto &pj : net->proj)
+      if (pj.from == a) mine.push_back(&pj);
+    std::sort(mine.begin(), mine.end(), [](auto *x, auto *y) { return x->to < y->to; });
+    pop_proj[a] = (uint32_t)gp.size();
+    for (const snn_projection *pj : mine) {
+      const uint32_t span = pj->to_span ? pj->to_span : 1u;
+      snn::GenProj g{};
+      g.kind = pj->kind;
+      g.k = pj->k;
+      g.first_pop = pj->to;
+      g.off = net->pop_off[pj->to];
+      g.size = net->pop_off[pj->to + span] - g.off;
+      g.self_in = (a >= pj->to && a < pj->to + span) ? 1u : 0u;
+      g.plastic = pj->plastic ? 1u : 0u;
+      g.w_q16 = q16(pj->w_mV, "weight");
+      g.w_f32 = (float)pj->w_mV;
+      g.thr = pj->p >= 1.0 ? (1ull << 32) : (uint64_t)(pj->p * 4294967296.0);
+      g.spare = pj->kind == SNN_PROJ_FIXED_OUT ? (uint64_t)(g.size - g.self_in - pj->k) : 0;
+      gp.push_back(g);
+    }
+  }
+  pop_proj[n_pops] = (uint32_t)gp.size();
+
+  snn::GenProj *d_proj = dev_array<snn::GenProj>(net, std::max<size_t>(gp.size(), 1));
+  uint32_t *d_pop_off = dev_array<uint32_t>(net, n_pops + 1);
+  uint32_t *d_pop_proj = dev_array<uint32_t>(net, n_pops + 1);
+  if (!gp.empty())
+    check(hipMemcpyAsync(d_proj, gp.data(), gp.size() * sizeof(snn::GenProj), hipMemcpyHostToDevice, s), "copy projections");
+  check(hipMemcpyAsync(d_pop_off, net->pop_off.data(), (n_pops + 1) * 4, hipMemcpyHostToDevice, s), "copy offsets");
+  check(hipMemcpyAsync(d_pop_proj, pop_proj.data(), (n_pops + 1) * 4, hipMemcpyHostToDevice, s), "copy ranges");
+  snn::GenArgs g{d_proj, d_pop_off, d_pop_proj, n_pops, n, net->key0, net->key1};
+
+  // row lengths -> row pointers -> rows
+  uint32_t *len = dev_array<uint32_t>(net, n);
+  if (net->plastic) {
+    net->plast_rel = dev_array<uint32_t>(net, n);
+    net->plast_len = dev_array<uint32_t>(net, n);
+  }
+  check(snn::launch_row_lengths(g, len, net->plast_rel, net->plast_len, s), "row lengths");
+  net->row_ptr = dev_array<uint64_t>(net, (size_t)n + 1);
+  uint64_t *scan_tmp = dev_array<uint64_t>(net, snn::scan_scratch_elems(n));
+  check(snn::launch_scan_u32_to_u64(len, net->row_ptr, n, scan_tmp, s), "row scan");
+  check(hipMemcpyAsync(&net->nnz, net->row_ptr + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s), "read nnz");
+  check(hipStreamSynchronize(s), "sync after row scan");
+  if (net->plastic && net->nnz >= (1ull << 32)) fail(SNN_E_INVALID, "plastic networks are limited to 2^32 synapses");
+  net->nnz_alloc = ((net->nnz + 3) & ~3ull) + 4;  // 16-byte groups of the atomic delivery
+  net->col = dev_array<int32_t>(net, net->nnz_alloc);
+  check(hipMemsetAsync(net->col, 0, net->nnz_alloc * 4, s), "clear col");
+  if (net->plastic) {
+    net->w_f32 = dev_array<float>(net, net->nnz_alloc);
+    check(hipMemsetAsync(net->w_f32, 0, net->nnz_alloc * 4, s), "clear w");
+  } else {
+    net->w_q16 = dev_array<int32_t>(net, net->nnz_alloc);
+    check(hipMemsetAsync(net->w_q16, 0, net->nnz_alloc * 4, s), "clear w");
+  }
+  check(snn::launch_fill_rows(g, net->row_ptr, net->col, net->w_q16, net->w_f32, s), "fill rows");
+
+  if (net->plastic) {
+    // plastic in-edges grouped by target: counting sort by target
+    uint32_t *cnt = dev_array<uint32_t>(net, n);
+    check(hipMemsetAsync(cnt, 0, (size_t)n * 4, s), "clear in-degree");
+    check(snn::launch_count_in_edges(net->row_ptr, net->col, net->plast_rel, net->plast_len, n, cnt, s), "count in-edges");
+    net->in_ptr = dev_array<uint64_t>(net, (size_t)n + 1);
+    check(snn::launch_scan_u32_to_u64(cnt, net->in_ptr, n, scan_tmp, s), "in-edge scan");
+    uint64_t n_in = 0;
+    check(hipMemcpyAsync(&n_in, net->in_ptr + n, 8, hipMemcpyDeviceToHost, s), "read plastic count");
+    check(hipStreamSynchronize(s), "sync");
+    net->in_src = dev_array<int32_t>(net, std::max<uint64_t>(n_in, 1));
+    net->in_edge = dev_array<uint32_t>(net, std::max<uint64_t>(n_in, 1));
+    uint64_t *cursor = dev_array<uint64_t>(net, n);
+    check(hipMemcpyAsync(cursor, net->in_ptr, (size_t)n * 8, hipMemcpyDeviceToDevice, s), "cursor");
+    check(snn::launch_fill_in_edges(net->row_ptr, net->col, net->plast_rel, net->plast_len, n, cursor,
+                                    net->in_src, net->in_edge, s), "fill in-edges");
+  }
+
+  choose_delivery(net);
+  if (net->delivery == SNN_DELIVERY_TILED) {
+    net->tile_off = dev_array<uint32_t>(net, (size_t)n * (net->tiles + 1));
+    check(snn::launch_tile_offsets(net->row_ptr, net->col, n, net->tiles, net->tile_size, net->tile_off, s),
+          "tile offsets");
+  }
+
+  // neuron state, FIFO, raster, control block
+  net->v = dev_array<float>(net, n);
+  net->ref = dev_array<int32_t>(net, n);
+  net->input = dev_array<int32_t>(net, (size_t)net->n_inbuf * n);
+  net->x_pre = dev_array<float>(net, n);
+  net->x_post = dev_array<float>(net, n);
+  net->queue = dev_array<int32_t>(net, (size_t)net->slots * n);
+  net->qlen = dev_array<uint32_t>(net, net->slots);
+  net->raster = dev_array<uint64_t>(net, (size_t)net->raster_cap * net->words);
+  net->d_table = dev_array<uint64_t>(net, snn::kTableCap);
+  net->ctl = dev_array<snn::Ctl>(net, 1);
+  check(hipMemsetAsync(net->input, 0, (size_t)net->n_inbuf * n * 4, s), "clear input");
+  check(hipMemsetAsync(net->x_pre, 0, (size_t)n * 4, s), "clear traces");
+  check(hipMemsetAsync(net->x_post, 0, (size_t)n * 4, s), "clear traces");
+  check(hipMemsetAsync(net->qlen, 0, net->slots * 4, s), "clear queues");
+  check(hipMemsetAsync(net->raster, 0, (size_t)net->raster_cap * net->words * 8, s), "clear raster");
+  check(hipMemsetAsync(net->ctl, 0, sizeof(snn::Ctl), s), "clear control");
+  check(hipMemcpyAsync(net->d_table, net->table, sizeof(net->table), hipMemcpyHostToDevice, s), "copy table");
+  const float lo = (float)net->prm.v0_lo_mV;
+  const float span = (float)(net->prm.v0_hi_mV - net->prm.v0_lo_mV);
+  check(snn::launch_init_neurons(net->v, net->ref, n, net->key0, net->key1, lo, span, s), "init neurons");
+  check(hipStreamSynchronize(s), "sync after build");
+}
+
+// ---- the step pipeline --------------------------------------------------------------
+snn::UpdateArgs update_args(snn_network *net) {
+  snn::UpdateArgs a{};
+  a.v = net->v;
+  a.ref = net->ref;
+  a.input = net->input;
+  a.x_pre = net->x_pre;
+  a.x_post = net->x_post;
+  a.queue = net->queue;
+  a.qlen = net->qlen;
+  a.raster = net->raster;
+  a.table = net->d_table;
+  a.ctl = net->ctl;
+  a.n = net->n;
+  a.slots = net->slots;
+  a.n_inbuf = net->n_inbuf;
+  a.raster_cap = net->raster_cap;
+  a.words = net->words;
+  a.table_len = net->table_len;
+  a.key0 = net->key0;
+  a.key1 = net->key1;
+  a.alpha = net->alpha;
+  a.v_inf = net->v_inf;
+  a.v_th = net->v_th;
+  a.v_reset = net->v_reset;
+  a.beta_plus = net->beta_plus;
+  a.beta_minus = net->beta_minus;
+  a.ref_steps = net->ref_steps;
+  a.w_ext_q16 = net->w_ext_q16;
+  // the tiled delivery overwrites every accumulator it owns; the atomic one adds
+  a.zero_input = net->delivery == SNN_DELIVERY_ATOMIC ? 1u : 0u;
+  a.plastic = net->plastic ? 1u : 0u;
+  return a;
+}
+
+snn::DeliverArgs deliver_args(snn_network *net) {
+  snn::DeliverArgs a{};
+  a.row_ptr = net->row_ptr;
+  a.col = net->col;
+  a.w_q16 = net->w_q16;
+  a.w_f32 = net->w_f32;
+  a.queue = net->queue;
+  a.qlen = net->qlen;
+  a.input = net->input;
+  a.tile_off = net->tile_off;
+  a.ctl = net->ctl;
+  a.n = net->n;
+  a.slots = net->slots;
+  a.n_inbuf = net->n_inbuf;
+  a.delay = net->delay;
+  a.window_max = net->window;
+  a.tiles = net->tiles;
+  a.tile_size = net->tile_size;
+  a.advance = 1;
+  return a;
+}
+
+snn::StdpArgs stdp_args(snn_network *net) {
+  snn::StdpArgs a{};
+  a.row_ptr = net->row_ptr;
+  a.col = net->col;
+  a.w_f32 = net->w_f32;
+  a.plast_rel = net->plast_rel;
+  a.plast_len = net->plast_len;
+  a.in_ptr = net->in_ptr;
+  a.in_src = net->in_src;
+  a.in_edge = net->in_edge;
+  a.x_pre = net->x_pre;
+  a.x_post = net->x_post;
+  a.queue = net->queue;
+  a.qlen = net->qlen;
+  a.ctl = net->ctl;
+  a.n = net->n;
+  a.slots = net->slots;
+  a.delay = net->delay;
+  a.a_plus = net->a_plus;
+  a.a_minus = net->a_minus;
+  a.w_max = net->w_max;
+  return a;
+}
+
+uint32_t atomic_grid(const snn_network *net) { return net->cu_count * 8; }
+
+hipError_t launch_delivery(snn_network *net, const snn::DeliverArgs &d, uint32_t steps) {
+  if (net->delivery == SNN_DELIVERY_TILED) return snn::launch_deliver_tiled(d, steps, 512, net->stream);
+  return snn::launch_deliver_atomic(d, steps, atomic_grid(net), net->plastic, net->stream);
+}
+
+hipEvent_t new_event() {
+  hipEvent_t e;
+  check(hipEventCreate(&e), "hipEventCreate");
+  return e;
+}
+
+template <typename F>
+void timed(snn_network *net, int kind, F &&launch) {
+  if (!net->profiling) {
+    check(launch(), "kernel launch");
+    return;
+  }
+  snn_network::ProfRecord r{kind, new_event(), new_event()};
+  check(hipEventRecord(r.a, net->stream), "hipEventRecord");
+  check(launch(), "kernel launch");
+  check(hipEventRecord(r.b, net->stream), "hipEventRecord");
+  net->prof_pending.push_back(r);
+}
+
+void resolve_profile(snn_network *net) {
+  auto &v = net->prof_pending;
+  if (v.empty()) return;
+  check(hipStreamSynchronize(net->stream), "sync");
+  for (auto &r : v) {
+    float ms = 0.f;
+    check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+    if (r.kind == 0) {
+      net->prof.update_ms += ms;
+      net->prof.update_launches++;
+    } else if (r.kind == 1) {
+      net->prof.deliver_ms += ms;
+      net->prof.deliver_launches++;
+    } else {
+      net->prof.stdp_ms += ms;
+      net->prof.stdp_launches++;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  v.clear();
+}
+
+// One window of `steps` consecutive steps: update -> [STDP] -> delivery.
+void issue_window(snn_network *net, uint32_t steps) {
+  const snn::UpdateArgs u = update_args(net);
+  timed(net, 0, [&] { return snn::launch_update(u, steps, net->stream); });
+  if (net->plastic) {
+    const snn::StdpArgs sa = stdp_args(net);
+    timed(net, 2, [&] { return snn::launch_stdp(sa, net->cu_count * 4, net->stream); });
+  }
+  const snn::DeliverArgs d = deliver_args(net);
+  timed(net, 1, [&] { return launch_delivery(net, d, steps); });
+  net->t_host += steps;
+}
+
+void ensure_graph(snn_network *net) {
+  if (net->graph) return;
+  const uint32_t windows = std::max(1u, (64u + net->window - 1) / net->window);
+  const uint32_t steps = windows * net->window;
+  hipGraph_t g = nullptr;
+  check(hipStreamBeginCapture(net->stream, hipStreamCaptureModeRelaxed), "begin capture");
+  const uint64_t saved = net->t_host;
+  try {
+    for (uint32_t k = 0; k < windows; ++k) issue_window(net, net->window);
+  } catch (...) {
+    (void)hipStreamEndCapture(net->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    net->t_host = saved;
+    throw;
+  }
+  net->t_host = saved;
+  check(hipStreamEndCapture(net->stream, &g), "end capture");
+  const hipError_t e = hipGraphInstantiate(&net->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  check(e, "graph instantiate");
+  net->graph_steps = steps;
+}
+
+void run(snn_network *net, uint64_t n_steps) {
+  while (n_steps > 0) {
+    if (!net->profiling && n_steps >= 64 && net->stream) {
+      ensure_graph(net);
+      if (n_steps >= net->graph_steps) {
+        check(hipGraphLaunch(net->graph, net->stream), "graph launch");
+        net->t_host += net->graph_steps;
+        n_steps -= net->graph_steps;
+        continue;
+      }
+    }
+    const uint32_t steps = (uint32_t)std::min<uint64_t>(n_steps, net->window);
+    issue_window(net, steps);
+    n_steps -= steps;
+  }
+}
+
+void sync(snn_network *net) { check(hipStreamSynchronize(net->stream), "stream sync"); }
+
+snn::Ctl read_ctl(snn_network *net) {
+  snn::Ctl c{};
+  check(hipMemcpyAsync(&c, net->ctl, sizeof(c), hipMemcpyDeviceToHost, net->stream), "read control");
+  sync(net);
+  return c;
+}
+
+void raster_range_check(snn_network *net, uint64_t t0, uint64_t t1) {
+  if (t1 < t0) fail(SNN_E_INVALID, "t_end < t_begin");
+  if (t1 > net->t_host) fail(SNN_E_INVALID, "raster range beyond the simulated steps");
+  if (net->t_host - t0 > net->raster_cap) fail(SNN_E_INVALID, "raster range no longer held by the ring");
+}
+
+void copy_raster_rows(snn_network *net, uint64_t t0, uint64_t t1, uint64_t *out) {
+  const size_t row = (size_t)net->words * 8;
+  for (uint64_t t = t0; t < t1;) {
+    const uint64_t r = t % net->raster_cap;
+    const uint64_t run = std::min<uint64_t>(t1 - t, net->raster_cap - r);
+    check(hipMemcpyAsync(out + (t - t0) * net->words, net->raster + r * net->words, run * row,
+                         hipMemcpyDeviceToHost, net->stream), "raster copy");
+    t += run;
+  }
+  sync(net);
+}
+
+}  // namespace
+
+extern "C" {
+
+snn_status snn_build_network(const snn_params *prm, const snn_population *pops, uint32_t n_pops,
+                             const snn_projection *proj, uint32_t n_proj, const snn_allocator *alloc,
+                             void *stream, snn_network **out) {
+  return guarded([&] {
+    if (!prm || !out || (!pops && n_pops) || (!proj && n_proj)) fail(SNN_E_INVALID, "null argument");
+    *out = nullptr;
+    snn_network *net = new snn_network();
+    try {
+      net->prm = *prm;
+      net->pops.assign(pops, pops + n_pops);
+      net->proj.assign(proj, proj + n_proj);
+      if (alloc && alloc->alloc && alloc->free) {
+        net->alloc = *alloc;
+        net->has_alloc = true;
+      }
+      check(hipGetDevice(&net->device), "hipGetDevice");
+      hipDeviceProp_t props;
+      check(hipGetDeviceProperties(&props, net->device), "hipGetDeviceProperties");
+      net->cu_count = (uint32_t)std::max(1, props.multiProcessorCount);
+      if (stream) {
+        net->stream = (hipStream_t)stream;
+      } else {
+        check(hipStreamCreateWithFlags(&net->stream, hipStreamNonBlocking), "hipStreamCreate");
+        net->own_stream = true;
+      }
+      build(net);
+    } catch (...) {
+      release(net);
+      delete net;
+      throw;
+    }
+    *out = net;
+  });
+}
+
+snn_status snn_step(snn_network *net) {
+  return guarded([&] {
+    if (!net) fail(SNN_E_INVALID, "null network");
+    issue_window(net, 1);
+  });
+}
+
+snn_status snn_run(snn_network *net, uint32_t n_steps) {
+  return guarded([&] {
+    if (!net) fail(SNN_E_INVALID, "null network");
+    run(net, n_steps);
+  });
+}
+
+snn_status snn_sync(snn_network *net) {
+  return guarded([&] {
+    if (!net) fail(SNN_E_INVALID, "null network");
+    sync(net);
+  });
+}
+
+snn_status snn_get_raster_bits(snn_network *net, uint64_t t_begin, uint64_t t_end, uint64_t *words) {
+  return guarded([&] {
+    if (!net || (!words && t_end > t_begin)) fail(SNN_E_INVALID, "null argument");
+    raster_range_check(net, t_begin, t_end);
+    copy_raster_rows(net, t_begin, t_end, words);
+  });
+}
+
+snn_status snn_get_raster(snn_network *net, uint64_t t_begin, uint64_t t_end, uint32_t *steps,
+                          uint32_t *ids, uint64_t capacity, uint64_t *n_spikes) {
+  return guarded([&] {
+    if (!net || !n_spikes) fail(SNN_E_INVALID, "null argument");
+    raster_range_check(net, t_begin, t_end);
+    std::vector<uint64_t> rows((size_t)(t_end - t_begin) * net->words);
+    copy_raster_rows(net, t_begin, t_end, rows.data());
+    uint64_t count = 0;
+    for (uint64_t w : rows) count += (uint64_t)__builtin_popcountll(w);
+    *n_spikes = count;
+    if (count > capacity) fail(SNN_E_OVERFLOW, "raster holds " + std::to_string(count) + " spikes");
+    if (count && (!steps || !ids)) fail(SNN_E_INVALID, "null output arrays");
+    uint64_t k = 0;
+    for (uint64_t t = t_begin; t < t_end; ++t)
+      for (uint32_t w = 0; w < net->words; ++w) {
+        uint64_t bits = rows[(t - t_begin) * net->words + w];
+        while (bits) {
+          const int b = __builtin_ctzll(bits);
+          bits &= bits - 1;
+          steps[k] = (uint32_t)t;
+          ids[k] = w * 64u + (uint32_t)b;
+          ++k;
+        }
+      }
+  });
+}
+
+snn_status snn_get_info(snn_network *net, snn_info *info) {
+  return guarded([&] {
+    if (!net || !info) fail(SNN_E_INVALID, "null argument");
+    const snn::Ctl c = read_ctl(net);
+    snn_info r{};
+    r.n = net->n;
+    r.delay = net->delay;
+    r.queue_slots = net->slots;
+    r.input_buffers = net->n_inbuf;
+    r.window = net->window;
+    r.delivery = net->delivery;
+    r.tiles = net->tiles;
+    r.plastic = net->plastic ? 1u : 0u;
+    r.raster_steps = net->raster_cap;
+    r.raster_words = net->words;
+    r.table_len = net->table_len;
+    r.nnz = net->nnz;
+    r.t = c.t;
+    r.events = c.events;
+    r.touches = c.touches;
+    r.device_bytes = net->device_bytes;
+    if (c.t != net->t_host) fail(SNN_E_STATE, "device step counter disagrees with the host");
+    *info = r;
+  });
+}
+
+snn_status snn_get_state(snn_network *net, const snn_state *st) {
+  return guarded([&] {
+    if (!net || !st) fail(SNN_E_INVALID, "null argument");
+    hipStream_t s = net->stream;
+    const size_t n = net->n;
+    auto d2h = [&](void *dst, const void *src, size_t bytes) {
+      if (dst) check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s), "state copy");
+    };
+    d2h(st->v, net->v, n * 4);
+    d2h(st->ref, net->ref, n * 4);
+    d2h(st->input, net->input, (size_t)net->n_inbuf * n * 4);
+    d2h(st->x_pre, net->x_pre, n * 4);
+    d2h(st->x_post, net->x_post, n * 4);
+    d2h(st->queue, net->queue, (size_t)net->slots * n * 4);
+    d2h(st->queue_len, net->qlen, (size_t)net->slots * 4);
+    if (st->w_f32) {
+      if (!net->plastic) fail(SNN_E_INVALID, "w_f32 requested from a static network");
+      d2h(st->w_f32, net->w_f32, net->nnz * 4);
+    }
+    sync(net);
+  });
+}
+
+snn_status snn_set_state(snn_network *net, const snn_state *st) {
+  return guarded([&] {
+    if (!net || !st) fail(SNN_E_INVALID, "null argument");
+    hipStream_t s = net->stream;
+    const size_t n = net->n;
+    auto h2d = [&](void *dst, const void *src, size_t bytes) {
+      if (src) check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s), "state copy");
+    };
+    h2d(net->v, st->v, n * 4);
+    h2d(net->ref, st->ref, n * 4);
+    h2d(net->input, st->input, (size_t)net->n_inbuf * n * 4);
+    h2d(net->x_pre, st->x_pre, n * 4);
+    h2d(net->x_post, st->x_post, n * 4);
+    h2d(net->queue, st->queue, (size_t)net->slots * n * 4);
+    h2d(net->qlen, st->queue_len, (size_t)net->slots * 4);
+    if (st->w_f32) {
+      if (!net->plastic) fail(SNN_E_INVALID, "w_f32 given to a static network");
+      h2d(net->w_f32, st->w_f32, net->nnz * 4);
+    }
+    sync(net);
+  });
+}
+
+snn_status snn_get_row(snn_network *net, uint32_t i, int32_t *col, int32_t *w_q16, float *w_f32,
+                       uint64_t cap, uint64_t *len) {
+  return guarded([&] {
+    if (!net || !len) fail(SNN_E_INVALID, "null argument");
+    if (i >= net->n) fail(SNN_E_INVALID, "neuron id out of range");
+    uint64_t rp[2];
+    check(hipMemcpyAsync(rp, net->row_ptr + i, 16, hipMemcpyDeviceToHost, net->stream), "row ptr");
+    sync(net);
+    *len = rp[1] - rp[0];
+    if (*len > cap) fail(SNN_E_OVERFLOW, "row longer than cap");
+    if (*len == 0) return;
+    if (col) check(hipMemcpyAsync(col, net->col + rp[0], *len * 4, hipMemcpyDeviceToHost, net->stream), "row");
+    if (w_q16) {
+      if (!net->w_q16) fail(SNN_E_INVALID, "network has FP32 weights");
+      check(hipMemcpyAsync(w_q16, net->w_q16 + rp[0], *len * 4, hipMemcpyDeviceToHost, net->stream), "row");
+    }
+    if (w_f32) {
+      if (!net->w_f32) fail(SNN_E_INVALID, "network has Q16 weights");
+      check(hipMemcpyAsync(w_f32, net->w_f32 + rp[0], *len * 4, hipMemcpyDeviceToHost, net->stream), "row");
+    }
+    sync(net);
+  });
+}
+
+snn_status snn_get_synapses(snn_network *net, uint64_t *row_ptr, int32_t *col, int32_t *w_q16,
+                            float *w_f32) {
+  return guarded([&] {
+    if (!net) fail(SNN_E_INVALID, "null network");
+    hipStream_t s = net->stream;
+    if (row_ptr) check(hipMemcpyAsync(row_ptr, net->row_ptr, ((size_t)net->n + 1) * 8, hipMemcpyDeviceToHost, s), "copy");
+    if (col) check(hipMemcpyAsync(col, net->col, net->nnz * 4, hipMemcpyDeviceToHost, s), "copy");
+    if (w_q16) {
+      if (!net->w_q16) fail(SNN_E_INVALID, "network has FP32 weights");
+      check(hipMemcpyAsync(w_q16, net->w_q16, net->nnz * 4, hipMemcpyDeviceToHost, s), "copy");
+    }
+    if (w_f32) {
+      if (!net->w_f32) fail(SNN_E_INVALID, "network has Q16 weights");
+      check(hipMemcpyAsync(w_f32, net->w_f32, net->nnz * 4, hipMemcpyDeviceToHost, s), "copy");
+    }
+    sync(net);
+  });
+}
+
+snn_status snn_get_drive_table(snn_network *net, uint64_t *table, uint32_t cap) {
+  return guarded([&] {
+    if (!net || !table) fail(SNN_E_INVALID, "null argument");
+    if (cap < net->table_len) fail(SNN_E_OVERFLOW, "table longer than cap");
+    std::memcpy(table, net->table, net->table_len * 8);
+  });
+}
+
+snn_status snn_set_profiling(snn_network *net, int32_t on) {
+  return guarded([&] {
+    if (!net) fail(SNN_E_INVALID, "null network");
+    net->profiling = on != 0;
+  });
+}
+
+snn_status snn_get_profile(snn_network *net, snn_profile *prof) {
+  return guarded([&] {
+    if (!net || !prof) fail(SNN_E_INVALID, "null argument");
+    resolve_profile(net);
+    *prof = net->prof;
+  });
+}
+
+snn_status snn_reset_profile(snn_network *net) {
+  return guarded([&] {
+    if (!net) fail(SNN_E_INVALID, "null network");
+    resolve_profile(net);
+    net->prof = snn_profile{};
+  });
+}
+
+snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_t n_ids, uint32_t reps,
+                             double *avg_ms, uint64_t *events) {
+  return guarded([&] {
+    if (!net || (!ids_host && n_ids) || !avg_ms) fail(SNN_E_INVALID, "null argument");
+    if (n_ids > net->n) fail(SNN_E_INVALID, "more ids than neurons");
+    for (uint32_t k = 0; k < n_ids; ++k)
+      if (ids_host[k] >= net->n) fail(SNN_E_INVALID, "id out of range");
+    if (reps == 0) reps = 1;
+    hipStream_t s = net->stream;
+    // scratch FIFO, accumulators and control block; the network's state is untouched
+    std::vector<snn_network::Alloc> mark(net->allocs);
+    const uint64_t bytes_before = net->device_bytes;
+    uint32_t *ids = dev_array<uint32_t>(net, std::max<uint32_t>(n_ids, 1));
+    int32_t *queue = dev_array<int32_t>(net, (size_t)net->slots * net->n);
+    uint32_t *qlen = dev_array<uint32_t>(net, net->slots);
+    int32_t *input = dev_array<int32_t>(net, (size_t)net->n_inbuf * net->n);
+    snn::Ctl *ctl = dev_array<snn::Ctl>(net, 1);
+    check(hipMemsetAsync(qlen, 0, net->slots * 4, s), "clear");
+    check(hipMemsetAsync(input, 0, (size_t)net->n_inbuf * net->n * 4, s), "clear");
+    if (n_ids) check(hipMemcpyAsync(ids, ids_host, (size_t)n_ids * 4, hipMemcpyHostToDevice, s), "ids");
+    check(snn::launch_scatter_ids(ids, n_ids, queue, qlen, s), "scatter ids");
+    // the queue in slot 0 is the one delivered by a one-step window at step t0
+    // when t0 + n_inbuf - delay = 0 (mod slots)
+    snn::Ctl c0{};
+    c0.t = (uint64_t)net->delay - net->n_inbuf;
+    check(hipMemcpyAsync(ctl, &c0, sizeof(c0), hipMemcpyHostToDevice, s), "ctl");
+    snn::DeliverArgs d = deliver_args(net);
+    d.queue = queue;
+    d.qlen = qlen;
+    d.input = input;
+    d.ctl = ctl;
+    d.advance = 0;
+    check(launch_delivery(net, d, 1), "warm-up delivery");
+    hipEvent_t a = new_event(), b = new_event();
+    check(hipEventRecord(a, s), "event");
+    for (uint32_t r = 0; r < reps; ++r) check(launch_delivery(net, d, 1), "delivery");
+    check(hipEventRecord(b, s), "event");
+    check(hipEventSynchronize(b), "event sync");
+    float ms = 0.f;
+    check(hipEventElapsedTime(&ms, a, b), "elapsed");
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    snn::Ctl c1{};
+    check(hipMemcpy(&c1, ctl, sizeof(c1), hipMemcpyDeviceToHost), "ctl");
+    *avg_ms = ms / reps;
+    if (events) *events = c1.events / (reps + 1);
+    // return the scratch memory
+    for (size_t k = mark.size(); k < net->allocs.size(); ++k) {
+      if (net->has_alloc) net->alloc.free(net->allocs[k].p, net->allocs[k].bytes, (void *)s, net->alloc.ctx);
+      else (void)hipFree(net->allocs[k].p);
+    }
+    net->allocs.resize(mark.size());
+    net->device_bytes = bytes_before;
+  });
+}
+
+void snn_destroy(snn_network *net) {
+  if (!net) return;
+  try {
+    resolve_profile(net);
+  } catch (...) {
+  }
+  release(net);
+  delete net;
+}
+
+const char *snn_last_error(void) { return g_error.c_str(); }
+
+}  // extern "C"

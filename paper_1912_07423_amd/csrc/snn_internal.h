@@ -1,0 +1,196 @@
+// snn_internal.h -- library-private types shared by the host runtime and kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/snn.h"
+
+namespace snn {
+
+constexpr uint32_t kTableCap = 256;
+
+// Device-resident control block: the step counter that every kernel of a window
+// reads (so a captured graph replays correctly), event and touch counters, and the
+// arrival counter of the last-workgroup hand-off.
+struct Ctl {
+  uint64_t t;
+  uint64_t events;
+  uint64_t touches;
+  uint32_t done;
+  uint32_t pad;
+};
+
+// One projection as the device generators see it (per source population, sorted by
+// first target population).
+struct GenProj {
+  uint32_t kind;     // SNN_PROJ_*
+  uint32_t k;        // out-degree (fixed)
+  uint32_t first_pop;  // first target population (stream id of the fixed generator)
+  uint32_t off;      // first target id
+  uint32_t size;     // number of target ids
+  uint32_t self_in;  // sources of this projection lie inside the target range
+  uint32_t plastic;
+  int32_t w_q16;
+  float w_f32;
+  uint32_t pad;
+  uint64_t thr;      // ER: edge iff word < thr
+  uint64_t spare;    // fixed: candidates - k
+};
+
+struct GenArgs {
+  const GenProj *proj;      // [n_proj] sorted by (source population, first target)
+  const uint32_t *pop_off;  // [n_pops + 1]
+  const uint32_t *pop_proj; // [n_pops + 1] projection range of each source population
+  uint32_t n_pops, n;
+  uint32_t key0, key1;
+};
+
+struct UpdateArgs {
+  float *v;
+  int32_t *ref;
+  int32_t *input;     // [n_inbuf][n]
+  float *x_pre, *x_post;
+  int32_t *queue;     // [slots][n]
+  uint32_t *qlen;     // [slots]
+  uint64_t *raster;   // [raster_cap][words]
+  const uint64_t *table;
+  Ctl *ctl;
+  uint32_t n, slots, n_inbuf, raster_cap, words, table_len;
+  uint32_t key0, key1;
+  float alpha, v_inf, v_th, v_reset, beta_plus, beta_minus;
+  int32_t ref_steps, w_ext_q16;
+  uint32_t zero_input, plastic;
+};
+
+struct DeliverArgs {
+  const uint64_t *row_ptr;
+  const int32_t *col;
+  const int32_t *w_q16;   // static networks
+  const float *w_f32;     // plastic networks
+  const int32_t *queue;
+  uint32_t *qlen;
+  int32_t *input;
+  const uint32_t *tile_off;  // [n][tiles + 1] relative tile boundaries of each row
+  Ctl *ctl;
+  uint32_t n, slots, n_inbuf, delay, window_max;
+  uint32_t tiles, tile_size;
+  uint32_t advance;       // this launch ends the window: bump the step counter
+};
+
+struct StdpArgs {
+  const uint64_t *row_ptr;
+  const int32_t *col;
+  float *w_f32;
+  const uint32_t *plast_rel, *plast_len;
+  const uint64_t *in_ptr;
+  const int32_t *in_src;
+  const uint32_t *in_edge;
+  float *x_pre, *x_post;
+  const int32_t *queue;
+  const uint32_t *qlen;
+  Ctl *ctl;
+  uint32_t n, slots, delay;
+  float a_plus, a_minus, w_max;
+};
+
+// kernel launchers (step.hip / generate.hip)
+hipError_t launch_update(const UpdateArgs &a, uint32_t steps, hipStream_t s);
+hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t grid,
+                                 bool plastic_w, hipStream_t s);
+hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t block,
+                                hipStream_t s);
+hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_row_lengths(const GenArgs &g, uint32_t *len, uint32_t *plast_rel,
+                              uint32_t *plast_len, hipStream_t s);
+hipError_t launch_fill_rows(const GenArgs &g, const uint64_t *row_ptr, int32_t *col,
+                            int32_t *w_q16, float *w_f32, hipStream_t s);
+hipError_t launch_scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint32_t n,
+                                  uint64_t *block_sums, hipStream_t s);
+size_t scan_scratch_elems(uint32_t n);
+hipError_t launch_count_in_edges(const uint64_t *row_ptr, const int32_t *col,
+                                 const uint32_t *plast_rel, const uint32_t *plast_len,
+                                 uint32_t n, uint32_t *count, hipStream_t s);
+hipError_t launch_fill_in_edges(const uint64_t *row_ptr, const int32_t *col,
+                                const uint32_t *plast_rel, const uint32_t *plast_len,
+                                uint32_t n, uint64_t *cursor, int32_t *in_src,
+                                uint32_t *in_edge, hipStream_t s);
+hipError_t launch_tile_offsets(const uint64_t *row_ptr, const int32_t *col, uint32_t n,
+                               uint32_t tiles, uint32_t tile_size, uint32_t *tile_off,
+                               hipStream_t s);
+hipError_t launch_init_neurons(float *v, int32_t *ref, uint32_t n, uint32_t key0, uint32_t key1,
+                               float lo, float span, hipStream_t s);
+hipError_t launch_scatter_ids(const uint32_t *ids, uint32_t n_ids, int32_t *queue,
+                              uint32_t *qlen, hipStream_t s);
+
+}  // namespace snn
+
+// The network object behind the opaque handle.
+struct snn_network {
+  // description
+  std::vector<snn_population> pops;
+  std::vector<snn_projection> proj;
+  std::vector<uint32_t> pop_off;
+  snn_params prm;
+  uint32_t key0 = 0, key1 = 0;
+
+  // sizes and schedule
+  uint32_t n = 0, delay = 1, slots = 2, n_inbuf = 1, window = 1;
+  uint32_t delivery = SNN_DELIVERY_ATOMIC, tiles = 1, tile_size = 1;
+  uint32_t raster_cap = 1024, words = 1;
+  bool plastic = false;
+  uint64_t nnz = 0, nnz_alloc = 0;
+
+  // derived constants
+  float alpha = 0, v_inf = 0, v_th = 0, v_reset = 0;
+  float beta_plus = 0, beta_minus = 0, a_plus = 0, a_minus = 0, w_max = 0;
+  int32_t ref_steps = 0, w_ext_q16 = 0;
+  uint64_t table[snn::kTableCap] = {};
+  uint32_t table_len = 0;
+
+  // device memory
+  uint64_t *row_ptr = nullptr;
+  int32_t *col = nullptr, *w_q16 = nullptr;
+  float *w_f32 = nullptr;
+  uint32_t *plast_rel = nullptr, *plast_len = nullptr;
+  uint64_t *in_ptr = nullptr;
+  int32_t *in_src = nullptr;
+  uint32_t *in_edge = nullptr;
+  uint32_t *tile_off = nullptr;
+  float *v = nullptr, *x_pre = nullptr, *x_post = nullptr;
+  int32_t *ref = nullptr, *input = nullptr, *queue = nullptr;
+  uint32_t *qlen = nullptr;
+  uint64_t *raster = nullptr;
+  uint64_t *d_table = nullptr;
+  snn::Ctl *ctl = nullptr;
+
+  // bookkeeping
+  struct Alloc {
+    void *p;
+    size_t bytes;
+  };
+  std::vector<Alloc> allocs;
+  snn_allocator alloc{};
+  bool has_alloc = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  uint32_t cu_count = 256;
+  uint64_t t_host = 0;  // steps issued (mirror of the device counter)
+  uint64_t device_bytes = 0;
+
+  // graph of a fixed chunk of windows
+  hipGraphExec_t graph = nullptr;
+  uint32_t graph_steps = 0;
+
+  // profiling: hipEvent pairs around launches, resolved at the next readout
+  struct ProfRecord {
+    int kind;  // 0 update, 1 deliver, 2 stdp
+    hipEvent_t a, b;
+  };
+  bool profiling = false;
+  snn_profile prof{};
+  std::vector<ProfRecord> prof_pending;
+};

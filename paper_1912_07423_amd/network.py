@@ -1,0 +1,224 @@
+"""Python front end of the simulator: a thin wrapper over the C ABI (include/snn.h).
+
+Every step of the simulation runs in the HIP kernels of libsnn.so; this module only
+marshals arguments.  PyTorch, when present, provides the HIP stream and the device
+memory (its caching allocator); it performs no part of the simulation.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _torch_stream_and_allocator(device):
+    try:
+        import torch
+    except ImportError:
+        return None, None, None
+    if not torch.cuda.is_available():
+        return None, None, None
+    stream = torch.cuda.current_stream(device)
+
+    def _alloc(nbytes, s, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+        except Exception:
+            return None
+
+    def _free(ptr, nbytes, s, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    keep = (L.ALLOC_FN(_alloc), L.FREE_FN(_free))
+    alloc = L.Allocator(keep[0], keep[1], None)
+    return stream, alloc, keep
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+class Network:
+    """A network built and simulated on the GPU from a workload spec (see workloads.py).
+
+    Parameters beyond the spec: raster_steps (raster ring capacity), window (max
+    steps per update launch; 0 = the delay), delivery ("auto" | "atomic" | "tiled"),
+    tiles (target tiles of the tiled delivery; 0 = auto), torch_memory (allocate
+    through torch's caching allocator and run on torch's current stream).
+    """
+
+    def __init__(self, spec, raster_steps=1024, window=0, delivery="auto", tiles=0,
+                 torch_memory=True, device=0):
+        lib = L.load()
+        self._lib = lib
+        self._h = None
+        prm = spec["params"]
+        fields = {k: prm[k] for k, _ in L.PARAM_FIELDS
+                  if k not in ("raster_steps", "window", "delivery", "tiles")}
+        p = L.Params(**fields, raster_steps=raster_steps, window=window,
+                     delivery=L.DELIVERY[delivery], tiles=tiles)
+        pops = (L.Population * len(spec["pops"]))(
+            *[L.Population(q["size"], q.get("excitatory", 1)) for q in spec["pops"]])
+        projs_in = spec.get("projs", [])
+        projs = (L.Projection * max(1, len(projs_in)))()
+        for k, q in enumerate(projs_in):
+            projs[k] = L.Projection(q["from"], q["to"], L.PROJ_KIND[q["kind"]], int(q.get("k", 0)),
+                                    float(q.get("p", 0.0)), float(q["w_mV"]),
+                                    int(q.get("plastic", 0)), int(q.get("to_span", 1)))
+        self._keep = None
+        stream_handle = None
+        alloc_ptr = None
+        if torch_memory:
+            stream, alloc, keep = _torch_stream_and_allocator(device)
+            if stream is not None:
+                self._keep = keep
+                self._alloc = alloc
+                alloc_ptr = C.byref(alloc)
+                stream_handle = stream.cuda_stream or None
+        h = C.c_void_p()
+        L.check(lib.snn_build_network(C.byref(p), pops, len(spec["pops"]), projs, len(projs_in),
+                                      alloc_ptr, stream_handle, C.byref(h)))
+        self._h = h
+        self.spec = spec
+        inf = self.info()
+        self.n = inf["n"]
+        self.words = inf["raster_words"]
+        self.plastic = bool(inf["plastic"])
+
+    # -- lifecycle --------------------------------------------------------------------
+    def close(self):
+        if self._h:
+            self._lib.snn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- simulation -------------------------------------------------------------------
+    def step(self):
+        L.check(self._lib.snn_step(self._h))
+
+    def run(self, n_steps):
+        L.check(self._lib.snn_run(self._h, int(n_steps)))
+
+    def sync(self):
+        L.check(self._lib.snn_sync(self._h))
+
+    # -- readback ---------------------------------------------------------------------
+    def info(self):
+        i = L.Info()
+        L.check(self._lib.snn_get_info(self._h, C.byref(i)))
+        d = {k: getattr(i, k) for k, _ in L.Info._fields_ if k != "pad_"}
+        d["delivery_name"] = L.DELIVERY_NAME.get(d["delivery"], "?")
+        return d
+
+    @property
+    def t(self):
+        return self.info()["t"]
+
+    @property
+    def events(self):
+        return self.info()["events"]
+
+    def raster_bits(self, t0, t1):
+        out = np.zeros((max(t1 - t0, 0), self.words), dtype=np.uint64)
+        L.check(self._lib.snn_get_raster_bits(self._h, t0, t1, _ptr(out)))
+        return out
+
+    def raster(self, t0, t1):
+        """Boolean spike matrix [t1 - t0, n]."""
+        rows = self.raster_bits(t0, t1)
+        bits = np.unpackbits(rows.view(np.uint8), axis=1, bitorder="little")
+        return bits[:, : self.n].astype(bool)
+
+    def spikes(self, t0, t1):
+        """(steps, ids) sorted by step then id."""
+        n = C.c_uint64()
+        st = self._lib.snn_get_raster(self._h, t0, t1, None, None, 0, C.byref(n))
+        if st not in (L.SNN_OK, L.SNN_E_OVERFLOW):
+            L.check(st)
+        steps = np.zeros(n.value, dtype=np.uint32)
+        ids = np.zeros(n.value, dtype=np.uint32)
+        L.check(self._lib.snn_get_raster(self._h, t0, t1, _ptr(steps), _ptr(ids), n.value,
+                                         C.byref(n)))
+        return steps, ids
+
+    def state(self, queues=False, weights=False):
+        inf = self.info()
+        n, nb, ns = inf["n"], inf["input_buffers"], inf["queue_slots"]
+        s = {"v": np.zeros(n, np.float32), "ref": np.zeros(n, np.int32),
+             "input": np.zeros((nb, n), np.int32), "x_pre": np.zeros(n, np.float32),
+             "x_post": np.zeros(n, np.float32)}
+        if queues:
+            s["queue"] = np.zeros((ns, n), np.int32)
+            s["queue_len"] = np.zeros(ns, np.uint32)
+        if weights:
+            s["w_f32"] = np.zeros(inf["nnz"], np.float32)
+        st = L.State(*[_ptr(s.get(k)) for k in ("v", "ref", "input", "x_pre", "x_post", "queue",
+                                                 "queue_len", "w_f32")])
+        L.check(self._lib.snn_get_state(self._h, C.byref(st)))
+        return s
+
+    def set_state(self, **arrays):
+        dtypes = {"v": np.float32, "ref": np.int32, "input": np.int32, "x_pre": np.float32,
+                  "x_post": np.float32, "queue": np.int32, "queue_len": np.uint32,
+                  "w_f32": np.float32}
+        conv = {k: np.ascontiguousarray(v, dtype=dtypes[k]) for k, v in arrays.items()}
+        st = L.State(*[_ptr(conv.get(k)) for k in ("v", "ref", "input", "x_pre", "x_post", "queue",
+                                                    "queue_len", "w_f32")])
+        L.check(self._lib.snn_set_state(self._h, C.byref(st)))
+
+    def row(self, i):
+        n = C.c_uint64()
+        st = self._lib.snn_get_row(self._h, i, None, None, None, 0, C.byref(n))
+        if st not in (L.SNN_OK, L.SNN_E_OVERFLOW):
+            L.check(st)
+        col = np.zeros(n.value, np.int32)
+        w = np.zeros(n.value, np.float32 if self.plastic else np.int32)
+        wq, wf = (None, w) if self.plastic else (w, None)
+        L.check(self._lib.snn_get_row(self._h, i, _ptr(col), _ptr(wq), _ptr(wf), n.value,
+                                      C.byref(n)))
+        return col, w
+
+    def synapses(self):
+        inf = self.info()
+        rp = np.zeros(inf["n"] + 1, np.uint64)
+        col = np.zeros(inf["nnz"], np.int32)
+        w = np.zeros(inf["nnz"], np.float32 if self.plastic else np.int32)
+        wq, wf = (None, w) if self.plastic else (w, None)
+        L.check(self._lib.snn_get_synapses(self._h, _ptr(rp), _ptr(col), _ptr(wq), _ptr(wf)))
+        return rp, col, w
+
+    def drive_table(self):
+        t = np.zeros(256, np.uint64)
+        L.check(self._lib.snn_get_drive_table(self._h, _ptr(t), 256))
+        return t[: self.info()["table_len"]]
+
+    # -- measurement ------------------------------------------------------------------
+    def set_profiling(self, on):
+        L.check(self._lib.snn_set_profiling(self._h, 1 if on else 0))
+
+    def profile(self):
+        p = L.Profile()
+        L.check(self._lib.snn_get_profile(self._h, C.byref(p)))
+        return {k: getattr(p, k) for k, _ in L.Profile._fields_}
+
+    def reset_profile(self):
+        L.check(self._lib.snn_reset_profile(self._h))
+
+    def time_delivery(self, ids, reps=10):
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        ms = C.c_double()
+        ev = C.c_uint64()
+        L.check(self._lib.snn_time_delivery(self._h, _ptr(ids), len(ids), reps, C.byref(ms),
+                                            C.byref(ev)))
+        return ms.value, ev.value

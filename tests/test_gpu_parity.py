@@ -1,0 +1,205 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by
+element on the same seeded inputs.  Spike rasters, integer state, Q16 accumulators and
+synapse tables must be bit-identical; binary32 state (V, traces, plastic weights) is
+compared bit for bit as well (same operations in the same order, no contraction), which
+is stricter than the 1e-6 relative bar."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_07423_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu(gpu_available):
+    return gpu_available
+
+
+def _net(spec, **kw):
+    from paper_1912_07423_amd import Network
+    return Network(spec, **kw)
+
+
+def _bits(a):
+    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+
+
+def _small_specs():
+    return {
+        "cuba_4k": W.cuba_lif_4k(steps=2000),
+        "cuba_ragged": W.cuba_lif_4k(n_exc=777, n_inh=190, p=0.05, steps=600),
+        "brunel_d15": W.brunel_fixed_out(n=3000, k=300, delay_steps=15, steps=400),
+        "brunel_d4_ragged": W.brunel_fixed_out(n=1111, k=97, delay_steps=4, steps=300),
+        "stdp_d10": W.stdp_er(n=2000, p=0.05, delay_steps=10, steps=400),
+    }
+
+
+@pytest.mark.parametrize("n_ext,rate", [(1000, 20.0), (1000, 10.0), (200, 200.0), (1, 10000.0), (0, 0.0)])
+def test_drive_table_matches_oracle(n_ext, rate):
+    spec = W.cuba_lif_4k(n_exc=64, n_inh=16)
+    spec["params"].update(n_ext=n_ext, rate_ext_hz=rate, w_ext_mV=0.1)
+    g = _net(spec)
+    o = oracle.OracleNet(spec)
+    assert np.array_equal(g.drive_table(), o.table())
+
+
+@pytest.mark.parametrize("name", list(_small_specs()))
+def test_generated_synapses_match_oracle(name):
+    spec = _small_specs()[name]
+    print(f"[gen] {name}", flush=True)
+    g = _net(spec)
+    o = oracle.OracleNet(spec)
+    rp, col, w = g.synapses()
+    assert np.array_equal(rp, o.row_ptr())
+    assert np.array_equal(col, o.col())
+    if o.const.plastic:
+        assert np.array_equal(_bits(w), _bits(o.w_f32()))
+    else:
+        assert np.array_equal(w, o.w_q16())
+
+
+@pytest.mark.parametrize("name", list(_small_specs()))
+def test_initial_state_matches_oracle(name):
+    spec = _small_specs()[name]
+    g = _net(spec)
+    o = oracle.OracleNet(spec)
+    s = g.state()
+    assert np.array_equal(_bits(s["v"]), _bits(o.v()))
+    assert not s["ref"].any() and not s["input"].any()
+
+
+def _compare_run(spec, steps, **kw):
+    g = _net(spec, raster_steps=steps, **kw)
+    o = oracle.OracleNet(spec, raster_cap=steps)
+    g.run(steps)
+    o.run(steps)
+    inf = g.info()
+    assert inf["t"] == steps
+    rg = g.raster_bits(0, steps)
+    ro = o.raster_words()[:steps]
+    if not np.array_equal(rg, ro):
+        bad = np.nonzero((rg != ro).any(axis=1))[0]
+        raise AssertionError(f"raster differs first at step {bad[0]} ({len(bad)} steps differ)")
+    s = g.state(weights=bool(inf["plastic"]))
+    assert np.array_equal(_bits(s["v"]), _bits(o.v()))
+    assert np.array_equal(s["ref"], o.ref())
+    assert np.array_equal(s["input"][steps % inf["input_buffers"]], o.input())
+    # events: out-degree sums over the delivered emission steps.  A spike of step e is
+    # delivered once the update of step e + d - B has run (B input buffers), so after
+    # T steps the GPU has delivered e < T - d + B and the oracle (B = 1) e < T - d + 1.
+    outdeg = np.diff(o.row_ptr().astype(np.int64))
+    spk = o.raster_bool(0, steps)
+    def delivered(upto):
+        return int(outdeg[np.nonzero(spk[:max(upto, 0)])[1]].sum())
+    assert o.events == delivered(steps - inf["delay"] + 1)
+    assert inf["events"] == delivered(steps - inf["delay"] + inf["input_buffers"])
+    if inf["plastic"]:
+        assert np.array_equal(_bits(s["x_pre"]), _bits(o.x_pre()))
+        assert np.array_equal(_bits(s["x_post"]), _bits(o.x_post()))
+        assert np.array_equal(_bits(s["w_f32"]), _bits(o.w_f32()))
+        assert inf["touches"] == o.touches
+    return rg, inf
+
+
+@pytest.mark.parametrize("name", list(_small_specs()))
+def test_raster_and_state_parity(name):
+    spec = _small_specs()[name]
+    print(f"[run] {name} steps={spec['steps']}", flush=True)
+    rg, inf = _compare_run(spec, spec["steps"])
+    print(f"[run] {name}: spikes={int(np.unpackbits(rg.view(np.uint8)).sum())} "
+          f"events={inf['events']} delivery={inf['delivery']} window={inf['window']}", flush=True)
+    assert rg.any()
+
+
+@pytest.mark.parametrize("delivery,window", [("atomic", 1), ("atomic", 7), ("atomic", 15),
+                                             ("tiled", 1), ("tiled", 6), ("tiled", 15)])
+def test_schedule_variants_identical(delivery, window):
+    spec = W.brunel_fixed_out(n=2500, k=250, delay_steps=15, steps=200)
+    print(f"[variant] {delivery} window={window}", flush=True)
+    _compare_run(spec, 200, delivery=delivery, window=window)
+
+
+def test_tiled_tile_counts():
+    spec = W.brunel_fixed_out(n=2500, k=250, delay_steps=15, steps=120)
+    for tiles in (1, 3, 17, 39):
+        print(f"[tiles] {tiles}", flush=True)
+        _compare_run(spec, 120, delivery="tiled", tiles=tiles)
+
+
+def test_step_by_step_equals_graph_run():
+    spec = W.brunel_fixed_out(n=2000, k=150, delay_steps=3, steps=300)
+    a = _net(spec, raster_steps=300)
+    b = _net(spec, raster_steps=300)
+    a.run(300)                       # graph replays + eager remainder
+    for _ in range(300):
+        b.step()                     # one-step windows
+    assert np.array_equal(a.raster_bits(0, 300), b.raster_bits(0, 300))
+    assert np.array_equal(_bits(a.state()["v"]), _bits(b.state()["v"]))
+    assert a.events == b.events
+
+
+def test_ping_pong_listing1_gpu():
+    spec = {"params": W.params(tau_m_ms=1e12, v_rest_mV=0.0, v_bg_mV=0.0, v_th_mV=0.5,
+                               v_reset_mV=0.0, t_ref_ms=0.0, v0_lo_mV=0.0, v0_hi_mV=0.0,
+                               delay_steps=1, seed=21),
+            "pops": [{"size": 100, "excitatory": 1}, {"size": 100, "excitatory": 1}],
+            "projs": [{"from": 0, "to": 1, "kind": "er", "p": 0.03, "w_mV": 1.0},
+                      {"from": 1, "to": 0, "kind": "er", "p": 0.03, "w_mV": 1.0}]}
+    g = _net(spec, raster_steps=30)
+    o = oracle.OracleNet(spec, raster_cap=30)
+    v0 = np.zeros(200, np.float32)
+    v0[:100] = 1.0
+    g.set_state(v=v0)
+    o.v()[:] = v0
+    g.run(30)
+    o.run(30)
+    assert np.array_equal(g.raster_bits(0, 30), o.raster_words()[:30])
+    assert g.raster(0, 30)[29].any()
+
+
+def test_fifo_single_spike_gpu():
+    D, t0 = 5, 7
+    spec = W.ei_er(40, 10, 0.2, 0.1, -0.1, delay_steps=D, tau_m_ms=1e6, v_bg_mV=0.0,
+                   v0_lo_mV=-60.0, v0_hi_mV=-60.0, seed=5)
+    g = _net(spec, raster_steps=64)
+    o = oracle.OracleNet(spec, raster_cap=64)
+    g.run(t0)
+    o.run(t0)
+    v = g.state()["v"]
+    v[3] = -40.0
+    g.set_state(v=v)
+    o.v()[3] = -40.0
+    g.run(2 * D + 3)
+    o.run(2 * D + 3)
+    assert np.argwhere(g.raster(0, t0 + 2 * D + 3)).tolist() == [[t0, 3]]
+    assert np.array_equal(_bits(g.state()["v"]), _bits(o.v()))
+    assert g.events == o.events == len(oracle.gen_row(spec, 3)[0])   # both delivered by now
+
+
+def test_time_delivery_counts_events():
+    spec = W.brunel_fixed_out(n=3000, k=200, delay_steps=15)
+    for delivery in ("atomic", "tiled"):
+        g = _net(spec, delivery=delivery)
+        ids = np.arange(0, 3000, 7, dtype=np.uint32)
+        ms, ev = g.time_delivery(ids, reps=3)
+        assert ev == 200 * len(ids) and ms > 0
+        assert g.t == 0 and g.events == 0
+
+
+def test_invalid_parameters_rejected_gpu():
+    from paper_1912_07423_amd import SnnError
+    bad = W.brunel_fixed_out(n=50, k=50, delay_steps=1, n_ext=0)
+    with pytest.raises(SnnError):
+        _net(bad)
+    bad = W.cuba_lif_4k(n_exc=10, n_inh=10)
+    bad["params"]["delay_steps"] = 0
+    with pytest.raises(SnnError):
+        _net(bad)
+    g = _net(W.cuba_lif_4k(n_exc=10, n_inh=10), raster_steps=4)
+    g.run(10)
+    with pytest.raises(SnnError):
+        g.raster_bits(0, 10)          # no longer held by the 4-step ring
+    with pytest.raises(SnnError):
+        g.raster_bits(8, 12)          # beyond the simulated steps
