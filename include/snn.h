@@ -91,6 +91,7 @@ typedef struct {
     uint32_t window;       /* max steps per update launch (0: auto, <= delay) */
     uint32_t delivery;     /* SNN_DELIVERY_* */
     uint32_t tiles;        /* target tiles of the tiled delivery (0: auto) */
+    uint32_t block;        /* workgroup size of the tiled delivery: 256, 512, 1024 (0: auto) */
 } snn_params;
 
 /* Optional device-memory provider (e.g. a framework's caching allocator).  alloc
@@ -115,18 +116,23 @@ typedef struct {
     uint32_t raster_steps;  /* raster ring capacity */
     uint32_t raster_words;  /* uint64 words per raster row = ceil(n / 64) */
     uint32_t table_len;     /* entries of the drive's inverse-CDF table */
+    uint32_t queue_groups;  /* sub-queues per spike queue */
+    uint32_t queue_stride;  /* entries per queue slot (queue_groups equal sub-queues) */
     uint32_t pad_;
     uint64_t nnz;           /* synapses */
     uint64_t t;             /* steps simulated */
     uint64_t events;        /* synaptic events delivered (sum of out-degrees of delivered spikes) */
+    uint64_t spikes;        /* spikes dequeued and delivered */
     uint64_t touches;       /* plastic synapse updates */
     uint64_t device_bytes;  /* device memory held */
 } snn_info;
 
 /* Host views for reading or writing the dynamic state; NULL members are skipped.
  * Sizes: v, ref, x_pre, x_post: n; input: input_buffers * n (buffer b holds the
- * Q16 input of the steps u with u mod input_buffers == b); queue: queue_slots * n;
- * queue_len: queue_slots; w_f32: nnz (plastic networks only). */
+ * Q16 input of the steps u with u mod input_buffers == b); queue: queue_slots *
+ * queue_stride (slot s holds queue_groups sub-queues of queue_stride / queue_groups
+ * entries); queue_len: queue_slots * queue_groups sub-queue lengths; w_f32: nnz
+ * (plastic networks only). */
 typedef struct {
     float *v;
     int32_t *ref;
@@ -143,8 +149,6 @@ typedef struct {
 typedef struct {
     double update_ms, deliver_ms, stdp_ms;
     uint64_t update_launches, deliver_launches, stdp_launches;
-    uint64_t deliver_events;  /* events delivered by the timed delivery launches */
-    uint64_t deliver_spikes;  /* spikes dequeued by the timed delivery launches */
 } snn_profile;
 
 /* Build a network: validate, allocate, generate the synapses on the device from the

@@ -163,6 +163,8 @@ int64_t orc_row_into(const orc_net *c, uint32_t i, int32_t *col, int32_t *w_q16,
                     ++len;
                 }
             }
+        } else if (!col && !w_q16 && !w_f32) {
+            len += pj->k; /* length only: every row of the projection has k edges */
         } else {
             /* fixed out-degree: Fig. 2 generator over the candidate targets of the
              * target range (self excluded), gap k drawn from word k of stream CONN,

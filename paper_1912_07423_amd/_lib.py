@@ -42,7 +42,7 @@ PARAM_FIELDS = [
     ("w_ext_mV", C.c_double), ("tau_plus_ms", C.c_double), ("tau_minus_ms", C.c_double),
     ("a_plus", C.c_double), ("a_minus", C.c_double), ("w_max_mV", C.c_double),
     ("seed", C.c_uint64), ("raster_steps", C.c_uint32), ("window", C.c_uint32),
-    ("delivery", C.c_uint32), ("tiles", C.c_uint32),
+    ("delivery", C.c_uint32), ("tiles", C.c_uint32), ("block", C.c_uint32),
 ]
 
 
@@ -62,9 +62,10 @@ class Info(C.Structure):
     _fields_ = [("n", C.c_uint32), ("delay", C.c_uint32), ("queue_slots", C.c_uint32),
                 ("input_buffers", C.c_uint32), ("window", C.c_uint32), ("delivery", C.c_uint32),
                 ("tiles", C.c_uint32), ("plastic", C.c_uint32), ("raster_steps", C.c_uint32),
-                ("raster_words", C.c_uint32), ("table_len", C.c_uint32), ("pad_", C.c_uint32),
+                ("raster_words", C.c_uint32), ("table_len", C.c_uint32),
+                ("queue_groups", C.c_uint32), ("queue_stride", C.c_uint32), ("pad_", C.c_uint32),
                 ("nnz", C.c_uint64), ("t", C.c_uint64), ("events", C.c_uint64),
-                ("touches", C.c_uint64), ("device_bytes", C.c_uint64)]
+                ("spikes", C.c_uint64), ("touches", C.c_uint64), ("device_bytes", C.c_uint64)]
 
 
 class State(C.Structure):
@@ -76,8 +77,7 @@ class State(C.Structure):
 class Profile(C.Structure):
     _fields_ = [("update_ms", C.c_double), ("deliver_ms", C.c_double), ("stdp_ms", C.c_double),
                 ("update_launches", C.c_uint64), ("deliver_launches", C.c_uint64),
-                ("stdp_launches", C.c_uint64), ("deliver_events", C.c_uint64),
-                ("deliver_spikes", C.c_uint64)]
+                ("stdp_launches", C.c_uint64)]
 
 
 # every symbol declared in include/snn.h, with its ctypes signature

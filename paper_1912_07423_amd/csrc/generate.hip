@@ -296,11 +296,13 @@ __global__ __launch_bounds__(kGenBlock) void k_init_neurons(float *v, int32_t *r
   ref[i] = 0;
 }
 
+// A caller-given spike list as the queue of slot 0: id k goes to sub-queue
+// k % kQueueGroups at position k / kQueueGroups.
 __global__ __launch_bounds__(kGenBlock) void k_scatter_ids(const uint32_t *ids, uint32_t n_ids,
-                                                           int32_t *queue, uint32_t *qlen) {
+                                                           QueueRef q) {
   const uint32_t k = blockIdx.x * kGenBlock + threadIdx.x;
-  if (k < n_ids) queue[k] = (int32_t)ids[k];
-  if (k == 0) qlen[0] = n_ids;
+  if (k < n_ids) q.ids[(k % kQueueGroups) * q.group_cap + k / kQueueGroups] = (int32_t)ids[k];
+  if (k < kQueueGroups) q.qlen[k * kQlenStride] = n_ids / kQueueGroups + (k < n_ids % kQueueGroups ? 1u : 0u);
 }
 
 uint32_t row_grid(uint32_t n) {
@@ -367,10 +369,10 @@ hipError_t launch_init_neurons(float *v, int32_t *ref, uint32_t n, uint32_t key0
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_ids(const uint32_t *ids, uint32_t n_ids, int32_t *queue,
-                              uint32_t *qlen, hipStream_t s) {
+hipError_t launch_scatter_ids(const uint32_t *ids, uint32_t n_ids, const QueueRef &q,
+                              hipStream_t s) {
   const uint32_t blocks = n_ids ? (n_ids + kGenBlock - 1) / kGenBlock : 1u;
-  k_scatter_ids<<<blocks, kGenBlock, 0, s>>>(ids, n_ids, queue, qlen);
+  k_scatter_ids<<<blocks, kGenBlock, 0, s>>>(ids, n_ids, q);
   return hipGetLastError();
 }
 

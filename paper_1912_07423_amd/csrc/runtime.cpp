@@ -80,11 +80,17 @@ void release(snn_network *net) {
     else (void)hipFree(a.p);
   }
   net->allocs.clear();
+  std::vector<hipEvent_t> pend;
   for (auto &r : net->prof_pending) {
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    pend.push_back(r.a);
+    pend.push_back(r.b);
   }
+  std::sort(pend.begin(), pend.end());
+  pend.erase(std::unique(pend.begin(), pend.end()), pend.end());
+  for (hipEvent_t e : pend) (void)hipEventDestroy(e);
   net->prof_pending.clear();
+  for (hipEvent_t e : net->event_pool) (void)hipEventDestroy(e);
+  net->event_pool.clear();
   if (net->own_stream && net->stream) (void)hipStreamDestroy(net->stream);
 }
 
@@ -224,10 +230,12 @@ void choose_schedule(snn_network *net) {
     // d updates run in one launch, followed by one delivery launch for its queues.
     net->n_inbuf = net->delay;
     net->window = p.window ? std::min(p.window, net->delay) : net->delay;
+    net->window = std::min(net->window, 64u);  // one ballot per lane of the update wave
     net->delivery = p.delivery;
   }
-  net->slots = std::max(net->delay + 2, 2 * net->window);
   net->raster_cap = p.raster_steps ? p.raster_steps : 1024u;
+  net->window = std::min(net->window, net->raster_cap);  // kernels step rings by one wrap
+  net->slots = std::max(net->delay + 2, 2 * net->window);
   net->words = (net->n + 63) / 64;
 }
 
@@ -237,6 +245,9 @@ void choose_delivery(snn_network *net) {
     net->delivery = (net->n >= 16384 && deg >= 64.0) ? SNN_DELIVERY_TILED : SNN_DELIVERY_ATOMIC;
   }
   if (net->delivery == SNN_DELIVERY_TILED) {
+    const uint32_t b = net->prm.block;
+    if (b != 0 && b != 256 && b != 512 && b != 1024) fail(SNN_E_INVALID, "block must be 256, 512 or 1024");
+    net->block = b ? b : 512;
     constexpr uint32_t kMaxTile = 8192;  // 32 KB of LDS per workgroup
     const uint32_t min_tiles = (net->n + kMaxTile - 1) / kMaxTile;
     uint32_t tiles = net->prm.tiles;
@@ -355,18 +366,48 @@ void build(snn_network *net) {
   net->input = dev_array<int32_t>(net, (size_t)net->n_inbuf * n);
   net->x_pre = dev_array<float>(net, n);
   net->x_post = dev_array<float>(net, n);
-  net->queue = dev_array<int32_t>(net, (size_t)net->slots * n);
-  net->qlen = dev_array<uint32_t>(net, net->slots);
+  // spike queues: kQueueGroups sub-queues per slot, sub-queue g collecting the spikes
+  // of update workgroups b with b % kQueueGroups == g
+  const uint32_t upd_blocks = (n + snn::kUpdateBlock - 1) / snn::kUpdateBlock;
+  net->group_cap = ((upd_blocks + snn::kQueueGroups - 1) / snn::kQueueGroups) * snn::kUpdateBlock;
+  net->queue_stride = snn::kQueueGroups * net->group_cap;
+  net->queue = dev_array<int32_t>(net, (size_t)net->slots * net->queue_stride);
+  net->qlen = dev_array<uint32_t>(net, (size_t)net->slots * snn::kQueueGroups * snn::kQlenStride);
   net->raster = dev_array<uint64_t>(net, (size_t)net->raster_cap * net->words);
-  net->d_table = dev_array<uint64_t>(net, snn::kTableCap);
+  net->d_table32 = dev_array<uint32_t>(net, snn::kTableCap);
+  net->d_guide = dev_array<uint16_t>(net, snn::kGuideBuckets);
   net->ctl = dev_array<snn::Ctl>(net, 1);
   check(hipMemsetAsync(net->input, 0, (size_t)net->n_inbuf * n * 4, s), "clear input");
   check(hipMemsetAsync(net->x_pre, 0, (size_t)n * 4, s), "clear traces");
   check(hipMemsetAsync(net->x_post, 0, (size_t)n * 4, s), "clear traces");
-  check(hipMemsetAsync(net->qlen, 0, net->slots * 4, s), "clear queues");
+  check(hipMemsetAsync(net->qlen, 0, (size_t)net->slots * snn::kQueueGroups * snn::kQlenStride * 4, s),
+        "clear queues");
   check(hipMemsetAsync(net->raster, 0, (size_t)net->raster_cap * net->words * 8, s), "clear raster");
   check(hipMemsetAsync(net->ctl, 0, sizeof(snn::Ctl), s), "clear control");
-  check(hipMemcpyAsync(net->d_table, net->table, sizeof(net->table), hipMemcpyHostToDevice, s), "copy table");
+  // the drive table as the kernels search it: thresholds below 2^32 as 32-bit words, and
+  // a guide table giving #{j : tbl[j] <= r} at both ends of each bucket of r's top bits
+  {
+    std::vector<uint32_t> t32(snn::kTableCap, 0u);
+    uint32_t below = 0;
+    while (below < net->table_len && net->table[below] < (1ull << 32)) {
+      t32[below] = (uint32_t)net->table[below];
+      ++below;
+    }
+    std::vector<uint16_t> guide(snn::kGuideBuckets);
+    const uint32_t shift = 32 - snn::kGuideBits;
+    for (uint32_t b = 0; b < snn::kGuideBuckets; ++b) {
+      const uint64_t r_lo = (uint64_t)b << shift, r_hi = r_lo + ((1ull << shift) - 1);
+      uint32_t lo = 0, hi = 0;
+      for (uint32_t j = 0; j < below; ++j) {
+        lo += t32[j] <= r_lo ? 1u : 0u;
+        hi += t32[j] <= r_hi ? 1u : 0u;
+      }
+      guide[b] = (uint16_t)(lo | (hi << 8));
+    }
+    check(hipMemcpyAsync(net->d_table32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice, s), "copy table");
+    check(hipMemcpyAsync(net->d_guide, guide.data(), guide.size() * 2, hipMemcpyHostToDevice, s), "copy guide");
+    check(hipStreamSynchronize(s), "sync tables");
+  }
   const float lo = (float)net->prm.v0_lo_mV;
   const float span = (float)(net->prm.v0_hi_mV - net->prm.v0_lo_mV);
   check(snn::launch_init_neurons(net->v, net->ref, n, net->key0, net->key1, lo, span, s), "init neurons");
@@ -374,6 +415,10 @@ void build(snn_network *net) {
 }
 
 // ---- the step pipeline --------------------------------------------------------------
+snn::QueueRef queue_ref(snn_network *net) {
+  return snn::QueueRef{net->queue, net->qlen, net->queue_stride, net->group_cap};
+}
+
 snn::UpdateArgs update_args(snn_network *net) {
   snn::UpdateArgs a{};
   a.v = net->v;
@@ -381,10 +426,10 @@ snn::UpdateArgs update_args(snn_network *net) {
   a.input = net->input;
   a.x_pre = net->x_pre;
   a.x_post = net->x_post;
-  a.queue = net->queue;
-  a.qlen = net->qlen;
+  a.q = queue_ref(net);
   a.raster = net->raster;
-  a.table = net->d_table;
+  a.table32 = net->d_table32;
+  a.guide = net->d_guide;
   a.ctl = net->ctl;
   a.n = net->n;
   a.slots = net->slots;
@@ -414,8 +459,7 @@ snn::DeliverArgs deliver_args(snn_network *net) {
   a.col = net->col;
   a.w_q16 = net->w_q16;
   a.w_f32 = net->w_f32;
-  a.queue = net->queue;
-  a.qlen = net->qlen;
+  a.q = queue_ref(net);
   a.input = net->input;
   a.tile_off = net->tile_off;
   a.ctl = net->ctl;
@@ -442,8 +486,7 @@ snn::StdpArgs stdp_args(snn_network *net) {
   a.in_edge = net->in_edge;
   a.x_pre = net->x_pre;
   a.x_post = net->x_post;
-  a.queue = net->queue;
-  a.qlen = net->qlen;
+  a.q = queue_ref(net);
   a.ctl = net->ctl;
   a.n = net->n;
   a.slots = net->slots;
@@ -457,7 +500,7 @@ snn::StdpArgs stdp_args(snn_network *net) {
 uint32_t atomic_grid(const snn_network *net) { return net->cu_count * 8; }
 
 hipError_t launch_delivery(snn_network *net, const snn::DeliverArgs &d, uint32_t steps) {
-  if (net->delivery == SNN_DELIVERY_TILED) return snn::launch_deliver_tiled(d, steps, 512, net->stream);
+  if (net->delivery == SNN_DELIVERY_TILED) return snn::launch_deliver_tiled(d, steps, net->block, net->stream);
   return snn::launch_deliver_atomic(d, steps, atomic_grid(net), net->plastic, net->stream);
 }
 
@@ -467,23 +510,39 @@ hipEvent_t new_event() {
   return e;
 }
 
+hipEvent_t pooled_event(snn_network *net) {
+  if (net->event_pool.empty()) return new_event();
+  hipEvent_t e = net->event_pool.back();
+  net->event_pool.pop_back();
+  return e;
+}
+
+// With profiling on, consecutive launches share events: the event after one launch is
+// the event before the next, so a window adds one marker per kernel to the stream.
 template <typename F>
 void timed(snn_network *net, int kind, F &&launch) {
   if (!net->profiling) {
     check(launch(), "kernel launch");
     return;
   }
-  snn_network::ProfRecord r{kind, new_event(), new_event()};
-  check(hipEventRecord(r.a, net->stream), "hipEventRecord");
+  hipEvent_t a = net->prof_last;
+  if (!a) {
+    a = pooled_event(net);
+    check(hipEventRecord(a, net->stream), "hipEventRecord");
+  }
   check(launch(), "kernel launch");
-  check(hipEventRecord(r.b, net->stream), "hipEventRecord");
-  net->prof_pending.push_back(r);
+  hipEvent_t b = pooled_event(net);
+  check(hipEventRecord(b, net->stream), "hipEventRecord");
+  net->prof_pending.push_back(snn_network::ProfRecord{kind, a, b});
+  net->prof_last = b;
 }
 
 void resolve_profile(snn_network *net) {
   auto &v = net->prof_pending;
+  net->prof_last = nullptr;
   if (v.empty()) return;
   check(hipStreamSynchronize(net->stream), "sync");
+  std::vector<hipEvent_t> done;
   for (auto &r : v) {
     float ms = 0.f;
     check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
@@ -497,9 +556,12 @@ void resolve_profile(snn_network *net) {
       net->prof.stdp_ms += ms;
       net->prof.stdp_launches++;
     }
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    done.push_back(r.a);
+    done.push_back(r.b);
   }
+  std::sort(done.begin(), done.end());
+  done.erase(std::unique(done.begin(), done.end()), done.end());
+  net->event_pool.insert(net->event_pool.end(), done.begin(), done.end());
   v.clear();
 }
 
@@ -556,13 +618,30 @@ void run(snn_network *net, uint64_t n_steps) {
   }
 }
 
-void sync(snn_network *net) { check(hipStreamSynchronize(net->stream), "stream sync"); }
+void sync(snn_network *net) {
+  net->prof_last = nullptr;
+  check(hipStreamSynchronize(net->stream), "stream sync");
+}
 
-snn::Ctl read_ctl(snn_network *net) {
-  snn::Ctl c{};
-  check(hipMemcpyAsync(&c, net->ctl, sizeof(c), hipMemcpyDeviceToHost, net->stream), "read control");
+struct CtlTotals {
+  uint64_t t, events, spikes, touches;
+};
+
+CtlTotals sum_ctl(const snn::Ctl &c) {
+  CtlTotals r{c.t, 0, 0, 0};
+  for (uint32_t p = 0; p < snn::kCounterParts; ++p) {
+    r.events += c.events[p * snn::kLineU64];
+    r.spikes += c.spikes[p * snn::kLineU64];
+    r.touches += c.touches[p * snn::kLineU64];
+  }
+  return r;
+}
+
+CtlTotals read_ctl(snn_network *net) {
+  std::vector<snn::Ctl> c(1);
+  check(hipMemcpyAsync(c.data(), net->ctl, sizeof(snn::Ctl), hipMemcpyDeviceToHost, net->stream), "read control");
   sync(net);
-  return c;
+  return sum_ctl(c[0]);
 }
 
 void raster_range_check(snn_network *net, uint64_t t0, uint64_t t1) {
@@ -681,11 +760,13 @@ snn_status snn_get_raster(snn_network *net, uint64_t t_begin, uint64_t t_end, ui
 snn_status snn_get_info(snn_network *net, snn_info *info) {
   return guarded([&] {
     if (!net || !info) fail(SNN_E_INVALID, "null argument");
-    const snn::Ctl c = read_ctl(net);
+    const CtlTotals c = read_ctl(net);
     snn_info r{};
     r.n = net->n;
     r.delay = net->delay;
     r.queue_slots = net->slots;
+    r.queue_groups = snn::kQueueGroups;
+    r.queue_stride = net->queue_stride;
     r.input_buffers = net->n_inbuf;
     r.window = net->window;
     r.delivery = net->delivery;
@@ -697,6 +778,7 @@ snn_status snn_get_info(snn_network *net, snn_info *info) {
     r.nnz = net->nnz;
     r.t = c.t;
     r.events = c.events;
+    r.spikes = c.spikes;
     r.touches = c.touches;
     r.device_bytes = net->device_bytes;
     if (c.t != net->t_host) fail(SNN_E_STATE, "device step counter disagrees with the host");
@@ -717,8 +799,11 @@ snn_status snn_get_state(snn_network *net, const snn_state *st) {
     d2h(st->input, net->input, (size_t)net->n_inbuf * n * 4);
     d2h(st->x_pre, net->x_pre, n * 4);
     d2h(st->x_post, net->x_post, n * 4);
-    d2h(st->queue, net->queue, (size_t)net->slots * n * 4);
-    d2h(st->queue_len, net->qlen, (size_t)net->slots * 4);
+    d2h(st->queue, net->queue, (size_t)net->slots * net->queue_stride * 4);
+    if (st->queue_len)
+      check(hipMemcpy2DAsync(st->queue_len, 4, net->qlen, snn::kQlenStride * 4, 4,
+                             (size_t)net->slots * snn::kQueueGroups, hipMemcpyDeviceToHost, s),
+            "queue counters");
     if (st->w_f32) {
       if (!net->plastic) fail(SNN_E_INVALID, "w_f32 requested from a static network");
       d2h(st->w_f32, net->w_f32, net->nnz * 4);
@@ -740,8 +825,11 @@ snn_status snn_set_state(snn_network *net, const snn_state *st) {
     h2d(net->input, st->input, (size_t)net->n_inbuf * n * 4);
     h2d(net->x_pre, st->x_pre, n * 4);
     h2d(net->x_post, st->x_post, n * 4);
-    h2d(net->queue, st->queue, (size_t)net->slots * n * 4);
-    h2d(net->qlen, st->queue_len, (size_t)net->slots * 4);
+    h2d(net->queue, st->queue, (size_t)net->slots * net->queue_stride * 4);
+    if (st->queue_len)
+      check(hipMemcpy2DAsync(net->qlen, snn::kQlenStride * 4, st->queue_len, 4, 4,
+                             (size_t)net->slots * snn::kQueueGroups, hipMemcpyHostToDevice, s),
+            "queue counters");
     if (st->w_f32) {
       if (!net->plastic) fail(SNN_E_INVALID, "w_f32 given to a static network");
       h2d(net->w_f32, st->w_f32, net->nnz * 4);
@@ -805,6 +893,7 @@ snn_status snn_set_profiling(snn_network *net, int32_t on) {
   return guarded([&] {
     if (!net) fail(SNN_E_INVALID, "null network");
     net->profiling = on != 0;
+    net->prof_last = nullptr;
   });
 }
 
@@ -837,26 +926,29 @@ snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_
     std::vector<snn_network::Alloc> mark(net->allocs);
     const uint64_t bytes_before = net->device_bytes;
     uint32_t *ids = dev_array<uint32_t>(net, std::max<uint32_t>(n_ids, 1));
-    int32_t *queue = dev_array<int32_t>(net, (size_t)net->slots * net->n);
-    uint32_t *qlen = dev_array<uint32_t>(net, net->slots);
+    int32_t *queue = dev_array<int32_t>(net, (size_t)net->slots * net->queue_stride);
+    uint32_t *qlen = dev_array<uint32_t>(net, (size_t)net->slots * snn::kQueueGroups * snn::kQlenStride);
     int32_t *input = dev_array<int32_t>(net, (size_t)net->n_inbuf * net->n);
     snn::Ctl *ctl = dev_array<snn::Ctl>(net, 1);
-    check(hipMemsetAsync(qlen, 0, net->slots * 4, s), "clear");
+    check(hipMemsetAsync(qlen, 0, (size_t)net->slots * snn::kQueueGroups * snn::kQlenStride * 4, s), "clear");
     check(hipMemsetAsync(input, 0, (size_t)net->n_inbuf * net->n * 4, s), "clear");
     if (n_ids) check(hipMemcpyAsync(ids, ids_host, (size_t)n_ids * 4, hipMemcpyHostToDevice, s), "ids");
-    check(snn::launch_scatter_ids(ids, n_ids, queue, qlen, s), "scatter ids");
-    // the queue in slot 0 is the one delivered by a one-step window at step t0
+    const snn::QueueRef sq{queue, qlen, net->queue_stride, net->group_cap};
+    check(snn::launch_scatter_ids(ids, n_ids, sq, s), "scatter ids");
+    // the queue in slot 0 is the one delivered by a one-step window starting at t0
     // when t0 + n_inbuf - delay = 0 (mod slots)
-    snn::Ctl c0{};
-    c0.t = (uint64_t)net->delay - net->n_inbuf;
-    check(hipMemcpyAsync(ctl, &c0, sizeof(c0), hipMemcpyHostToDevice, s), "ctl");
+    std::vector<snn::Ctl> c0(1);
+    std::memset(c0.data(), 0, sizeof(snn::Ctl));
+    c0[0].t_deliver = (uint64_t)net->delay - net->n_inbuf;
+    check(hipMemcpyAsync(ctl, c0.data(), sizeof(snn::Ctl), hipMemcpyHostToDevice, s), "ctl");
+    check(hipStreamSynchronize(s), "sync");
     snn::DeliverArgs d = deliver_args(net);
-    d.queue = queue;
-    d.qlen = qlen;
+    d.q = sq;
     d.input = input;
     d.ctl = ctl;
     d.advance = 0;
     check(launch_delivery(net, d, 1), "warm-up delivery");
+    net->prof_last = nullptr;
     hipEvent_t a = new_event(), b = new_event();
     check(hipEventRecord(a, s), "event");
     for (uint32_t r = 0; r < reps; ++r) check(launch_delivery(net, d, 1), "delivery");
@@ -866,10 +958,10 @@ snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_
     check(hipEventElapsedTime(&ms, a, b), "elapsed");
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    snn::Ctl c1{};
-    check(hipMemcpy(&c1, ctl, sizeof(c1), hipMemcpyDeviceToHost), "ctl");
+    std::vector<snn::Ctl> c1(1);
+    check(hipMemcpy(c1.data(), ctl, sizeof(snn::Ctl), hipMemcpyDeviceToHost), "ctl");
     *avg_ms = ms / reps;
-    if (events) *events = c1.events / (reps + 1);
+    if (events) *events = sum_ctl(c1[0]).events / (reps + 1);
     // return the scratch memory
     for (size_t k = mark.size(); k < net->allocs.size(); ++k) {
       if (net->has_alloc) net->alloc.free(net->allocs[k].p, net->allocs[k].bytes, (void *)s, net->alloc.ctx);

@@ -12,15 +12,38 @@ namespace snn {
 
 constexpr uint32_t kTableCap = 256;
 
-// Device-resident control block: the step counter that every kernel of a window
-// reads (so a captured graph replays correctly), event and touch counters, and the
-// arrival counter of the last-workgroup hand-off.
+// Many workgroups update the same counters at the same moment; same-line atomics
+// from a burst of workgroups serialise, so every shared counter gets its own
+// 256-byte line and the hot ones are split into independent parts.
+constexpr uint32_t kQlenStride = 64;    // uint32 per counter line
+constexpr uint32_t kLineU64 = 32;       // uint64 per 256-byte line
+constexpr uint32_t kQueueGroups = 8;    // sub-queues of a step's spike queue
+constexpr uint32_t kCounterParts = 64;  // partial sums of the event/spike/touch counters
+constexpr uint32_t kUpdateBlock = 256;  // neurons per update workgroup
+constexpr uint32_t kGuideBits = 12;     // drive guide table: buckets on the top bits of r
+constexpr uint32_t kGuideBuckets = 1u << kGuideBits;
+
+// Device-resident control block.  `t` is the first step of the next update launch;
+// the update launch copies it to `t_deliver` and the delivery launch that closes the
+// window advances `t`, so every kernel finds its step on the device and a captured
+// HIP graph replays correctly.
 struct Ctl {
   uint64_t t;
-  uint64_t events;
-  uint64_t touches;
-  uint32_t done;
-  uint32_t pad;
+  uint64_t t_deliver;
+  uint64_t pad[kLineU64 - 2];
+  uint64_t events[kCounterParts * kLineU64];   // part p at [p * kLineU64]
+  uint64_t spikes[kCounterParts * kLineU64];
+  uint64_t touches[kCounterParts * kLineU64];
+};
+
+// A step's spike queue is kQueueGroups sub-queues of group_cap entries each; update
+// workgroup b appends to sub-queue b % kQueueGroups.  Counter of (slot, group) at
+// qlen[(slot * kQueueGroups + group) * kQlenStride].
+struct QueueRef {
+  int32_t *ids;       // [slots][stride]
+  uint32_t *qlen;
+  uint32_t stride;    // kQueueGroups * group_cap
+  uint32_t group_cap;
 };
 
 // One projection as the device generators see it (per source population, sorted by
@@ -53,10 +76,10 @@ struct UpdateArgs {
   int32_t *ref;
   int32_t *input;     // [n_inbuf][n]
   float *x_pre, *x_post;
-  int32_t *queue;     // [slots][n]
-  uint32_t *qlen;     // [slots]
+  QueueRef q;
   uint64_t *raster;   // [raster_cap][words]
-  const uint64_t *table;
+  const uint32_t *table32;  // drive thresholds below 2^32
+  const uint16_t *guide;    // [kGuideBuckets]: count at the bucket's low end | high end << 8
   Ctl *ctl;
   uint32_t n, slots, n_inbuf, raster_cap, words, table_len;
   uint32_t key0, key1;
@@ -70,14 +93,13 @@ struct DeliverArgs {
   const int32_t *col;
   const int32_t *w_q16;   // static networks
   const float *w_f32;     // plastic networks
-  const int32_t *queue;
-  uint32_t *qlen;
+  QueueRef q;
   int32_t *input;
   const uint32_t *tile_off;  // [n][tiles + 1] relative tile boundaries of each row
   Ctl *ctl;
   uint32_t n, slots, n_inbuf, delay, window_max;
   uint32_t tiles, tile_size;
-  uint32_t advance;       // this launch ends the window: bump the step counter
+  uint32_t advance;       // this launch closes the window: advance the step counter
 };
 
 struct StdpArgs {
@@ -89,8 +111,7 @@ struct StdpArgs {
   const int32_t *in_src;
   const uint32_t *in_edge;
   float *x_pre, *x_post;
-  const int32_t *queue;
-  const uint32_t *qlen;
+  QueueRef q;
   Ctl *ctl;
   uint32_t n, slots, delay;
   float a_plus, a_minus, w_max;
@@ -122,8 +143,8 @@ hipError_t launch_tile_offsets(const uint64_t *row_ptr, const int32_t *col, uint
                                hipStream_t s);
 hipError_t launch_init_neurons(float *v, int32_t *ref, uint32_t n, uint32_t key0, uint32_t key1,
                                float lo, float span, hipStream_t s);
-hipError_t launch_scatter_ids(const uint32_t *ids, uint32_t n_ids, int32_t *queue,
-                              uint32_t *qlen, hipStream_t s);
+hipError_t launch_scatter_ids(const uint32_t *ids, uint32_t n_ids, const QueueRef &q,
+                              hipStream_t s);
 
 }  // namespace snn
 
@@ -138,7 +159,7 @@ struct snn_network {
 
   // sizes and schedule
   uint32_t n = 0, delay = 1, slots = 2, n_inbuf = 1, window = 1;
-  uint32_t delivery = SNN_DELIVERY_ATOMIC, tiles = 1, tile_size = 1;
+  uint32_t delivery = SNN_DELIVERY_ATOMIC, tiles = 1, tile_size = 1, block = 512;
   uint32_t raster_cap = 1024, words = 1;
   bool plastic = false;
   uint64_t nnz = 0, nnz_alloc = 0;
@@ -162,8 +183,10 @@ struct snn_network {
   float *v = nullptr, *x_pre = nullptr, *x_post = nullptr;
   int32_t *ref = nullptr, *input = nullptr, *queue = nullptr;
   uint32_t *qlen = nullptr;
+  uint32_t queue_stride = 0, group_cap = 0;  // entries per queue slot / per sub-queue
   uint64_t *raster = nullptr;
-  uint64_t *d_table = nullptr;
+  uint32_t *d_table32 = nullptr;
+  uint16_t *d_guide = nullptr;
   snn::Ctl *ctl = nullptr;
 
   // bookkeeping
@@ -193,4 +216,6 @@ struct snn_network {
   bool profiling = false;
   snn_profile prof{};
   std::vector<ProfRecord> prof_pending;
+  std::vector<hipEvent_t> event_pool;
+  hipEvent_t prof_last = nullptr;  // last event recorded, if nothing was enqueued since
 };

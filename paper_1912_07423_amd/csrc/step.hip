@@ -1,10 +1,10 @@
 // step.hip -- the per-step kernels of the work-queue pipeline (Sec. III-A.1, Fig. 1).
 //
 //  k_update          Update Neurons for a window of consecutive steps: each lane owns
-//                    one neuron, keeps V/ref/traces in registers across the window,
-//                    and appends its spikes to the step's queue with one ballot and
-//                    one queue-counter atomic per wavefront; the ballot is also the
-//                    step's raster word.
+//                    one neuron and keeps V/ref/traces in registers across the window;
+//                    the ballot of each step is both the step's raster word and the
+//                    compaction mask of the spike queue (one queue reservation per
+//                    workgroup and step).
 //  k_deliver_atomic  Receive Spikes, one wavefront per dequeued spike, aligned 16-byte
 //                    loads of targets/weights, no-return int32 atomics into the Q16
 //                    input accumulators in global memory.
@@ -15,29 +15,99 @@
 //  k_stdp_ltd/ltp    Update Synapses: depression over S_{t-d}'s plastic out-edges,
 //                    potentiation over S_t's plastic in-edges (transposed index).
 //
-// Step bookkeeping lives on the device (Ctl::t) so that a captured HIP graph replays
-// correctly: every kernel reads the step, and the last workgroup of the delivery
-// kernel that closes a window clears the next window's queue counters and advances t.
+// Step bookkeeping lives on the device (Ctl) so that a captured HIP graph replays
+// correctly; no kernel waits on another workgroup of its own launch.
 #include "device_math.h"
 #include "snn_internal.h"
 
 namespace snn {
 namespace {
 
-constexpr int kUpdateBlock = 256;
+// Ring indices: the window's first step is reduced modulo each ring size once per
+// launch; step t0 + w is then reached by one conditional subtraction, which needs
+// w < size (the window fits every ring, checked by the host).
+__device__ __forceinline__ uint32_t ring_add(uint32_t base, uint32_t w, uint32_t size) {
+  const uint32_t x = base + w;
+  return x >= size ? x - size : x;
+}
 
+// floor-modulo of a possibly negative step
+__device__ __forceinline__ uint32_t ring_of(int64_t x, uint32_t size) {
+  const int64_t r = x % (int64_t)size;
+  return (uint32_t)(r < 0 ? r + size : r);
+}
+
+__device__ __forceinline__ uint32_t *qcount(const QueueRef &q, uint32_t slot, uint32_t g) {
+  return q.qlen + (size_t)(slot * kQueueGroups + g) * kQlenStride;
+}
+
+// Exclusive prefix of the sub-queue lengths of one slot: pre[kQueueGroups] = total.
+__device__ __forceinline__ void queue_prefix(const QueueRef &q, uint32_t slot,
+                                             uint32_t (&pre)[kQueueGroups + 1]) {
+  pre[0] = 0;
+#pragma unroll
+  for (uint32_t g = 0; g < kQueueGroups; ++g) pre[g + 1] = pre[g] + min(*qcount(q, slot, g), q.group_cap);
+}
+
+// The f-th spike (f < pre[kQueueGroups]) of a slot.
+__device__ __forceinline__ int32_t queue_entry(const QueueRef &q, uint32_t slot,
+                                               const uint32_t (&pre)[kQueueGroups + 1], uint32_t f) {
+  uint32_t g = 0;
+#pragma unroll
+  for (uint32_t k = 1; k < kQueueGroups; ++k) g += f >= pre[k] ? 1u : 0u;
+  return q.ids[(size_t)slot * q.stride + g * q.group_cap + (f - pre[g])];
+}
+
+__device__ __forceinline__ void add_part(uint64_t *counter, uint32_t part, uint64_t x) {
+  if (x) atomicAdd((unsigned long long *)&counter[(part % kCounterParts) * kLineU64], (unsigned long long)x);
+}
+
+constexpr int kUpdateWaves = kUpdateBlock / kWave;
+constexpr int kPrefetch = 16;  // steps of input in flight (4 quads)
+
+// Update Neurons for `steps` (<= 64) consecutive steps.  The LIF arithmetic is
+// sequential per neuron; the rest is batched.  Steps are processed in quads aligned
+// to absolute time (one Philox block per quad, its word t mod 4 feeding step t); the
+// inputs of the next 4 quads are always in flight (a rolling register window, static
+// indices only); the ballot of step w is parked in lane w; after the loop one thread
+// per step reserves the workgroup's space in its sub-queue with one atomic.
+// The drive count k = #{j : tbl[j] <= r} over the thresholds below 2^32 (an entry
+// equal to 2^32 cannot be reached by a 32-bit word) is found from a guide table over
+// the top 12 bits of r, which holds the count at both ends of each bucket, plus a
+// short scan when a threshold falls inside the bucket.
 __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t steps) {
-  __shared__ uint64_t tbl[kTableCap];
-  for (uint32_t j = threadIdx.x; j < a.table_len; j += kUpdateBlock) tbl[j] = a.table[j];
-  __syncthreads();
+  __shared__ uint32_t tbl[kTableCap];
+  __shared__ uint16_t guide[kGuideBuckets];
+  __shared__ uint32_t s_base[kUpdateWaves][kWave];
 
   const uint64_t t0 = a.ctl->t;
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->t_deliver = t0;
+  const uint32_t in0 = (uint32_t)(t0 % a.n_inbuf);
+  const uint32_t slot0 = (uint32_t)(t0 % a.slots);
+  const uint32_t ras0 = (uint32_t)(t0 % a.raster_cap);
+  const uint32_t off = (uint32_t)(t0 & 3u);      // position of t0 in its quad
+  const uint64_t quad0 = t0 >> 2;
+  const uint32_t n_quads = (off + steps + 3) >> 2;
+  const uint32_t group = blockIdx.x % kQueueGroups;
   const uint32_t i = blockIdx.x * kUpdateBlock + threadIdx.x;
   const bool active = i < a.n;
   const uint32_t lane = lane_id();
+  const uint32_t wave = threadIdx.x / kWave;
   const uint32_t word = i / kWave;
   const bool drive = a.table_len > 1;
 
+  // input of window position p = w + off (w = p - off), zeroed behind the read if the
+  // delivery accumulates with atomics
+  auto load_input = [&](int32_t p) -> int32_t {
+    const int32_t w = p - (int32_t)off;
+    if (!active || w < 0 || w >= (int32_t)steps) return 0;
+    int32_t *in = a.input + (size_t)ring_add(in0, (uint32_t)w, a.n_inbuf) * a.n + i;
+    const int32_t x = *in;
+    if (a.zero_input) *in = 0;
+    return x;
+  };
+
+  // ---- one round trip: state, drive tables, first kPrefetch inputs ----
   float v = 0.f, xp = 0.f, xq = 0.f;
   int32_t ref = 0;
   if (active) {
@@ -48,52 +118,65 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
       xq = a.x_post[i];
     }
   }
-  Words4 rnd{};
-  for (uint32_t w = 0; w < steps; ++w) {
-    const uint64_t t = t0 + w;
-    bool spike = false;
-    if (active) {
-      int32_t *in = a.input + (size_t)(t % a.n_inbuf) * a.n + i;
-      const int32_t acc = *in;
-      if (a.zero_input) *in = 0;
-      if (drive && (w == 0 || (t & 3u) == 0))
-        rnd = philox(i, (uint32_t)(t >> 2), (uint32_t)(t >> 34), kStreamPoisson, a.key0, a.key1);
-      if (ref > 0) {
-        ref -= 1;
-      } else {
-        int32_t k = 0;
-        if (drive) {
-          const uint64_t r = rnd.w[t & 3u];
-          while (r >= tbl[k]) ++k;
+  int32_t acc[kPrefetch];
+#pragma unroll
+  for (int j = 0; j < kPrefetch; ++j) acc[j] = load_input(j);
+  if (drive) {
+    for (uint32_t j = threadIdx.x; j < a.table_len; j += kUpdateBlock) tbl[j] = a.table32[j];
+    for (uint32_t j = threadIdx.x; j < kGuideBuckets; j += kUpdateBlock) guide[j] = a.guide[j];
+  }
+  __syncthreads();
+
+  uint64_t my_mask = 0;    // lane w: ballot of step w
+  uint64_t my_spikes = 0;  // bit w: this neuron spiked at step w
+  for (uint32_t qq = 0; qq < n_quads; ++qq) {
+    Words4 rnd{};
+    if (drive && active)
+      rnd = philox(i, (uint32_t)(quad0 + qq), (uint32_t)((quad0 + qq) >> 32), kStreamPoisson, a.key0, a.key1);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t w = (int32_t)(4 * qq + u) - (int32_t)off;
+      if (w < 0 || w >= (int32_t)steps) continue;  // uniform
+      bool spike = false;
+      if (active) {
+        if (ref > 0) {
+          ref -= 1;
+        } else {
+          int32_t k = 0;
+          if (drive) {
+            const uint32_t r = rnd.w[u];
+            const uint32_t gk = guide[r >> (32 - kGuideBits)];
+            k = (int32_t)(gk & 0xFFu);
+            const int32_t k_hi = (int32_t)(gk >> 8);
+            while (k < k_hi && tbl[k] <= r) ++k;
+          }
+          const uint32_t sum = (uint32_t)acc[u] + (uint32_t)k * (uint32_t)a.w_ext_q16;
+          const float dv = (float)(int32_t)sum * 0x1p-16f;
+          float vv = v + dv;
+          const float diff = vv - a.v_inf;
+          const float leak = diff * a.alpha;
+          vv = a.v_inf + leak;
+          if (vv >= a.v_th) {
+            spike = true;
+            vv = a.v_reset;
+            ref = a.ref_steps;
+          }
+          v = vv;
         }
-        const uint32_t sum = (uint32_t)acc + (uint32_t)k * (uint32_t)a.w_ext_q16;
-        const float dv = (float)(int32_t)sum * 0x1p-16f;
-        float vv = v + dv;
-        const float diff = vv - a.v_inf;
-        const float leak = diff * a.alpha;
-        vv = a.v_inf + leak;
-        if (vv >= a.v_th) {
-          spike = true;
-          vv = a.v_reset;
-          ref = a.ref_steps;
+        if (a.plastic) {
+          xp = xp * a.beta_plus;
+          xq = xq * a.beta_minus;
         }
-        v = vv;
       }
-      if (a.plastic) {
-        xp = xp * a.beta_plus;
-        xq = xq * a.beta_minus;
-      }
+      const uint64_t mask = __ballot(spike);
+      if (lane == (uint32_t)w) my_mask = mask;
+      if (spike) my_spikes |= 1ull << w;
     }
-    const uint64_t mask = __ballot(spike);
-    const uint32_t slot = (uint32_t)(t % a.slots);
-    if (lane == 0 && word < a.words) a.raster[(size_t)(t % a.raster_cap) * a.words + word] = mask;
-    if (mask) {
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(&a.qlen[slot], (uint32_t)__popcll(mask));
-      base = __shfl(base, 0, kWave);
-      const uint32_t pos = base + lanes_below(mask);
-      if (spike && pos < a.n) a.queue[(size_t)slot * a.n + pos] = (int32_t)i;
-    }
+    // roll the input window by one quad and request the quad kPrefetch / 4 ahead
+#pragma unroll
+    for (int j = 0; j < kPrefetch - 4; ++j) acc[j] = acc[j + 4];
+#pragma unroll
+    for (int j = kPrefetch - 4; j < kPrefetch; ++j) acc[j] = load_input((int32_t)(4 * (qq + 1)) + j);
   }
   if (active) {
     a.v[i] = v;
@@ -103,33 +186,32 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
       a.x_post[i] = xq;
     }
   }
-}
-
-// Hand-off at the end of the delivery kernel: the last workgroup to finish clears the
-// queue counters of the next window and advances the step counter.
-__device__ __forceinline__ void finish_window(const DeliverArgs &a, uint64_t t0, uint32_t steps) {
-  __shared__ bool last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    last = atomicAdd(&a.ctl->done, 1u) == gridDim.x - 1;
+  // raster rows and queue reservations of the whole window, one lane per step
+  if (lane < steps) {
+    if (word < a.words) a.raster[(size_t)ring_add(ras0, lane, a.raster_cap) * a.words + word] = my_mask;
+    s_base[wave][lane] = (uint32_t)__popcll(my_mask);
   }
   __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
-    if (a.advance) {
-      for (uint32_t w = 0; w < a.window_max; ++w) a.qlen[(t0 + steps + w) % a.slots] = 0u;
-      a.ctl->t = t0 + steps;
+  if (threadIdx.x < steps) {
+    const uint32_t w = threadIdx.x;
+    uint32_t total = 0;
+    for (int v2 = 0; v2 < kUpdateWaves; ++v2) {
+      const uint32_t c = s_base[v2][w];
+      s_base[v2][w] = total;
+      total += c;
     }
-    a.ctl->done = 0u;
-    __threadfence();
+    const uint32_t base = total ? atomicAdd(qcount(a.q, ring_add(slot0, w, a.slots), group), total) : 0u;
+    for (int v2 = 0; v2 < kUpdateWaves; ++v2) s_base[v2][w] += base;
   }
-}
-
-template <bool kPlasticW>
-__device__ __forceinline__ int32_t q16_of(const DeliverArgs &a, uint64_t e) {
-  if constexpr (kPlasticW) return __float2int_rn(a.w_f32[e] * 65536.0f);
-  else return a.w_q16[e];
+  __syncthreads();
+  for (uint32_t w = 0; w < steps; ++w) {
+    const uint64_t mask = __shfl(my_mask, w, kWave);
+    if (!mask) continue;
+    const uint32_t pos = s_base[wave][w] + lanes_below(mask);
+    const uint32_t slot = ring_add(slot0, w, a.slots);
+    if (((my_spikes >> w) & 1u) && pos < a.q.group_cap)
+      a.q.ids[(size_t)slot * a.q.stride + group * a.q.group_cap + pos] = (int32_t)i;
+  }
 }
 
 // Emission step of the w-th queue delivered by a window starting at t0: spikes of step
@@ -138,31 +220,64 @@ __device__ __forceinline__ int64_t emission_step(const DeliverArgs &a, uint64_t 
   return (int64_t)t0 + (int64_t)w + (int64_t)a.n_inbuf - (int64_t)a.delay;
 }
 
+// The delivery launch that closes a window clears the next window's queue counters and
+// advances the step.  Done by one thread at launch start: no workgroup of this launch
+// reads the next window's counters or `t` (they read `t_deliver`), and the next
+// launches see the writes after the kernel boundary.
+__device__ __forceinline__ void close_window(const DeliverArgs &a, uint64_t t0, uint32_t steps) {
+  if (a.advance && blockIdx.x == 0 && threadIdx.x == 0) {
+    const uint32_t next = (uint32_t)((t0 + steps) % a.slots);
+    for (uint32_t w = 0; w < a.window_max; ++w)
+      for (uint32_t g = 0; g < kQueueGroups; ++g) *qcount(a.q, ring_add(next, w, a.slots), g) = 0u;
+    a.ctl->t = t0 + steps;
+  }
+}
+
 constexpr int kAtomicBlock = 256;
+constexpr int kAtomicWaves = kAtomicBlock / kWave;
 
 template <bool kPlasticW>
 __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, uint32_t steps) {
-  const uint64_t t0 = a.ctl->t;
+  __shared__ uint32_t s_pre[kWave][kQueueGroups + 1];  // per step: sub-queue prefix
+  __shared__ uint32_t s_slot[kWave];
+  __shared__ uint32_t s_step[kWave + 1];               // prefix of the per-step totals
+  const uint64_t t0 = a.ctl->t_deliver;
+  close_window(a, t0, steps);
+  const int64_t e0 = emission_step(a, t0, 0);
+  const uint32_t eslot0 = ring_of(e0, a.slots);
+  const uint32_t in0 = (uint32_t)(t0 % a.n_inbuf);
   const uint32_t lane = lane_id();
-  uint32_t c = 0;
-  if (lane < steps) {
-    const int64_t e = emission_step(a, t0, lane);
-    if (e >= 0) c = min(a.qlen[(uint64_t)e % a.slots], a.n);
+  if (threadIdx.x < kWave) {
+    uint32_t pre[kQueueGroups + 1] = {};
+    const uint32_t w = threadIdx.x;
+    uint32_t slot = 0;
+    if (w < steps && e0 + (int64_t)w >= 0) {
+      slot = ring_add(eslot0, w, a.slots);
+      queue_prefix(a.q, slot, pre);
+    }
+    s_slot[w] = slot;
+#pragma unroll
+    for (uint32_t g = 0; g <= kQueueGroups; ++g) s_pre[w][g] = pre[g];
+    const uint32_t c = pre[kQueueGroups];
+    const uint32_t incl = wave_inclusive_scan(c);
+    s_step[w + 1] = incl;
+    if (w == 0) s_step[0] = 0;
   }
-  const uint32_t incl = wave_inclusive_scan(c);
-  const uint32_t total = __shfl(incl, kWave - 1, kWave);
-  const uint32_t gwave = blockIdx.x * (kAtomicBlock / kWave) + threadIdx.x / kWave;
-  const uint32_t n_gwaves = gridDim.x * (kAtomicBlock / kWave);
-  uint64_t ev = 0;
+  __syncthreads();
+  const uint32_t total = s_step[kWave];
+  const uint32_t gwave = blockIdx.x * kAtomicWaves + threadIdx.x / kWave;
+  const uint32_t n_gwaves = gridDim.x * kAtomicWaves;
+  uint64_t ev = 0, n_spk = 0;
   for (uint32_t f = gwave; f < total; f += n_gwaves) {
-    const uint32_t w = (uint32_t)__popcll(__ballot(incl <= f));
-    const uint32_t prev = __shfl(incl, (w + kWave - 1) % kWave, kWave);
-    const uint32_t before = w ? prev : 0u;
-    const uint64_t e = (uint64_t)emission_step(a, t0, w);
-    const uint32_t slot = (uint32_t)(e % a.slots);
-    int32_t *in = a.input + (size_t)((t0 + w) % a.n_inbuf) * a.n;
-    const int32_t src = a.queue[(size_t)slot * a.n + (f - before)];
+    uint32_t w = 0;  // step of spike f: last w with s_step[w] <= f
+    for (uint32_t half = kWave / 2; half > 0; half >>= 1)
+      if (s_step[w + half] <= f) w += half;
+    uint32_t pre[kQueueGroups + 1];
+#pragma unroll
+    for (uint32_t g = 0; g <= kQueueGroups; ++g) pre[g] = s_pre[w][g];
+    const int32_t src = queue_entry(a.q, s_slot[w], pre, f - s_step[w]);
     if ((uint32_t)src >= a.n) continue;
+    int32_t *in = a.input + (size_t)ring_add(in0, w, a.n_inbuf) * a.n;
     const uint64_t rs = a.row_ptr[src], re = a.row_ptr[src + 1];
     for (uint64_t g = (rs >> 2) + lane; g < ((re + 3) >> 2); g += kWave) {
       const int4 c4 = reinterpret_cast<const int4 *>(a.col)[g];
@@ -189,74 +304,159 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
       }
     }
     ev += re - rs;
+    ++n_spk;
   }
-  if (lane == 0 && ev) atomicAdd((unsigned long long *)&a.ctl->events, (unsigned long long)ev);
-  finish_window(a, t0, steps);
+  if (lane == 0) {
+    add_part(a.ctl->events, gwave, ev);
+    add_part(a.ctl->spikes, gwave, n_spk);
+  }
 }
 
+constexpr int kTiledUnroll = 8;
+
+// Loads kTiledUnroll elements of the flattened sub-row range, 64 apart, starting at
+// this lane's element `first`; `o` is the lane's current sub-row (monotone).
+template <int kU>
+__device__ __forceinline__ void tiled_load(const DeliverArgs &a, const uint64_t *s_lo,
+                                           const uint32_t *s_pre, uint32_t first, uint32_t end,
+                                           int32_t tile_lo, uint32_t &o, int32_t (&cv)[kU],
+                                           int32_t (&wv)[kU]) {
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const uint32_t idx = first + u * kWave;
+    cv[u] = tile_lo;
+    wv[u] = 0;
+    if (idx < end) {
+      while (s_pre[o + 1] <= idx) ++o;
+      const uint64_t e = s_lo[o] + (idx - s_pre[o]);
+      cv[u] = a.col[e];
+      wv[u] = a.w_q16[e];
+    }
+  }
+}
+
+// One workgroup owns (target tile, emission step): it accumulates that step's
+// deliveries into the tile in LDS and then writes the tile's accumulators.  Spikes are
+// processed in chunks of kBlock: every thread fetches one spike's sub-row bounds (the
+// edges of the spike's sorted row that fall in this tile), a block scan lays the
+// sub-rows end to end, and each wave streams a contiguous share of the flattened edge
+// range, 64 x kTiledUnroll elements at a time, with the next batch's loads issued
+// before the current batch's LDS atomics.
 template <int kBlock>
 __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a) {
   extern __shared__ int32_t acc[];
   constexpr int kWaves = kBlock / kWave;
-  const uint64_t t0 = a.ctl->t;
+  constexpr int kU = kTiledUnroll;
+  __shared__ uint64_t s_lo[kBlock];
+  __shared__ uint32_t s_pre[kBlock + 1];
+  __shared__ uint32_t s_wave[kWaves];
+  const uint64_t t0 = a.ctl->t_deliver;
   const uint32_t tile = blockIdx.x % a.tiles;
   const uint32_t w = blockIdx.x / a.tiles;
   const uint32_t steps = gridDim.x / a.tiles;
+  close_window(a, t0, steps);
   const uint32_t tile_lo = tile * a.tile_size;
   const uint32_t tile_n = min(a.tile_size, a.n - tile_lo);
   for (uint32_t j = threadIdx.x; j < tile_n; j += kBlock) acc[j] = 0;
-  __syncthreads();
 
   const uint32_t lane = lane_id();
   const uint32_t wave = threadIdx.x / kWave;
   const int64_t e_step = emission_step(a, t0, w);
   uint64_t ev = 0;
+  uint32_t qpre[kQueueGroups + 1] = {};
+  uint32_t slot = 0;
   if (e_step >= 0) {
-    const uint32_t slot = (uint32_t)((uint64_t)e_step % a.slots);
-    const uint32_t cnt = min(a.qlen[slot], a.n);
-    const int32_t *ids = a.queue + (size_t)slot * a.n;
-    for (uint32_t s = wave; s < cnt; s += kWaves) {
-      const int32_t src = ids[s];
-      if ((uint32_t)src >= a.n) continue;
-      const uint64_t base = a.row_ptr[src];
-      const uint32_t *to = a.tile_off + (size_t)src * (a.tiles + 1) + tile;
-      const uint64_t lo = base + to[0], hi = base + to[1];
-      for (uint64_t e = lo + lane; e < hi; e += 4 * kWave) {
-        int32_t cv[4], wv[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint64_t x = e + (uint64_t)q * kWave;
-          cv[q] = x < hi ? a.col[x] : (int32_t)tile_lo;
-          wv[q] = x < hi ? a.w_q16[x] : 0;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (wv[q]) atomicAdd(&acc[cv[q] - (int32_t)tile_lo], wv[q]);
+    slot = ring_of(e_step, a.slots);
+    queue_prefix(a.q, slot, qpre);
+  }
+  const uint32_t cnt = qpre[kQueueGroups];
+  __syncthreads();
+  for (uint32_t c0 = 0; c0 < cnt; c0 += kBlock) {
+    const uint32_t m = min((uint32_t)kBlock, cnt - c0);
+    // (1) sub-row bounds of this chunk's spikes
+    uint32_t len = 0;
+    uint64_t lo = 0;
+    if (threadIdx.x < m) {
+      const int32_t src = queue_entry(a.q, slot, qpre, c0 + threadIdx.x);
+      if ((uint32_t)src < a.n) {
+        const uint32_t *to = a.tile_off + (size_t)src * (a.tiles + 1) + tile;
+        const uint32_t o0 = to[0], o1 = to[1];
+        lo = a.row_ptr[src] + o0;
+        len = o1 - o0;
       }
-      ev += hi - lo;
     }
+    // (2) block-wide exclusive scan of the sub-row lengths
+    const uint32_t incl = wave_inclusive_scan(len);
+    if (lane == kWave - 1) s_wave[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+      const uint32_t x = lane < kWaves ? s_wave[lane] : 0u;
+      const uint32_t xi = wave_inclusive_scan(x);
+      if (lane < kWaves) s_wave[lane] = xi - x;
+    }
+    __syncthreads();
+    const uint32_t pre = s_wave[wave] + incl - len;
+    if (threadIdx.x < m) {
+      s_pre[threadIdx.x] = pre;
+      s_lo[threadIdx.x] = lo;
+    }
+    if (threadIdx.x == kBlock - 1) s_pre[m] = pre + len;
+    __syncthreads();
+    const uint32_t total = s_pre[m];
+    ev += total;
+    // (3) this wave's contiguous share of the flattened edges
+    const uint32_t share = (total + kWaves - 1) / kWaves;
+    const uint32_t beg = min(wave * share, total), end = min(beg + share, total);
+    if (beg < end) {
+      uint32_t lo_j = 0, hi_j = m;  // sub-row holding element beg
+      while (hi_j - lo_j > 1) {
+        const uint32_t mid = (lo_j + hi_j) >> 1;
+        if (s_pre[mid] <= beg) lo_j = mid;
+        else hi_j = mid;
+      }
+      uint32_t o = lo_j;
+      int32_t cv[kU], wv[kU], cn[kU], wn[kU];
+      tiled_load<kU>(a, s_lo, s_pre, beg + lane, end, (int32_t)tile_lo, o, cv, wv);
+      for (uint32_t b0 = beg; b0 < end; b0 += kWave * kU) {
+        const uint32_t nb = b0 + kWave * kU;
+        if (nb < end) tiled_load<kU>(a, s_lo, s_pre, nb + lane, end, (int32_t)tile_lo, o, cn, wn);
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (wv[u]) atomicAdd(&acc[cv[u] - (int32_t)tile_lo], wv[u]);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          cv[u] = cn[u];
+          wv[u] = wn[u];
+        }
+      }
+    }
+    __syncthreads();
   }
   __syncthreads();
-  int32_t *out = a.input + (size_t)((t0 + w) % a.n_inbuf) * a.n + tile_lo;
+  int32_t *out = a.input + (size_t)ring_add((uint32_t)(t0 % a.n_inbuf), w, a.n_inbuf) * a.n + tile_lo;
   for (uint32_t j = threadIdx.x; j < tile_n; j += kBlock) out[j] = acc[j];
-  if (lane == 0 && ev) atomicAdd((unsigned long long *)&a.ctl->events, (unsigned long long)ev);
-  finish_window(a, t0, steps);
+  if (threadIdx.x == 0) {
+    add_part(a.ctl->events, blockIdx.x, ev);
+    if (tile == 0) add_part(a.ctl->spikes, blockIdx.x, cnt);
+  }
 }
 
 constexpr int kStdpBlock = 256;
+constexpr int kStdpWaves = kStdpBlock / kWave;
 
 __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltd(StdpArgs a) {
   const uint64_t t = a.ctl->t;
   if (t < a.delay) return;
   const uint32_t slot = (uint32_t)((t - a.delay) % a.slots);
-  const uint32_t cnt = min(a.qlen[slot], a.n);
-  const int32_t *ids = a.queue + (size_t)slot * a.n;
+  uint32_t pre[kQueueGroups + 1];
+  queue_prefix(a.q, slot, pre);
+  const uint32_t cnt = pre[kQueueGroups];
   const uint32_t lane = lane_id();
-  const uint32_t gwave = blockIdx.x * (kStdpBlock / kWave) + threadIdx.x / kWave;
-  const uint32_t n_gwaves = gridDim.x * (kStdpBlock / kWave);
+  const uint32_t gwave = blockIdx.x * kStdpWaves + threadIdx.x / kWave;
+  const uint32_t n_gwaves = gridDim.x * kStdpWaves;
   uint64_t touched = 0;
   for (uint32_t s = gwave; s < cnt; s += n_gwaves) {
-    const int32_t i = ids[s];
+    const int32_t i = queue_entry(a.q, slot, pre, s);
     if ((uint32_t)i >= a.n) continue;
     if (lane == 0) a.x_pre[i] = a.x_pre[i] + 1.0f;
     const uint64_t lo = a.row_ptr[i] + a.plast_rel[i];
@@ -270,20 +470,21 @@ __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltd(StdpArgs a) {
     }
     touched += len;
   }
-  if (lane == 0 && touched) atomicAdd((unsigned long long *)&a.ctl->touches, (unsigned long long)touched);
+  if (lane == 0) add_part(a.ctl->touches, gwave, touched);
 }
 
 __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltp(StdpArgs a) {
   const uint64_t t = a.ctl->t;
   const uint32_t slot = (uint32_t)(t % a.slots);
-  const uint32_t cnt = min(a.qlen[slot], a.n);
-  const int32_t *ids = a.queue + (size_t)slot * a.n;
+  uint32_t pre[kQueueGroups + 1];
+  queue_prefix(a.q, slot, pre);
+  const uint32_t cnt = pre[kQueueGroups];
   const uint32_t lane = lane_id();
-  const uint32_t gwave = blockIdx.x * (kStdpBlock / kWave) + threadIdx.x / kWave;
-  const uint32_t n_gwaves = gridDim.x * (kStdpBlock / kWave);
+  const uint32_t gwave = blockIdx.x * kStdpWaves + threadIdx.x / kWave;
+  const uint32_t n_gwaves = gridDim.x * kStdpWaves;
   uint64_t touched = 0;
   for (uint32_t s = gwave; s < cnt; s += n_gwaves) {
-    const int32_t j = ids[s];
+    const int32_t j = queue_entry(a.q, slot, pre, s);
     if ((uint32_t)j >= a.n) continue;
     if (lane == 0) a.x_post[j] = a.x_post[j] + 1.0f;
     const uint64_t lo = a.in_ptr[j], hi = a.in_ptr[j + 1];
@@ -296,7 +497,7 @@ __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltp(StdpArgs a) {
     }
     touched += hi - lo;
   }
-  if (lane == 0 && touched) atomicAdd((unsigned long long *)&a.ctl->touches, (unsigned long long)touched);
+  if (lane == 0) add_part(a.ctl->touches, gwave, touched);
 }
 
 }  // namespace

@@ -43,20 +43,21 @@ class Network:
 
     Parameters beyond the spec: raster_steps (raster ring capacity), window (max
     steps per update launch; 0 = the delay), delivery ("auto" | "atomic" | "tiled"),
-    tiles (target tiles of the tiled delivery; 0 = auto), torch_memory (allocate
+    tiles (target tiles of the tiled delivery; 0 = auto), block (its workgroup size:
+    256 | 512 | 1024; 0 = auto), torch_memory (allocate
     through torch's caching allocator and run on torch's current stream).
     """
 
-    def __init__(self, spec, raster_steps=1024, window=0, delivery="auto", tiles=0,
+    def __init__(self, spec, raster_steps=1024, window=0, delivery="auto", tiles=0, block=0,
                  torch_memory=True, device=0):
         lib = L.load()
         self._lib = lib
         self._h = None
         prm = spec["params"]
         fields = {k: prm[k] for k, _ in L.PARAM_FIELDS
-                  if k not in ("raster_steps", "window", "delivery", "tiles")}
+                  if k not in ("raster_steps", "window", "delivery", "tiles", "block")}
         p = L.Params(**fields, raster_steps=raster_steps, window=window,
-                     delivery=L.DELIVERY[delivery], tiles=tiles)
+                     delivery=L.DELIVERY[delivery], tiles=tiles, block=block)
         pops = (L.Population * len(spec["pops"]))(
             *[L.Population(q["size"], q.get("excitatory", 1)) for q in spec["pops"]])
         projs_in = spec.get("projs", [])
@@ -159,8 +160,8 @@ class Network:
              "input": np.zeros((nb, n), np.int32), "x_pre": np.zeros(n, np.float32),
              "x_post": np.zeros(n, np.float32)}
         if queues:
-            s["queue"] = np.zeros((ns, n), np.int32)
-            s["queue_len"] = np.zeros(ns, np.uint32)
+            s["queue"] = np.zeros((ns, inf["queue_stride"]), np.int32)
+            s["queue_len"] = np.zeros((ns, inf["queue_groups"]), np.uint32)
         if weights:
             s["w_f32"] = np.zeros(inf["nnz"], np.float32)
         st = L.State(*[_ptr(s.get(k)) for k in ("v", "ref", "input", "x_pre", "x_post", "queue",
