@@ -92,6 +92,7 @@ typedef struct {
     uint32_t delivery;     /* SNN_DELIVERY_* */
     uint32_t tiles;        /* target tiles of the tiled delivery (0: auto) */
     uint32_t block;        /* workgroup size of the tiled delivery: 256, 512, 1024 (0: auto) */
+    uint32_t grid;         /* workgroups of the tiled delivery (0: auto) */
 } snn_params;
 
 /* Optional device-memory provider (e.g. a framework's caching allocator).  alloc
@@ -200,12 +201,13 @@ snn_status snn_get_profile(snn_network *net, snn_profile *prof);
 snn_status snn_reset_profile(snn_network *net);
 snn_status snn_sync(snn_network *net);
 
-/* Deliver a caller-given spike list (device array of ids) once with the network's
- * delivery kernel into scratch accumulators, `reps` times, and return the average
- * kernel time in ms (HIP events).  The network's own state is left unchanged.  Used
- * to measure the delivery kernel alone at a chosen load. */
+/* Deliver a caller-given spike list with the network's delivery kernel, spread
+ * round-robin over `steps` emission steps (0: the network's window) as one window,
+ * into scratch accumulators, `reps` times; returns the mean kernel time in ms (HIP
+ * events) and the events of one launch.  The network's own state is left unchanged.
+ * Used to measure the delivery kernel alone at a chosen load. */
 snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_t n_ids,
-                             uint32_t reps, double *avg_ms, uint64_t *events);
+                             uint32_t steps, uint32_t reps, double *avg_ms, uint64_t *events);
 
 void snn_destroy(snn_network *net);
 const char *snn_last_error(void);

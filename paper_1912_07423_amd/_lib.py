@@ -43,6 +43,7 @@ PARAM_FIELDS = [
     ("a_plus", C.c_double), ("a_minus", C.c_double), ("w_max_mV", C.c_double),
     ("seed", C.c_uint64), ("raster_steps", C.c_uint32), ("window", C.c_uint32),
     ("delivery", C.c_uint32), ("tiles", C.c_uint32), ("block", C.c_uint32),
+    ("grid", C.c_uint32),
 ]
 
 
@@ -101,7 +102,7 @@ SIGNATURES = {
     "snn_get_profile": (C.c_int32, [C.c_void_p, C.POINTER(Profile)]),
     "snn_reset_profile": (C.c_int32, [C.c_void_p]),
     "snn_sync": (C.c_int32, [C.c_void_p]),
-    "snn_time_delivery": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32,
+    "snn_time_delivery": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
                                       C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "snn_destroy": (None, [C.c_void_p]),
     "snn_last_error": (C.c_char_p, []),

@@ -248,16 +248,18 @@ void choose_delivery(snn_network *net) {
     const uint32_t b = net->prm.block;
     if (b != 0 && b != 256 && b != 512 && b != 1024) fail(SNN_E_INVALID, "block must be 256, 512 or 1024");
     net->block = b ? b : 512;
-    constexpr uint32_t kMaxTile = 8192;  // 32 KB of LDS per workgroup
-    const uint32_t min_tiles = (net->n + kMaxTile - 1) / kMaxTile;
-    uint32_t tiles = net->prm.tiles;
-    if (!tiles) tiles = std::max(min_tiles, (512u + net->window - 1) / net->window);
-    tiles = std::min(std::max(tiles, min_tiles), std::max(1u, net->n / 64u));
-    tiles = std::max(tiles, min_tiles);
-    net->tiles = tiles;
+    // base tiles of at most kMaxRange / kTileGroupMax targets, so that a workgroup's
+    // range of up to kTileGroupMax base tiles (48 KB) plus its scan arrays fit the
+    // 64 KB a workgroup may allocate
+    constexpr uint32_t kMaxRange = 12288;
+    const uint32_t tile_cap = kMaxRange / snn::kTileGroupMax;
+    const uint32_t min_tiles = (net->n + tile_cap - 1) / tile_cap;
+    uint32_t tiles = net->prm.tiles ? net->prm.tiles : min_tiles;
+    tiles = std::max(std::min(tiles, std::max(1u, net->n / 16u)), min_tiles);
     net->tile_size = (net->n + tiles - 1) / tiles;
     net->tiles = (net->n + net->tile_size - 1) / net->tile_size;
-    if (net->tile_size > kMaxTile) fail(SNN_E_INVALID, "tile too large for LDS");
+    if (net->tile_size > tile_cap) fail(SNN_E_INVALID, "tile too large for LDS");
+    net->grid = net->prm.grid ? net->prm.grid : 2 * net->cu_count;  // two resident per CU
   } else if (net->delivery == SNN_DELIVERY_ATOMIC) {
     net->tiles = 1;
     net->tile_size = net->n;
@@ -500,7 +502,8 @@ snn::StdpArgs stdp_args(snn_network *net) {
 uint32_t atomic_grid(const snn_network *net) { return net->cu_count * 8; }
 
 hipError_t launch_delivery(snn_network *net, const snn::DeliverArgs &d, uint32_t steps) {
-  if (net->delivery == SNN_DELIVERY_TILED) return snn::launch_deliver_tiled(d, steps, net->block, net->stream);
+  if (net->delivery == SNN_DELIVERY_TILED)
+    return snn::launch_deliver_tiled(d, steps, net->block, net->grid, net->stream);
   return snn::launch_deliver_atomic(d, steps, atomic_grid(net), net->plastic, net->stream);
 }
 
@@ -913,11 +916,13 @@ snn_status snn_reset_profile(snn_network *net) {
   });
 }
 
-snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_t n_ids, uint32_t reps,
-                             double *avg_ms, uint64_t *events) {
+snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_t n_ids,
+                             uint32_t steps, uint32_t reps, double *avg_ms, uint64_t *events) {
   return guarded([&] {
     if (!net || (!ids_host && n_ids) || !avg_ms) fail(SNN_E_INVALID, "null argument");
-    if (n_ids > net->n) fail(SNN_E_INVALID, "more ids than neurons");
+    if (steps == 0) steps = net->window;
+    if (steps > net->window) fail(SNN_E_INVALID, "steps exceeds the network's window");
+    if (n_ids > (uint64_t)net->n * steps) fail(SNN_E_INVALID, "more ids than the queues hold");
     for (uint32_t k = 0; k < n_ids; ++k)
       if (ids_host[k] >= net->n) fail(SNN_E_INVALID, "id out of range");
     if (reps == 0) reps = 1;
@@ -934,9 +939,9 @@ snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_
     check(hipMemsetAsync(input, 0, (size_t)net->n_inbuf * net->n * 4, s), "clear");
     if (n_ids) check(hipMemcpyAsync(ids, ids_host, (size_t)n_ids * 4, hipMemcpyHostToDevice, s), "ids");
     const snn::QueueRef sq{queue, qlen, net->queue_stride, net->group_cap};
-    check(snn::launch_scatter_ids(ids, n_ids, sq, s), "scatter ids");
-    // the queue in slot 0 is the one delivered by a one-step window starting at t0
-    // when t0 + n_inbuf - delay = 0 (mod slots)
+    check(snn::launch_scatter_ids(ids, n_ids, steps, sq, s), "scatter ids");
+    // slots 0..steps-1 are the queues delivered by a window starting at t0 when
+    // t0 + n_inbuf - delay = 0 (mod slots)
     std::vector<snn::Ctl> c0(1);
     std::memset(c0.data(), 0, sizeof(snn::Ctl));
     c0[0].t_deliver = (uint64_t)net->delay - net->n_inbuf;
@@ -947,11 +952,11 @@ snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_
     d.input = input;
     d.ctl = ctl;
     d.advance = 0;
-    check(launch_delivery(net, d, 1), "warm-up delivery");
+    check(launch_delivery(net, d, steps), "warm-up delivery");
     net->prof_last = nullptr;
     hipEvent_t a = new_event(), b = new_event();
     check(hipEventRecord(a, s), "event");
-    for (uint32_t r = 0; r < reps; ++r) check(launch_delivery(net, d, 1), "delivery");
+    for (uint32_t r = 0; r < reps; ++r) check(launch_delivery(net, d, steps), "delivery");
     check(hipEventRecord(b, s), "event");
     check(hipEventSynchronize(b), "event sync");
     float ms = 0.f;

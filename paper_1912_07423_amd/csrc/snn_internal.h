@@ -122,7 +122,8 @@ hipError_t launch_update(const UpdateArgs &a, uint32_t steps, hipStream_t s);
 hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t grid,
                                  bool plastic_w, hipStream_t s);
 hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t block,
-                                hipStream_t s);
+                                uint32_t grid, hipStream_t s);
+constexpr uint32_t kTileGroupMax = 4;  // base tiles one tiled-delivery workgroup may own
 hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_row_lengths(const GenArgs &g, uint32_t *len, uint32_t *plast_rel,
                               uint32_t *plast_len, hipStream_t s);
@@ -143,8 +144,8 @@ hipError_t launch_tile_offsets(const uint64_t *row_ptr, const int32_t *col, uint
                                hipStream_t s);
 hipError_t launch_init_neurons(float *v, int32_t *ref, uint32_t n, uint32_t key0, uint32_t key1,
                                float lo, float span, hipStream_t s);
-hipError_t launch_scatter_ids(const uint32_t *ids, uint32_t n_ids, const QueueRef &q,
-                              hipStream_t s);
+hipError_t launch_scatter_ids(const uint32_t *ids, uint32_t n_ids, uint32_t steps,
+                              const QueueRef &q, hipStream_t s);
 
 }  // namespace snn
 
@@ -159,7 +160,7 @@ struct snn_network {
 
   // sizes and schedule
   uint32_t n = 0, delay = 1, slots = 2, n_inbuf = 1, window = 1;
-  uint32_t delivery = SNN_DELIVERY_ATOMIC, tiles = 1, tile_size = 1, block = 512;
+  uint32_t delivery = SNN_DELIVERY_ATOMIC, tiles = 1, tile_size = 1, block = 512, grid = 512;
   uint32_t raster_cap = 1024, words = 1;
   bool plastic = false;
   uint64_t nnz = 0, nnz_alloc = 0;

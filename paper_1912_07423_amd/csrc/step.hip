@@ -335,52 +335,128 @@ __device__ __forceinline__ void tiled_load(const DeliverArgs &a, const uint64_t 
   }
 }
 
-// One workgroup owns (target tile, emission step): it accumulates that step's
-// deliveries into the tile in LDS and then writes the tile's accumulators.  Spikes are
-// processed in chunks of kBlock: every thread fetches one spike's sub-row bounds (the
-// edges of the spike's sorted row that fall in this tile), a block scan lays the
-// sub-rows end to end, and each wave streams a contiguous share of the flattened edge
-// range, 64 x kTiledUnroll elements at a time, with the next batch's loads issued
-// before the current batch's LDS atomics.
+constexpr uint32_t kMaxTileGroup = 4;  // base tiles a workgroup may own
+
+// Balanced schedule of one window, derived by every workgroup from the step counts
+// c_w: step w is cut into ceil(P / m_w) target ranges of m_w consecutive base tiles,
+// one workgroup each, with m_w in [1, kMaxTileGroup].  The work of a range is about
+// c_w * m_w sub-rows; the schedule takes the smallest bound X on it for which the
+// ranges fit the grid, m_w = clamp(X / c_w, 1, kMaxTileGroup).  The candidate bounds
+// are the products c_w * m (one lane each), so a wave finds X in one pass.
+struct TileSchedule {
+  uint32_t m[kWave];          // base tiles per range, per step
+  uint32_t first[kWave + 1];  // first workgroup of each step
+};
+
+// Base tiles per range of a step with count c under the work bound x (division-free:
+// m = clamp(floor(x / c), 1, kMaxTileGroup)).
+__device__ __forceinline__ uint32_t group_for(uint32_t x, uint32_t c) {
+  if (c == 0) return kMaxTileGroup;
+  uint32_t m = 1;
+#pragma unroll
+  for (uint32_t k = 2; k <= kMaxTileGroup; ++k) m += (uint64_t)x >= (uint64_t)c * k ? 1u : 0u;
+  return m;
+}
+
+__device__ void make_schedule(const uint32_t *cnt, uint32_t steps, uint32_t tiles, uint32_t grid,
+                              TileSchedule &sch) {
+  const uint32_t lane = lane_id();
+  uint32_t ranges[kMaxTileGroup + 1];
+#pragma unroll
+  for (uint32_t m = 1; m <= kMaxTileGroup; ++m) ranges[m] = (tiles + m - 1) / m;
+  // candidate bound from lane = (step, m) pairs; other lanes propose "all ranges maximal"
+  const uint32_t w_c = lane / kMaxTileGroup, m_c = lane % kMaxTileGroup + 1;
+  uint32_t x = 0xFFFFFFFFu;
+  if (w_c < steps) x = cnt[w_c] * m_c;
+  uint32_t need = 0;
+  for (uint32_t w = 0; w < steps; ++w) {
+    const uint32_t g = x == 0xFFFFFFFFu ? kMaxTileGroup : group_for(x, cnt[w]);
+#pragma unroll
+    for (uint32_t m = 1; m <= kMaxTileGroup; ++m) need += g == m ? ranges[m] : 0u;
+  }
+  uint32_t best = need <= grid ? x : 0xFFFFFFFFu;
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) best = min(best, (uint32_t)__shfl_xor(best, d, kWave));
+  if (lane == 0) {
+    uint32_t acc = 0;
+    for (uint32_t w = 0; w < steps; ++w) {
+      const uint32_t g = best == 0xFFFFFFFFu ? kMaxTileGroup : group_for(best, cnt[w]);
+      sch.m[w] = g;
+      sch.first[w] = acc;
+      acc += (tiles + g - 1) / g;
+    }
+    sch.first[steps] = acc;
+  }
+}
+
+// A workgroup owns (a range of consecutive base tiles, one emission step): it
+// accumulates that step's deliveries to the range's targets in LDS and then writes the
+// range's input accumulators.  Spikes are processed in chunks of kBlock: every thread
+// fetches one spike's sub-row bounds (the edges of the spike's sorted row that fall in
+// the range), a block scan lays the sub-rows end to end, and each wave streams a
+// contiguous share of the flattened edge range, 64 x kTiledUnroll elements at a time,
+// with the next batch's loads issued before the current batch's LDS atomics.
 template <int kBlock>
-__global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a) {
+__global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_t steps) {
   extern __shared__ int32_t acc[];
   constexpr int kWaves = kBlock / kWave;
   constexpr int kU = kTiledUnroll;
   __shared__ uint64_t s_lo[kBlock];
   __shared__ uint32_t s_pre[kBlock + 1];
   __shared__ uint32_t s_wave[kWaves];
+  __shared__ uint32_t s_cnt[kWave];
+  __shared__ uint32_t s_qpre[kWave][kQueueGroups + 1];
+  __shared__ uint32_t s_slot[kWave];
+  __shared__ TileSchedule sch;
   const uint64_t t0 = a.ctl->t_deliver;
-  const uint32_t tile = blockIdx.x % a.tiles;
-  const uint32_t w = blockIdx.x / a.tiles;
-  const uint32_t steps = gridDim.x / a.tiles;
   close_window(a, t0, steps);
-  const uint32_t tile_lo = tile * a.tile_size;
-  const uint32_t tile_n = min(a.tile_size, a.n - tile_lo);
-  for (uint32_t j = threadIdx.x; j < tile_n; j += kBlock) acc[j] = 0;
-
   const uint32_t lane = lane_id();
   const uint32_t wave = threadIdx.x / kWave;
-  const int64_t e_step = emission_step(a, t0, w);
-  uint64_t ev = 0;
-  uint32_t qpre[kQueueGroups + 1] = {};
-  uint32_t slot = 0;
-  if (e_step >= 0) {
-    slot = ring_of(e_step, a.slots);
-    queue_prefix(a.q, slot, qpre);
+
+  // ---- the window's queue lengths and the balanced schedule ----
+  if (wave == 0) {
+    uint32_t qp[kQueueGroups + 1] = {};
+    uint32_t slot = 0;
+    const int64_t e = emission_step(a, t0, lane);
+    if (lane < steps && e >= 0) {
+      slot = ring_of(e, a.slots);
+      queue_prefix(a.q, slot, qp);
+    }
+    s_slot[lane] = slot;
+#pragma unroll
+    for (uint32_t g = 0; g <= kQueueGroups; ++g) s_qpre[lane][g] = qp[g];
+    s_cnt[lane] = qp[kQueueGroups];
   }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < kMaxTileGroup * a.tile_size; j += kBlock) acc[j] = 0;
+  if (wave == 0) make_schedule(s_cnt, steps, a.tiles, gridDim.x, sch);
+  __syncthreads();
+  if (blockIdx.x >= sch.first[steps]) return;  // more workgroups than ranges this window
+  uint32_t w = 0;
+  while (sch.first[w + 1] <= blockIdx.x) ++w;
+  const uint32_t m = sch.m[w];
+  const uint32_t tile_a = (blockIdx.x - sch.first[w]) * m;
+  const uint32_t tile_b = min(tile_a + m, a.tiles);
+  const uint32_t tile_lo = tile_a * a.tile_size;
+  const uint32_t tile_n = min(tile_b * a.tile_size, a.n) - tile_lo;
+
+  const uint32_t slot = s_slot[w];
+  uint32_t qpre[kQueueGroups + 1];
+#pragma unroll
+  for (uint32_t g = 0; g <= kQueueGroups; ++g) qpre[g] = s_qpre[w][g];
   const uint32_t cnt = qpre[kQueueGroups];
+  uint64_t ev = 0;
   __syncthreads();
   for (uint32_t c0 = 0; c0 < cnt; c0 += kBlock) {
-    const uint32_t m = min((uint32_t)kBlock, cnt - c0);
+    const uint32_t mm = min((uint32_t)kBlock, cnt - c0);
     // (1) sub-row bounds of this chunk's spikes
     uint32_t len = 0;
     uint64_t lo = 0;
-    if (threadIdx.x < m) {
+    if (threadIdx.x < mm) {
       const int32_t src = queue_entry(a.q, slot, qpre, c0 + threadIdx.x);
       if ((uint32_t)src < a.n) {
-        const uint32_t *to = a.tile_off + (size_t)src * (a.tiles + 1) + tile;
-        const uint32_t o0 = to[0], o1 = to[1];
+        const uint32_t *to = a.tile_off + (size_t)src * (a.tiles + 1);
+        const uint32_t o0 = to[tile_a], o1 = to[tile_b];
         lo = a.row_ptr[src] + o0;
         len = o1 - o0;
       }
@@ -396,19 +472,19 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a) {
     }
     __syncthreads();
     const uint32_t pre = s_wave[wave] + incl - len;
-    if (threadIdx.x < m) {
+    if (threadIdx.x < mm) {
       s_pre[threadIdx.x] = pre;
       s_lo[threadIdx.x] = lo;
     }
-    if (threadIdx.x == kBlock - 1) s_pre[m] = pre + len;
+    if (threadIdx.x == kBlock - 1) s_pre[mm] = pre + len;
     __syncthreads();
-    const uint32_t total = s_pre[m];
+    const uint32_t total = s_pre[mm];
     ev += total;
     // (3) this wave's contiguous share of the flattened edges
     const uint32_t share = (total + kWaves - 1) / kWaves;
     const uint32_t beg = min(wave * share, total), end = min(beg + share, total);
     if (beg < end) {
-      uint32_t lo_j = 0, hi_j = m;  // sub-row holding element beg
+      uint32_t lo_j = 0, hi_j = mm;  // sub-row holding element beg
       while (hi_j - lo_j > 1) {
         const uint32_t mid = (lo_j + hi_j) >> 1;
         if (s_pre[mid] <= beg) lo_j = mid;
@@ -437,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a) {
   for (uint32_t j = threadIdx.x; j < tile_n; j += kBlock) out[j] = acc[j];
   if (threadIdx.x == 0) {
     add_part(a.ctl->events, blockIdx.x, ev);
-    if (tile == 0) add_part(a.ctl->spikes, blockIdx.x, cnt);
+    if (tile_a == 0) add_part(a.ctl->spikes, blockIdx.x, cnt);
   }
 }
 
@@ -516,13 +592,15 @@ hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t 
 }
 
 hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t block,
-                                hipStream_t s) {
-  const uint32_t grid = a.tiles * steps;
-  const size_t lds = (size_t)a.tile_size * sizeof(int32_t);
+                                uint32_t grid, hipStream_t s) {
+  // the schedule always fits when every step uses maximal ranges
+  const uint32_t floor_grid = steps * ((a.tiles + kMaxTileGroup - 1) / kMaxTileGroup);
+  if (grid < floor_grid) grid = floor_grid;
+  const size_t lds = (size_t)kMaxTileGroup * a.tile_size * sizeof(int32_t);
   switch (block) {
-    case 256: k_deliver_tiled<256><<<grid, 256, lds, s>>>(a); break;
-    case 512: k_deliver_tiled<512><<<grid, 512, lds, s>>>(a); break;
-    default: k_deliver_tiled<1024><<<grid, 1024, lds, s>>>(a); break;
+    case 256: k_deliver_tiled<256><<<grid, 256, lds, s>>>(a, steps); break;
+    case 512: k_deliver_tiled<512><<<grid, 512, lds, s>>>(a, steps); break;
+    default: k_deliver_tiled<1024><<<grid, 1024, lds, s>>>(a, steps); break;
   }
   return hipGetLastError();
 }

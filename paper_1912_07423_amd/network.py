@@ -43,21 +43,21 @@ class Network:
 
     Parameters beyond the spec: raster_steps (raster ring capacity), window (max
     steps per update launch; 0 = the delay), delivery ("auto" | "atomic" | "tiled"),
-    tiles (target tiles of the tiled delivery; 0 = auto), block (its workgroup size:
-    256 | 512 | 1024; 0 = auto), torch_memory (allocate
+    tiles (target base tiles of the tiled delivery; 0 = auto), block (its workgroup
+    size: 256 | 512 | 1024; 0 = auto), grid (its workgroups; 0 = auto), torch_memory (allocate
     through torch's caching allocator and run on torch's current stream).
     """
 
     def __init__(self, spec, raster_steps=1024, window=0, delivery="auto", tiles=0, block=0,
-                 torch_memory=True, device=0):
+                 grid=0, torch_memory=True, device=0):
         lib = L.load()
         self._lib = lib
         self._h = None
         prm = spec["params"]
         fields = {k: prm[k] for k, _ in L.PARAM_FIELDS
-                  if k not in ("raster_steps", "window", "delivery", "tiles", "block")}
+                  if k not in ("raster_steps", "window", "delivery", "tiles", "block", "grid")}
         p = L.Params(**fields, raster_steps=raster_steps, window=window,
-                     delivery=L.DELIVERY[delivery], tiles=tiles, block=block)
+                     delivery=L.DELIVERY[delivery], tiles=tiles, block=block, grid=grid)
         pops = (L.Population * len(spec["pops"]))(
             *[L.Population(q["size"], q.get("excitatory", 1)) for q in spec["pops"]])
         projs_in = spec.get("projs", [])
@@ -216,10 +216,12 @@ class Network:
     def reset_profile(self):
         L.check(self._lib.snn_reset_profile(self._h))
 
-    def time_delivery(self, ids, reps=10):
+    def time_delivery(self, ids, reps=10, steps=0):
+        """Mean time (ms) of one delivery launch over the given spike ids spread evenly over
+        `steps` emission steps (0: the network's window), and the events per launch."""
         ids = np.ascontiguousarray(ids, dtype=np.uint32)
         ms = C.c_double()
         ev = C.c_uint64()
-        L.check(self._lib.snn_time_delivery(self._h, _ptr(ids), len(ids), reps, C.byref(ms),
-                                            C.byref(ev)))
+        L.check(self._lib.snn_time_delivery(self._h, _ptr(ids), len(ids), steps, reps,
+                                            C.byref(ms), C.byref(ev)))
         return ms.value, ev.value

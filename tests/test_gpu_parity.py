@@ -123,7 +123,7 @@ def test_schedule_variants_identical(delivery, window):
 
 def test_tiled_tile_counts():
     spec = W.brunel_fixed_out(n=2500, k=250, delay_steps=15, steps=120)
-    for tiles in (1, 3, 17, 39):
+    for tiles in (1, 3, 17, 39, 120):
         print(f"[tiles] {tiles}", flush=True)
         _compare_run(spec, 120, delivery="tiled", tiles=tiles)
 
@@ -183,7 +183,7 @@ def test_time_delivery_counts_events():
     for delivery in ("atomic", "tiled"):
         g = _net(spec, delivery=delivery)
         ids = np.arange(0, 3000, 7, dtype=np.uint32)
-        ms, ev = g.time_delivery(ids, reps=3)
+        ms, ev = g.time_delivery(ids, reps=3, steps=1)
         assert ev == 200 * len(ids) and ms > 0
         assert g.t == 0 and g.events == 0
 
