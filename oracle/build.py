@@ -3,6 +3,8 @@
 gcc -O2 -ffp-contract=off: no fused multiply-add contraction and no fast-math, so
 binary32/binary64 arithmetic follows IEEE round-to-nearest-even operation by
 operation; the only fused operations are the explicit fma() calls of the logarithm.
+-fopenmp only spreads the independent rows of network construction over host threads;
+the simulation loop is single-threaded.
 """
 import os
 import subprocess
@@ -14,7 +16,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC",
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fopenmp", "-fPIC",
            "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", LIB + ".tmp"]
     cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
     if verbose:

@@ -288,12 +288,14 @@ orc_net *orc_create(const orc_params *prm, const orc_pop *pops, uint32_t n_pops,
     c->row_ptr = (uint64_t *)malloc(sizeof(uint64_t) * (n + 1));
     c->plast_lo = (uint64_t *)calloc(n, sizeof(uint64_t));
     c->plast_len = (uint32_t *)calloc(n, sizeof(uint32_t));
-    /* pass 1: row lengths */
+    /* pass 1: row lengths, then their prefix sum.  Rows are independent, so the row
+     * loops of both passes may run on several host threads (OpenMP) without changing
+     * a single result. */
     c->row_ptr[0] = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        int64_t len = orc_row_into(c, i, NULL, NULL, NULL, NULL, NULL, 0);
-        c->row_ptr[i + 1] = c->row_ptr[i] + (uint64_t)len;
-    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (uint32_t i = 0; i < n; ++i)
+        c->row_ptr[i + 1] = (uint64_t)orc_row_into(c, i, NULL, NULL, NULL, NULL, NULL, 0);
+    for (uint32_t i = 0; i < n; ++i) c->row_ptr[i + 1] += c->row_ptr[i];
     c->nnz = c->row_ptr[n];
     size_t alloc_nnz = c->nnz ? c->nnz : 1;
     c->col = (int32_t *)malloc(sizeof(int32_t) * alloc_nnz);
@@ -306,6 +308,7 @@ orc_net *orc_create(const orc_params *prm, const orc_pop *pops, uint32_t n_pops,
         return NULL;
     }
     /* pass 2: fill */
+#pragma omp parallel for schedule(dynamic, 64)
     for (uint32_t i = 0; i < n; ++i) {
         uint64_t b = c->row_ptr[i];
         int64_t len = (int64_t)(c->row_ptr[i + 1] - b);

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 from paper_1912_07423_amd import workloads as W
+from gpu_compare import bits as _bits, compare_run as _compare_run, net as _net
 
 pytestmark = pytest.mark.gpu
 
@@ -15,15 +16,6 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module", autouse=True)
 def _gpu(gpu_available):
     return gpu_available
-
-
-def _net(spec, **kw):
-    from paper_1912_07423_amd import Network
-    return Network(spec, **kw)
-
-
-def _bits(a):
-    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
 
 
 def _small_specs():
@@ -68,39 +60,6 @@ def test_initial_state_matches_oracle(name):
     s = g.state()
     assert np.array_equal(_bits(s["v"]), _bits(o.v()))
     assert not s["ref"].any() and not s["input"].any()
-
-
-def _compare_run(spec, steps, **kw):
-    g = _net(spec, raster_steps=steps, **kw)
-    o = oracle.OracleNet(spec, raster_cap=steps)
-    g.run(steps)
-    o.run(steps)
-    inf = g.info()
-    assert inf["t"] == steps
-    rg = g.raster_bits(0, steps)
-    ro = o.raster_words()[:steps]
-    if not np.array_equal(rg, ro):
-        bad = np.nonzero((rg != ro).any(axis=1))[0]
-        raise AssertionError(f"raster differs first at step {bad[0]} ({len(bad)} steps differ)")
-    s = g.state(weights=bool(inf["plastic"]))
-    assert np.array_equal(_bits(s["v"]), _bits(o.v()))
-    assert np.array_equal(s["ref"], o.ref())
-    assert np.array_equal(s["input"][steps % inf["input_buffers"]], o.input())
-    # events: out-degree sums over the delivered emission steps.  A spike of step e is
-    # delivered once the update of step e + d - B has run (B input buffers), so after
-    # T steps the GPU has delivered e < T - d + B and the oracle (B = 1) e < T - d + 1.
-    outdeg = np.diff(o.row_ptr().astype(np.int64))
-    spk = o.raster_bool(0, steps)
-    def delivered(upto):
-        return int(outdeg[np.nonzero(spk[:max(upto, 0)])[1]].sum())
-    assert o.events == delivered(steps - inf["delay"] + 1)
-    assert inf["events"] == delivered(steps - inf["delay"] + inf["input_buffers"])
-    if inf["plastic"]:
-        assert np.array_equal(_bits(s["x_pre"]), _bits(o.x_pre()))
-        assert np.array_equal(_bits(s["x_post"]), _bits(o.x_post()))
-        assert np.array_equal(_bits(s["w_f32"]), _bits(o.w_f32()))
-        assert inf["touches"] == o.touches
-    return rg, inf
 
 
 @pytest.mark.parametrize("name", list(_small_specs()))
