@@ -212,6 +212,124 @@ snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_
 void snn_destroy(snn_network *net);
 const char *snn_last_error(void);
 
+/* ---- Batched form: many independent static networks, one persistent launch -------
+ *
+ * Parameter sweeps and seed studies run hundreds of small networks of uneven size.
+ * One at a time they leave most of the GPU idle, so a batch steps all of them in one
+ * persistent kernel (captured in a HIP graph and replayed): each workgroup owns one
+ * network for the whole launch and runs its step pipeline (update, spike queue, delay
+ * ring, delivery) with the delay ring of Q16 accumulators in LDS.  Every network has
+ * exactly the semantics of snn_build_network + snn_run with the same parameters
+ * (same synapses, same spikes, same state). */
+typedef struct snn_batch snn_batch;
+
+typedef struct {
+    const snn_params *params;      /* raster_steps, window, delivery, tiles, block and
+                                      grid are ignored (the batch sets them) */
+    const snn_population *pops;
+    const snn_projection *proj;
+    uint32_t n_pops, n_proj;
+} snn_batch_member;
+
+/* Launch shape of the batch kernel, chosen by snn_batch_autotune or set by hand. */
+typedef struct {
+    uint32_t block;        /* workgroup size: 256, 512 or 1024 */
+    uint32_t per_lane;     /* neurons per lane (output; derived from block and the largest network) */
+    uint32_t degree_div;   /* lanes per spike = the power of two >= mean out-degree / degree_div,
+                              clamped to [1, 64]: 1, 2, 4, 8 or 16 */
+    uint32_t pad_;
+    double ms_per_step;    /* output of snn_batch_autotune: measured time of the chosen shape */
+} snn_batch_tuning;
+
+/* Build every member (validated and generated exactly as snn_build_network does) and
+ * the batch around them.  Members must be static (no plastic projection) and each
+ * must fit one workgroup: n <= 20,480 neurons (held in registers) and
+ * (delay * n + drive thresholds) * 4 bytes of delay ring within the workgroup LDS
+ * limit (160 KB on MI355X).  raster_steps is each member's raster ring.  Errors as
+ * snn_build_network; SNN_E_INVALID names the member that does not fit. */
+snn_status snn_build_batch(const snn_batch_member *nets, uint32_t n_nets, uint32_t raster_steps,
+                           const snn_allocator *alloc, void *stream, snn_batch **out);
+
+/* Advance every network of the batch by n_steps steps (asynchronous). */
+snn_status snn_batch_run(snn_batch *b, uint32_t n_steps);
+snn_status snn_batch_sync(snn_batch *b);
+
+/* Member k as a network handle owned by the batch: every reader (snn_get_info,
+ * snn_get_raster*, snn_get_state, snn_get_row, snn_get_synapses, ...) and
+ * snn_set_state work on it; snn_step, snn_run and snn_time_delivery return
+ * SNN_E_STATE, and snn_destroy ignores it. */
+snn_status snn_batch_network(snn_batch *b, uint32_t k, snn_network **net);
+
+/* Time each candidate launch shape (block 256/512/1024 x degree_div 1..16) over
+ * trial_steps steps from the current state without changing it (nothing is written
+ * back and no raster row is written), keep the fastest and return it. */
+snn_status snn_batch_autotune(snn_batch *b, uint32_t trial_steps, snn_batch_tuning *chosen);
+snn_status snn_batch_set_tuning(snn_batch *b, const snn_batch_tuning *tuning);
+snn_status snn_batch_get_tuning(snn_batch *b, snn_batch_tuning *tuning);
+
+void snn_batch_destroy(snn_batch *b);
+
+/* ---- Surrogate-gradient BPTT of a recurrent LIF network --------------------------
+ *
+ * Training needs gradients through spikes, which are discontinuous (Sec. I); this form
+ * replaces the spike's derivative by a fast-sigmoid surrogate.  Model, per batch
+ * element, steps t = 0 .. steps-1, with V, s, U zero before step 0:
+ *   I_t = W_in^T x_t + W_rec^T s_{t-1}            (sparse CSR weights, FP32)
+ *   V_t = beta V_{t-1} + I_t - theta s_{t-1}      (reset by subtraction)
+ *   s_t = H(V_t - theta)                          (smooth = 0; H(0) = 1)
+ *       = 1/2 + 1/2 a/(1+|a|), a = slope (V_t - theta)   (smooth = 1)
+ *   U_t = beta_out U_{t-1} + W_out^T s_t          (dense [n_hidden][n_out] readout)
+ *   loss = mean_b cross-entropy(max_t U_t[b], label_b)
+ * The backward pass is the adjoint recurrence of this model with
+ * d s/d V = 1/(1 + slope |V - theta|)^2 and the reset term detached (smooth = 0), or
+ * the exact derivative with the reset term (smooth = 1, for finite-difference checks).
+ * The forward keeps every step's s and the membrane state at the end of every
+ * `checkpoint` steps; the backward recomputes each segment's membranes from its
+ * checkpoint.  The current into neuron j sums its in-edges in ascending source order,
+ * input projection first, one term at a time; the readout sums ascending; the maximum
+ * over time is taken at its first step. */
+typedef struct snn_bptt snn_bptt;
+
+typedef struct {
+    uint32_t batch;        /* 1..64 */
+    uint32_t steps, n_in, n_hidden, n_out;
+    uint32_t checkpoint;   /* steps per checkpoint segment, 1..32 */
+    float beta, beta_out, theta, slope;
+    uint32_t smooth;       /* 0: spiking forward, surrogate backward; 1: smooth forward */
+    uint32_t pad_;
+} snn_bptt_desc;
+
+/* A plan for one network structure: host CSR arrays (rows = presynaptic neuron, targets
+ * strictly ascending) of the input (n_in rows, targets < n_hidden) and recurrent
+ * (n_hidden rows) weights.  The plan owns its device workspace; weights are passed to
+ * each call.  SNN_E_INVALID for invalid sizes or CSR arrays. */
+snn_status snn_bptt_create(const snn_bptt_desc *desc, const uint64_t *in_row_ptr, const int32_t *in_col,
+                           const uint64_t *rec_row_ptr, const int32_t *rec_col,
+                           const snn_allocator *alloc, void *stream, snn_bptt **out);
+
+/* Forward pass on device arrays: x [batch][steps][n_in] (0/1), w_in [nnz_in] and
+ * w_rec [nnz_rec] in CSR order, w_out [n_hidden][n_out], labels [batch] int32 in
+ * [0, n_out); writes the mean loss to *loss (device).  Asynchronous on `stream`
+ * (NULL: the plan's stream).  The plan keeps the trajectory for the next backward. */
+snn_status snn_bptt_forward(snn_bptt *p, const float *x, const float *w_in, const float *w_rec,
+                            const float *w_out, const int32_t *labels, float *loss, void *stream);
+
+/* Backward pass of the latest forward pass (same weights): writes dloss/dw_in [nnz_in],
+ * dloss/dw_rec [nnz_rec] and dloss/dw_out [n_hidden][n_out] (device), each scaled by
+ * *g_loss (device scalar; NULL = 1).  SNN_E_STATE before any forward pass. */
+snn_status snn_bptt_backward(snn_bptt *p, const float *w_in, const float *w_rec, const float *w_out,
+                             const float *g_loss, float *g_w_in, float *g_w_rec, float *g_w_out,
+                             void *stream);
+
+/* Host copies of the latest forward pass (any pointer may be NULL): spikes
+ * [steps][n_hidden][64] (batch innermost, lanes >= batch unused), membrane checkpoints
+ * [ceil(steps/checkpoint)][n_hidden][64], readout maxima and their steps
+ * [batch][n_out].  Synchronises the stream. */
+snn_status snn_bptt_get_trace(snn_bptt *p, float *spikes, float *v_checkpoints, float *readout_max,
+                              int32_t *readout_argmax, void *stream);
+
+void snn_bptt_destroy(snn_bptt *p);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,16 +2,20 @@
 (Bautembach et al., "Faster and Simpler SNN Simulation with Work Queues").
 
 The simulation runs in hand-written HIP kernels behind the C ABI of include/snn.h
-(libsnn.so); `Network` is its Python binding.  `workloads` holds the synthetic
-network descriptions.
+(libsnn.so); `Network` (one network) and `Batch` (many independent networks in one
+persistent launch) are its Python binding.  `workloads` holds the synthetic network
+descriptions.
 """
-__all__ = ["Network", "SnnError", "library_path"]
+__all__ = ["Network", "Batch", "SnnError", "library_path"]
 
 
 def __getattr__(name):
     if name == "Network":
         from .network import Network
         return Network
+    if name == "Batch":
+        from .network import Batch
+        return Batch
     if name == "SnnError":
         from ._lib import SnnError
         return SnnError

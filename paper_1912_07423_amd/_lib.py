@@ -81,6 +81,23 @@ class Profile(C.Structure):
                 ("stdp_launches", C.c_uint64)]
 
 
+class BatchMember(C.Structure):
+    _fields_ = [("params", C.POINTER(Params)), ("pops", C.POINTER(Population)),
+                ("proj", C.POINTER(Projection)), ("n_pops", C.c_uint32), ("n_proj", C.c_uint32)]
+
+
+class BatchTuning(C.Structure):
+    _fields_ = [("block", C.c_uint32), ("per_lane", C.c_uint32), ("degree_div", C.c_uint32),
+                ("pad_", C.c_uint32), ("ms_per_step", C.c_double)]
+
+
+class BpttDesc(C.Structure):
+    _fields_ = [("batch", C.c_uint32), ("steps", C.c_uint32), ("n_in", C.c_uint32),
+                ("n_hidden", C.c_uint32), ("n_out", C.c_uint32), ("checkpoint", C.c_uint32),
+                ("beta", C.c_float), ("beta_out", C.c_float), ("theta", C.c_float),
+                ("slope", C.c_float), ("smooth", C.c_uint32), ("pad_", C.c_uint32)]
+
+
 # every symbol declared in include/snn.h, with its ctypes signature
 SIGNATURES = {
     "snn_build_network": (C.c_int32, [C.POINTER(Params), C.POINTER(Population), C.c_uint32,
@@ -106,6 +123,22 @@ SIGNATURES = {
                                       C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "snn_destroy": (None, [C.c_void_p]),
     "snn_last_error": (C.c_char_p, []),
+    "snn_build_batch": (C.c_int32, [C.POINTER(BatchMember), C.c_uint32, C.c_uint32,
+                                    C.POINTER(Allocator), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "snn_batch_run": (C.c_int32, [C.c_void_p, C.c_uint32]),
+    "snn_batch_sync": (C.c_int32, [C.c_void_p]),
+    "snn_batch_network": (C.c_int32, [C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p)]),
+    "snn_batch_autotune": (C.c_int32, [C.c_void_p, C.c_uint32, C.POINTER(BatchTuning)]),
+    "snn_batch_set_tuning": (C.c_int32, [C.c_void_p, C.POINTER(BatchTuning)]),
+    "snn_batch_get_tuning": (C.c_int32, [C.c_void_p, C.POINTER(BatchTuning)]),
+    "snn_batch_destroy": (None, [C.c_void_p]),
+    "snn_bptt_create": (C.c_int32, [C.POINTER(BpttDesc), C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.POINTER(Allocator), C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
+    "snn_bptt_forward": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 6 + [C.c_void_p]),
+    "snn_bptt_backward": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 7 + [C.c_void_p]),
+    "snn_bptt_get_trace": (C.c_int32, [C.c_void_p] + [C.c_void_p] * 4 + [C.c_void_p]),
+    "snn_bptt_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None

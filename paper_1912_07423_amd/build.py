@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsnn.so")
-SOURCES = ["generate.hip", "step.hip", "runtime.cpp"]
+SOURCES = ["generate.hip", "step.hip", "batch.hip", "bptt.hip", "runtime.cpp"]
 ARCH = os.environ.get("SNN_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unused-result",
          f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -94,4 +94,45 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
+// Constants of the LIF update (Sec. IV: current-based LIF), derived once on the host.
+struct LifConst {
+  float alpha;      // fl32(exp(-dt / tau_m))
+  float v_inf;      // fl32(V_rest + V_bg)
+  float v_th, v_reset;
+  int32_t ref_steps;
+  int32_t w_ext_q16;  // Q16 weight of one virtual drive input
+};
+
+// One neuron, one step, in binary32 without contraction and in this order: a
+// refractory neuron counts down and discards its input; otherwise the Q16 input plus
+// k drive inputs (int32, wrapping) is added to V, V leaks towards v_inf by alpha, and
+// V >= V_th emits a spike, resets V and starts the refractory count.  Returns the spike.
+__device__ __forceinline__ bool lif_advance(float &v, int32_t &ref, int32_t input, int32_t k,
+                                            const LifConst &c) {
+  if (ref > 0) {
+    ref -= 1;
+    return false;
+  }
+  const uint32_t sum = (uint32_t)input + (uint32_t)k * (uint32_t)c.w_ext_q16;
+  const float dv = (float)(int32_t)sum * 0x1p-16f;
+  float vv = v + dv;
+  const float diff = vv - c.v_inf;
+  const float leak = diff * c.alpha;
+  vv = c.v_inf + leak;
+  const bool spike = vv >= c.v_th;
+  if (spike) {
+    vv = c.v_reset;
+    ref = c.ref_steps;
+  }
+  v = vv;
+  return spike;
+}
+
+// Word u (0..3) of a Philox block by selects, never by a dynamic register index.
+__device__ __forceinline__ uint32_t word_of(const Words4 &r, uint32_t u) {
+  const uint32_t lo = (u & 1u) ? r.w[1] : r.w[0];
+  const uint32_t hi = (u & 1u) ? r.w[3] : r.w[2];
+  return (u & 2u) ? hi : lo;
+}
+
 }  // namespace snn

@@ -30,6 +30,10 @@ void check(hipError_t e, const char *what) {
   if (e != hipSuccess) fail(SNN_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+void refuse_member(const snn_network *net) {
+  if (net->owner) fail(SNN_E_STATE, "this network belongs to a batch: advance it with snn_batch_run");
+}
+
 template <typename F>
 snn_status guarded(F &&f) {
   try {
@@ -248,13 +252,15 @@ void choose_delivery(snn_network *net) {
     const uint32_t b = net->prm.block;
     if (b != 0 && b != 256 && b != 512 && b != 1024) fail(SNN_E_INVALID, "block must be 256, 512 or 1024");
     net->block = b ? b : 512;
-    // base tiles of at most kMaxRange / kTileGroupMax targets, so that a workgroup's
-    // range of up to kTileGroupMax base tiles (48 KB) plus its scan arrays fit the
-    // 64 KB a workgroup may allocate
-    constexpr uint32_t kMaxRange = 12288;
-    const uint32_t tile_cap = kMaxRange / snn::kTileGroupMax;
+    // A workgroup accumulates a range of up to kTileGroupMax base tiles in LDS.  The
+    // largest base tile is set by the workgroup LDS limit (160 KB on gfx950, less the
+    // kernel's static arrays); the default base tile is kDefaultTile targets.
+    size_t lds_dyn = 0;
+    check(snn::prepare_deliver_tiled(net->block, &lds_dyn), "tiled delivery LDS limit");
+    const uint32_t tile_cap = (uint32_t)(lds_dyn / 4 / snn::kTileGroupMax);
+    constexpr uint32_t kDefaultTile = 3072;
     const uint32_t min_tiles = (net->n + tile_cap - 1) / tile_cap;
-    uint32_t tiles = net->prm.tiles ? net->prm.tiles : min_tiles;
+    uint32_t tiles = net->prm.tiles ? net->prm.tiles : (net->n + kDefaultTile - 1) / kDefaultTile;
     tiles = std::max(std::min(tiles, std::max(1u, net->n / 16u)), min_tiles);
     net->tile_size = (net->n + tiles - 1) / tiles;
     net->tiles = (net->n + net->tile_size - 1) / net->tile_size;
@@ -665,6 +671,347 @@ void copy_raster_rows(snn_network *net, uint64_t t0, uint64_t t1, uint64_t *out)
   sync(net);
 }
 
+
+// ---- batched form ----------------------------------------------------------------
+}  // namespace
+
+struct snn_batch {
+  std::vector<snn_network *> nets;
+  snn_network pool;                  // holds the batch's own allocations and stream
+  std::vector<snn::BatchNet> desc;
+  std::vector<double> degree;        // mean out-degree of each member
+  std::vector<uint32_t> order;       // workgroup -> member, heaviest first
+  snn::BatchNet *d_desc = nullptr;
+  uint32_t *d_order = nullptr;
+  uint32_t n_max = 0;
+  size_t lds_need = 0;               // dynamic LDS of the largest member
+  uint32_t lds_limit = 0;
+  snn_batch_tuning tuning{};
+  std::vector<std::pair<uint32_t, hipGraphExec_t>> graphs;  // by steps per launch
+};
+
+namespace {
+
+uint32_t lanes_shift_for(double degree, uint32_t degree_div) {
+  const double want = degree / (double)std::max(1u, degree_div);
+  uint32_t sh = 0;
+  while (sh < 6 && (double)(1u << sh) < want) ++sh;
+  return sh;
+}
+
+void batch_clear_graphs(snn_batch *b) {
+  for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  b->graphs.clear();
+}
+
+void batch_apply_tuning(snn_batch *b, const snn_batch_tuning &t) {
+  if (t.block != 256 && t.block != 512 && t.block != 1024) fail(SNN_E_INVALID, "block must be 256, 512 or 1024");
+  if (t.degree_div != 1 && t.degree_div != 2 && t.degree_div != 4 && t.degree_div != 8 && t.degree_div != 16)
+    fail(SNN_E_INVALID, "degree_div must be 1, 2, 4, 8 or 16");
+  const uint32_t per = snn::batch_per_lane(t.block, b->n_max);
+  if (per == 0) fail(SNN_E_INVALID, "largest network does not fit a workgroup of this size");
+  for (size_t k = 0; k < b->desc.size(); ++k) b->desc[k].lanes_shift = lanes_shift_for(b->degree[k], t.degree_div);
+  check(hipMemcpyAsync(b->d_desc, b->desc.data(), b->desc.size() * sizeof(snn::BatchNet), hipMemcpyHostToDevice,
+                       b->pool.stream), "copy batch descriptors");
+  check(hipStreamSynchronize(b->pool.stream), "sync");
+  b->tuning = t;
+  b->tuning.per_lane = per;
+  b->tuning.pad_ = 0;
+  batch_clear_graphs(b);
+}
+
+void batch_launch(snn_batch *b, uint32_t steps, uint32_t flags) {
+  check(snn::launch_batch(b->d_desc, b->d_order, (uint32_t)b->nets.size(), steps, b->tuning.block,
+                          b->tuning.per_lane, flags, b->lds_need, b->pool.stream), "batch launch");
+}
+
+hipGraphExec_t batch_graph(snn_batch *b, uint32_t steps) {
+  for (auto &g : b->graphs)
+    if (g.first == steps) return g.second;
+  hipGraph_t g = nullptr;
+  hipStream_t s = b->pool.stream;
+  check(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "begin capture");
+  try {
+    batch_launch(b, steps, snn::kBatchCommit | snn::kBatchWriteRaster);
+  } catch (...) {
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  check(hipStreamEndCapture(s, &g), "end capture");
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  check(e, "graph instantiate");
+  if (b->graphs.size() >= 8) batch_clear_graphs(b);
+  b->graphs.push_back({steps, ex});
+  return ex;
+}
+
+// Each launch advances every member by `chunk` steps; one kernel node per launch,
+// replayed from a graph captured once per chunk length.
+void batch_run(snn_batch *b, uint64_t n_steps) {
+  constexpr uint32_t kMaxChunk = 1u << 14;
+  while (n_steps > 0) {
+    const uint32_t chunk = (uint32_t)std::min<uint64_t>(n_steps, kMaxChunk);
+    check(hipGraphLaunch(batch_graph(b, chunk), b->pool.stream), "graph launch");
+    for (snn_network *m : b->nets) m->t_host += chunk;
+    n_steps -= chunk;
+  }
+}
+
+void batch_destroy(snn_batch *b) {
+  if (b->pool.stream) (void)hipStreamSynchronize(b->pool.stream);
+  batch_clear_graphs(b);
+  for (snn_network *m : b->nets) {
+    m->owner = nullptr;
+    m->own_stream = false;  // the stream belongs to the pool
+    release(m);
+    delete m;
+  }
+  b->nets.clear();
+  release(&b->pool);
+}
+
+void build_batch(snn_batch *b, const snn_batch_member *members, uint32_t n_nets, uint32_t raster_steps) {
+  hipStream_t s = b->pool.stream;
+  int lds_max = 0;
+  check(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->pool.device),
+        "LDS limit");
+  b->lds_limit = (uint32_t)std::max(0, lds_max - 64);  // the kernel's static LDS
+  for (uint32_t k = 0; k < n_nets; ++k) {
+    const snn_batch_member &mb = members[k];
+    if (!mb.params || (!mb.pops && mb.n_pops) || (!mb.proj && mb.n_proj))
+      fail(SNN_E_INVALID, "member " + std::to_string(k) + ": null argument");
+    snn_network *m = new snn_network();
+    b->nets.push_back(m);
+    m->owner = b;
+    m->prm = *mb.params;
+    m->prm.raster_steps = raster_steps;
+    m->prm.window = 0;
+    m->prm.delivery = SNN_DELIVERY_ATOMIC;
+    m->prm.tiles = m->prm.block = m->prm.grid = 0;
+    m->pops.assign(mb.pops, mb.pops + mb.n_pops);
+    m->proj.assign(mb.proj, mb.proj + mb.n_proj);
+    m->alloc = b->pool.alloc;
+    m->has_alloc = b->pool.has_alloc;
+    m->device = b->pool.device;
+    m->cu_count = b->pool.cu_count;
+    m->stream = s;
+    try {
+      build(m);
+    } catch (const Failure &f) {
+      fail(f.code, "member " + std::to_string(k) + ": " + f.msg);
+    }
+    if (m->plastic) fail(SNN_E_INVALID, "member " + std::to_string(k) + ": the batched form needs static weights");
+    if (m->n_inbuf != m->delay) fail(SNN_E_INVALID, "member " + std::to_string(k) + ": unexpected input ring");
+    uint32_t below = 0;
+    while (below < m->table_len && m->table[below] < (1ull << 32)) ++below;
+    const size_t lds = ((size_t)m->delay * m->n + below) * 4;
+    if (m->n > 20480 || lds > b->lds_limit)
+      fail(SNN_E_INVALID, "member " + std::to_string(k) + " does not fit one workgroup (n = " + std::to_string(m->n) +
+                              ", delay ring + drive table = " + std::to_string(lds) + " bytes of LDS, limit " +
+                              std::to_string(b->lds_limit) + ")");
+    b->lds_need = std::max(b->lds_need, (lds + 15) & ~(size_t)15);
+    b->n_max = std::max(b->n_max, m->n);
+    snn::BatchNet d{};
+    d.row_ptr = m->row_ptr;
+    d.col = m->col;
+    d.w_q16 = m->w_q16;
+    d.v = m->v;
+    d.ref = m->ref;
+    d.input = m->input;
+    d.queue = m->queue;
+    d.raster = m->raster;
+    d.table32 = m->d_table32;
+    d.ctl = m->ctl;
+    d.n = m->n;
+    d.words = m->words;
+    d.delay = m->delay;
+    d.raster_cap = m->raster_cap;
+    d.below = below;
+    d.key0 = m->key0;
+    d.key1 = m->key1;
+    d.alpha = m->alpha;
+    d.v_inf = m->v_inf;
+    d.v_th = m->v_th;
+    d.v_reset = m->v_reset;
+    d.ref_steps = m->ref_steps;
+    d.w_ext_q16 = m->w_ext_q16;
+    b->desc.push_back(d);
+    b->degree.push_back(m->n ? (double)m->nnz / m->n : 0.0);
+  }
+  // heaviest networks first: the first workgroups start first and get a CU each
+  std::vector<double> work(n_nets);
+  for (uint32_t k = 0; k < n_nets; ++k) work[k] = (double)b->nets[k]->nnz + 8.0 * b->nets[k]->n;
+  b->order.resize(n_nets);
+  std::iota(b->order.begin(), b->order.end(), 0u);
+  std::stable_sort(b->order.begin(), b->order.end(), [&](uint32_t x, uint32_t y) { return work[x] > work[y]; });
+  b->d_desc = dev_array<snn::BatchNet>(&b->pool, std::max<size_t>(1, n_nets));
+  b->d_order = dev_array<uint32_t>(&b->pool, std::max<size_t>(1, n_nets));
+  check(hipMemcpyAsync(b->d_order, b->order.data(), n_nets * 4, hipMemcpyHostToDevice, s), "copy order");
+  snn_batch_tuning t{};
+  t.degree_div = 4;
+  t.block = 256;
+  for (uint32_t blk : {512u, 1024u, 256u})
+    if (snn::batch_per_lane(blk, b->n_max)) {
+      t.block = blk;
+      break;
+    }
+  batch_apply_tuning(b, t);
+}
+
+snn_batch_tuning batch_autotune(snn_batch *b, uint32_t trial_steps) {
+  if (trial_steps == 0) fail(SNN_E_INVALID, "trial_steps must be positive");
+  hipStream_t s = b->pool.stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  check(hipEventCreate(&e0), "event");
+  check(hipEventCreate(&e1), "event");
+  snn_batch_tuning best{};
+  double best_ms = 1e300;
+  try {
+    for (uint32_t blk : {256u, 512u, 1024u}) {
+      if (!snn::batch_per_lane(blk, b->n_max)) continue;
+      for (uint32_t div : {1u, 2u, 4u, 8u, 16u}) {
+        snn_batch_tuning t{};
+        t.block = blk;
+        t.degree_div = div;
+        batch_apply_tuning(b, t);
+        batch_launch(b, trial_steps, 0u);  // warm-up
+        check(hipEventRecord(e0, s), "event record");
+        batch_launch(b, trial_steps, 0u);
+        check(hipEventRecord(e1, s), "event record");
+        check(hipEventSynchronize(e1), "event sync");
+        float ms = 0.f;
+        check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = b->tuning;
+        }
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  batch_apply_tuning(b, best);
+  b->tuning.ms_per_step = best_ms / trial_steps;
+  return b->tuning;
+}
+
+
+// ---- surrogate-gradient BPTT plan ------------------------------------------------
+}  // namespace
+
+struct snn_bptt {
+  snn_bptt_desc desc{};
+  snn_network pool;          // holds the plan's allocations and default stream
+  snn::BpttArgs args{};
+  uint64_t forwards = 0;     // forward passes run (the backward uses the latest)
+};
+
+namespace {
+
+// Transposed index of a CSR matrix with `rows` rows and `cols` columns: for each
+// column, its (row, edge) pairs in ascending row order (a counting sort over rows).
+void transpose_csr(const uint64_t *ptr, const int32_t *col, uint32_t rows, uint32_t cols,
+                   std::vector<uint64_t> &t_ptr, std::vector<int32_t> &t_src, std::vector<uint32_t> &t_edge) {
+  const uint64_t nnz = ptr[rows];
+  t_ptr.assign((size_t)cols + 1, 0);
+  for (uint64_t e = 0; e < nnz; ++e) t_ptr[(size_t)col[e] + 1]++;
+  for (uint32_t c = 0; c < cols; ++c) t_ptr[c + 1] += t_ptr[c];
+  std::vector<uint64_t> fill(t_ptr.begin(), t_ptr.end() - 1);
+  t_src.assign(nnz ? nnz : 1, 0);
+  t_edge.assign(nnz ? nnz : 1, 0);
+  for (uint32_t r = 0; r < rows; ++r)
+    for (uint64_t e = ptr[r]; e < ptr[r + 1]; ++e) {
+      const uint64_t at = fill[(size_t)col[e]]++;
+      t_src[at] = (int32_t)r;
+      t_edge[at] = (uint32_t)e;
+    }
+}
+
+void check_csr(const uint64_t *ptr, const int32_t *col, uint32_t rows, uint32_t cols, uint64_t nnz,
+               const char *what) {
+  if (!ptr || (!col && nnz)) fail(SNN_E_INVALID, std::string(what) + ": null CSR array");
+  if (ptr[0] != 0 || ptr[rows] != nnz) fail(SNN_E_INVALID, std::string(what) + ": row pointers do not span nnz");
+  if (nnz >= (1ull << 32)) fail(SNN_E_INVALID, std::string(what) + ": more than 2^32 - 1 synapses");
+  for (uint32_t r = 0; r < rows; ++r) {
+    if (ptr[r + 1] < ptr[r]) fail(SNN_E_INVALID, std::string(what) + ": decreasing row pointers");
+    for (uint64_t e = ptr[r]; e < ptr[r + 1]; ++e) {
+      if (col[e] < 0 || (uint32_t)col[e] >= cols) fail(SNN_E_INVALID, std::string(what) + ": target out of range");
+      if (e > ptr[r] && col[e] <= col[e - 1]) fail(SNN_E_INVALID, std::string(what) + ": row not strictly ascending");
+    }
+  }
+}
+
+template <typename T>
+T *upload(snn_network *pool, const std::vector<T> &v) {
+  T *d = dev_array<T>(pool, std::max<size_t>(1, v.size()));
+  if (!v.empty())
+    check(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, pool->stream), "upload");
+  return d;
+}
+
+void build_bptt(snn_bptt *p, const uint64_t *in_ptr, const int32_t *in_col, const uint64_t *rec_ptr,
+                const int32_t *rec_col) {
+  const snn_bptt_desc &d = p->desc;
+  if (d.batch < 1 || d.batch > 64) fail(SNN_E_INVALID, "batch must be 1..64");
+  if (d.steps < 1 || d.n_in < 1 || d.n_hidden < 1 || d.n_out < 1) fail(SNN_E_INVALID, "empty dimension");
+  if (d.checkpoint < 1 || d.checkpoint > 32) fail(SNN_E_INVALID, "checkpoint interval must be 1..32");
+  if (d.n_out > 1024) fail(SNN_E_INVALID, "at most 1024 readouts");
+  if (!(d.slope > 0.f) || !(d.beta >= 0.f) || !(d.beta_out >= 0.f)) fail(SNN_E_INVALID, "invalid constants");
+  const uint64_t nnz_in = in_ptr ? in_ptr[d.n_in] : 0, nnz_rec = rec_ptr ? rec_ptr[d.n_hidden] : 0;
+  check_csr(in_ptr, in_col, d.n_in, d.n_hidden, nnz_in, "input weights");
+  check_csr(rec_ptr, rec_col, d.n_hidden, d.n_hidden, nnz_rec, "recurrent weights");
+  std::vector<uint64_t> it_ptr, rt_ptr;
+  std::vector<int32_t> it_src, rt_src;
+  std::vector<uint32_t> it_edge, rt_edge;
+  transpose_csr(in_ptr, in_col, d.n_in, d.n_hidden, it_ptr, it_src, it_edge);
+  transpose_csr(rec_ptr, rec_col, d.n_hidden, d.n_hidden, rt_ptr, rt_src, rt_edge);
+  snn::BpttArgs &a = p->args;
+  snn_network *pool = &p->pool;
+  a.B = d.batch;
+  a.T = d.steps;
+  a.C = d.n_in;
+  a.H = d.n_hidden;
+  a.O = d.n_out;
+  a.K = d.checkpoint;
+  a.beta = d.beta;
+  a.beta_out = d.beta_out;
+  a.theta = d.theta;
+  a.slope = d.slope;
+  a.smooth = d.smooth ? 1u : 0u;
+  a.detach_reset = d.smooth ? 0u : 1u;
+  a.nnz_in = nnz_in;
+  a.nnz_rec = nnz_rec;
+  a.in_t_ptr = upload(pool, it_ptr);
+  a.in_t_src = upload(pool, it_src);
+  a.in_t_edge = upload(pool, it_edge);
+  a.rec_t_ptr = upload(pool, rt_ptr);
+  a.rec_t_src = upload(pool, rt_src);
+  a.rec_t_edge = upload(pool, rt_edge);
+  a.rec_ptr = upload(pool, std::vector<uint64_t>(rec_ptr, rec_ptr + d.n_hidden + 1));
+  a.rec_col = upload(pool, std::vector<int32_t>(rec_col, rec_col + nnz_rec));
+  const size_t HB = (size_t)a.H * 64, n_seg = (a.T + a.K - 1) / a.K;
+  a.xt = dev_array<float>(pool, (size_t)a.T * a.C * 64);
+  a.s = dev_array<float>(pool, (size_t)a.T * HB);
+  a.vck = dev_array<float>(pool, n_seg * HB);
+  a.vtmp = dev_array<float>(pool, 2 * HB);
+  a.vseg = dev_array<float>(pool, (size_t)a.K * HB);
+  a.ro = dev_array<float>(pool, (size_t)a.T * a.O * 64);
+  a.lamu = dev_array<float>(pool, (size_t)a.T * a.O * 64);
+  a.lamv = dev_array<float>(pool, (size_t)a.K * HB);
+  a.lam_carry = dev_array<float>(pool, HB);
+  a.m = dev_array<float>(pool, (size_t)a.B * a.O);
+  a.dm = dev_array<float>(pool, (size_t)a.B * a.O);
+  a.tmax = dev_array<int32_t>(pool, (size_t)a.B * a.O);
+  check(hipStreamSynchronize(pool->stream), "sync after plan");
+}
+
 }  // namespace
 
 extern "C" {
@@ -707,6 +1054,7 @@ snn_status snn_build_network(const snn_params *prm, const snn_population *pops, 
 snn_status snn_step(snn_network *net) {
   return guarded([&] {
     if (!net) fail(SNN_E_INVALID, "null network");
+    refuse_member(net);
     issue_window(net, 1);
   });
 }
@@ -714,6 +1062,7 @@ snn_status snn_step(snn_network *net) {
 snn_status snn_run(snn_network *net, uint32_t n_steps) {
   return guarded([&] {
     if (!net) fail(SNN_E_INVALID, "null network");
+    refuse_member(net);
     run(net, n_steps);
   });
 }
@@ -920,6 +1269,7 @@ snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_
                              uint32_t steps, uint32_t reps, double *avg_ms, uint64_t *events) {
   return guarded([&] {
     if (!net || (!ids_host && n_ids) || !avg_ms) fail(SNN_E_INVALID, "null argument");
+    refuse_member(net);
     if (steps == 0) steps = net->window;
     if (steps > net->window) fail(SNN_E_INVALID, "steps exceeds the network's window");
     if (n_ids > (uint64_t)net->n * steps) fail(SNN_E_INVALID, "more ids than the queues hold");
@@ -978,7 +1328,7 @@ snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_
 }
 
 void snn_destroy(snn_network *net) {
-  if (!net) return;
+  if (!net || net->owner) return;
   try {
     resolve_profile(net);
   } catch (...) {
@@ -988,5 +1338,175 @@ void snn_destroy(snn_network *net) {
 }
 
 const char *snn_last_error(void) { return g_error.c_str(); }
+
+snn_status snn_build_batch(const snn_batch_member *nets, uint32_t n_nets, uint32_t raster_steps,
+                           const snn_allocator *alloc, void *stream, snn_batch **out) {
+  return guarded([&] {
+    if (!out || (!nets && n_nets)) fail(SNN_E_INVALID, "null argument");
+    *out = nullptr;
+    if (n_nets == 0) fail(SNN_E_INVALID, "a batch needs at least one network");
+    snn_batch *b = new snn_batch();
+    try {
+      if (alloc && alloc->alloc && alloc->free) {
+        b->pool.alloc = *alloc;
+        b->pool.has_alloc = true;
+      }
+      check(hipGetDevice(&b->pool.device), "hipGetDevice");
+      hipDeviceProp_t props;
+      check(hipGetDeviceProperties(&props, b->pool.device), "hipGetDeviceProperties");
+      b->pool.cu_count = (uint32_t)std::max(1, props.multiProcessorCount);
+      if (stream) {
+        b->pool.stream = (hipStream_t)stream;
+      } else {
+        check(hipStreamCreateWithFlags(&b->pool.stream, hipStreamNonBlocking), "hipStreamCreate");
+        b->pool.own_stream = true;
+      }
+      build_batch(b, nets, n_nets, raster_steps);
+    } catch (...) {
+      batch_destroy(b);
+      delete b;
+      throw;
+    }
+    *out = b;
+  });
+}
+
+snn_status snn_batch_run(snn_batch *b, uint32_t n_steps) {
+  return guarded([&] {
+    if (!b) fail(SNN_E_INVALID, "null batch");
+    batch_run(b, n_steps);
+  });
+}
+
+snn_status snn_batch_sync(snn_batch *b) {
+  return guarded([&] {
+    if (!b) fail(SNN_E_INVALID, "null batch");
+    check(hipStreamSynchronize(b->pool.stream), "stream sync");
+  });
+}
+
+snn_status snn_batch_network(snn_batch *b, uint32_t k, snn_network **net) {
+  return guarded([&] {
+    if (!b || !net) fail(SNN_E_INVALID, "null argument");
+    if (k >= b->nets.size()) fail(SNN_E_INVALID, "member index out of range");
+    *net = b->nets[k];
+  });
+}
+
+snn_status snn_batch_autotune(snn_batch *b, uint32_t trial_steps, snn_batch_tuning *chosen) {
+  return guarded([&] {
+    if (!b) fail(SNN_E_INVALID, "null batch");
+    const snn_batch_tuning t = batch_autotune(b, trial_steps);
+    if (chosen) *chosen = t;
+  });
+}
+
+snn_status snn_batch_set_tuning(snn_batch *b, const snn_batch_tuning *tuning) {
+  return guarded([&] {
+    if (!b || !tuning) fail(SNN_E_INVALID, "null argument");
+    check(hipStreamSynchronize(b->pool.stream), "stream sync");
+    batch_apply_tuning(b, *tuning);
+  });
+}
+
+snn_status snn_batch_get_tuning(snn_batch *b, snn_batch_tuning *tuning) {
+  return guarded([&] {
+    if (!b || !tuning) fail(SNN_E_INVALID, "null argument");
+    *tuning = b->tuning;
+  });
+}
+
+void snn_batch_destroy(snn_batch *b) {
+  if (!b) return;
+  batch_destroy(b);
+  delete b;
+}
+
+snn_status snn_bptt_create(const snn_bptt_desc *desc, const uint64_t *in_row_ptr, const int32_t *in_col,
+                           const uint64_t *rec_row_ptr, const int32_t *rec_col, const snn_allocator *alloc,
+                           void *stream, snn_bptt **out) {
+  return guarded([&] {
+    if (!desc || !out || !in_row_ptr || !rec_row_ptr) fail(SNN_E_INVALID, "null argument");
+    *out = nullptr;
+    snn_bptt *p = new snn_bptt();
+    try {
+      p->desc = *desc;
+      if (alloc && alloc->alloc && alloc->free) {
+        p->pool.alloc = *alloc;
+        p->pool.has_alloc = true;
+      }
+      check(hipGetDevice(&p->pool.device), "hipGetDevice");
+      if (stream) {
+        p->pool.stream = (hipStream_t)stream;
+      } else {
+        check(hipStreamCreateWithFlags(&p->pool.stream, hipStreamNonBlocking), "hipStreamCreate");
+        p->pool.own_stream = true;
+      }
+      build_bptt(p, in_row_ptr, in_col, rec_row_ptr, rec_col);
+    } catch (...) {
+      release(&p->pool);
+      delete p;
+      throw;
+    }
+    *out = p;
+  });
+}
+
+snn_status snn_bptt_forward(snn_bptt *p, const float *x, const float *w_in, const float *w_rec,
+                            const float *w_out, const int32_t *labels, float *loss, void *stream) {
+  return guarded([&] {
+    if (!p || !x || !w_out || !labels || !loss || (!w_in && p->args.nnz_in) || (!w_rec && p->args.nnz_rec))
+      fail(SNN_E_INVALID, "null argument");
+    snn::BpttArgs a = p->args;
+    a.w_in = w_in;
+    a.w_rec = w_rec;
+    a.w_out = w_out;
+    hipStream_t s = stream ? (hipStream_t)stream : p->pool.stream;
+    check(snn::bptt_forward(a, x, labels, loss, s), "bptt forward");
+    p->forwards++;
+  });
+}
+
+snn_status snn_bptt_backward(snn_bptt *p, const float *w_in, const float *w_rec, const float *w_out,
+                             const float *g_loss, float *g_w_in, float *g_w_rec, float *g_w_out,
+                             void *stream) {
+  return guarded([&] {
+    if (!p || !w_out || !g_w_out || (!w_in && p->args.nnz_in) || (!w_rec && p->args.nnz_rec) ||
+        (!g_w_in && p->args.nnz_in) || (!g_w_rec && p->args.nnz_rec))
+      fail(SNN_E_INVALID, "null argument");
+    if (p->forwards == 0) fail(SNN_E_STATE, "backward before any forward pass");
+    snn::BpttArgs a = p->args;
+    a.w_in = w_in;
+    a.w_rec = w_rec;
+    a.w_out = w_out;
+    a.g_w_in = g_w_in;
+    a.g_w_rec = g_w_rec;
+    a.g_w_out = g_w_out;
+    hipStream_t s = stream ? (hipStream_t)stream : p->pool.stream;
+    check(snn::bptt_backward(a, g_loss, s), "bptt backward");
+  });
+}
+
+snn_status snn_bptt_get_trace(snn_bptt *p, float *spikes, float *v_checkpoints, float *readout_max,
+                              int32_t *readout_argmax, void *stream) {
+  return guarded([&] {
+    if (!p) fail(SNN_E_INVALID, "null plan");
+    const snn::BpttArgs &a = p->args;
+    hipStream_t s = stream ? (hipStream_t)stream : p->pool.stream;
+    const size_t HB = (size_t)a.H * 64, n_seg = (a.T + a.K - 1) / a.K;
+    if (spikes) check(hipMemcpyAsync(spikes, a.s, (size_t)a.T * HB * 4, hipMemcpyDeviceToHost, s), "copy");
+    if (v_checkpoints) check(hipMemcpyAsync(v_checkpoints, a.vck, n_seg * HB * 4, hipMemcpyDeviceToHost, s), "copy");
+    if (readout_max) check(hipMemcpyAsync(readout_max, a.m, (size_t)a.B * a.O * 4, hipMemcpyDeviceToHost, s), "copy");
+    if (readout_argmax)
+      check(hipMemcpyAsync(readout_argmax, a.tmax, (size_t)a.B * a.O * 4, hipMemcpyDeviceToHost, s), "copy");
+    check(hipStreamSynchronize(s), "sync");
+  });
+}
+
+void snn_bptt_destroy(snn_bptt *p) {
+  if (!p) return;
+  release(&p->pool);
+  delete p;
+}
 
 }  // extern "C"

@@ -117,6 +117,58 @@ struct StdpArgs {
   float a_plus, a_minus, w_max;
 };
 
+// One network of a batch as the persistent batch kernel sees it: pointers into the
+// network's own buffers (state layout identical to the single-network pipeline) and
+// its derived constants.
+struct BatchNet {
+  const uint64_t *row_ptr;
+  const int32_t *col, *w_q16;
+  float *v;
+  int32_t *ref;
+  int32_t *input;            // [delay][n] Q16 accumulators, slot t mod delay
+  int32_t *queue;            // >= n spike ids
+  uint64_t *raster;          // [raster_cap][words]
+  const uint32_t *table32;   // drive thresholds below 2^32
+  Ctl *ctl;
+  uint32_t n, words, delay, raster_cap;
+  uint32_t below;            // number of drive thresholds below 2^32 (0: no drive)
+  uint32_t lanes_shift;      // log2 of the lanes that share one spike's row
+  uint32_t key0, key1;
+  float alpha, v_inf, v_th, v_reset;
+  int32_t ref_steps, w_ext_q16;
+};
+constexpr uint32_t kBatchCommit = 1u;       // write state, counters and t back
+constexpr uint32_t kBatchWriteRaster = 2u;  // write the raster rows
+bool batch_variant_supported(uint32_t block, uint32_t per);
+uint32_t batch_per_lane(uint32_t block, uint32_t n_max);  // 0: n_max too large for block
+hipError_t launch_batch(const BatchNet *nets, const uint32_t *order, uint32_t n_nets, uint32_t steps,
+                        uint32_t block, uint32_t per, uint32_t flags, size_t lds, hipStream_t s);
+
+// Surrogate-gradient BPTT plan as its kernels see it (bptt.hip).  Batch <= 64: lane b
+// of a wavefront is batch element b; sizes are B batch, T steps, C inputs, H hidden,
+// O readouts, K steps per checkpoint segment (<= 32).
+struct BpttArgs {
+  uint32_t B, T, C, H, O, K;
+  float beta, beta_out, theta, slope;
+  uint32_t smooth, detach_reset;
+  uint64_t nnz_in, nnz_rec;
+  const uint64_t *in_t_ptr;    // W_in transposed: in-edges of each hidden neuron,
+  const int32_t *in_t_src;     //   sources ascending, with their CSR edge index
+  const uint32_t *in_t_edge;
+  const uint64_t *rec_t_ptr;   // W_rec transposed, likewise
+  const int32_t *rec_t_src;
+  const uint32_t *rec_t_edge;
+  const uint64_t *rec_ptr;     // W_rec forward rows
+  const int32_t *rec_col;
+  const float *w_in, *w_rec, *w_out;  // caller's weights: CSR order, CSR order, [H][O]
+  float *g_w_in, *g_w_rec, *g_w_out;
+  float *xt, *s, *vck, *vtmp, *vseg, *ro, *lamu, *lamv, *lam_carry, *m, *dm;
+  int32_t *tmax;
+};
+hipError_t bptt_forward(const BpttArgs &a, const float *x, const int32_t *labels, float *loss,
+                        hipStream_t s);
+hipError_t bptt_backward(const BpttArgs &a, const float *g_loss, hipStream_t s);
+
 // kernel launchers (step.hip / generate.hip)
 hipError_t launch_update(const UpdateArgs &a, uint32_t steps, hipStream_t s);
 hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t grid,
@@ -124,6 +176,7 @@ hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t 
 hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t block,
                                 uint32_t grid, hipStream_t s);
 constexpr uint32_t kTileGroupMax = 4;  // base tiles one tiled-delivery workgroup may own
+hipError_t prepare_deliver_tiled(uint32_t block, size_t *max_dynamic_lds);
 hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_row_lengths(const GenArgs &g, uint32_t *len, uint32_t *plast_rel,
                               uint32_t *plast_len, hipStream_t s);
@@ -203,6 +256,7 @@ struct snn_network {
   int device = 0;
   uint32_t cu_count = 256;
   uint64_t t_host = 0;  // steps issued (mirror of the device counter)
+  snn_batch *owner = nullptr;  // set for the members of a batch
   uint64_t device_bytes = 0;
 
   // graph of a fixed chunk of windows

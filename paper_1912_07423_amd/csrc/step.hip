@@ -95,6 +95,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
   const uint32_t wave = threadIdx.x / kWave;
   const uint32_t word = i / kWave;
   const bool drive = a.table_len > 1;
+  const LifConst lif{a.alpha, a.v_inf, a.v_th, a.v_reset, a.ref_steps, a.w_ext_q16};
 
   // input of window position p = w + off (w = p - off), zeroed behind the read if the
   // delivery accumulates with atomics
@@ -139,30 +140,15 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
       if (w < 0 || w >= (int32_t)steps) continue;  // uniform
       bool spike = false;
       if (active) {
-        if (ref > 0) {
-          ref -= 1;
-        } else {
-          int32_t k = 0;
-          if (drive) {
-            const uint32_t r = rnd.w[u];
-            const uint32_t gk = guide[r >> (32 - kGuideBits)];
-            k = (int32_t)(gk & 0xFFu);
-            const int32_t k_hi = (int32_t)(gk >> 8);
-            while (k < k_hi && tbl[k] <= r) ++k;
-          }
-          const uint32_t sum = (uint32_t)acc[u] + (uint32_t)k * (uint32_t)a.w_ext_q16;
-          const float dv = (float)(int32_t)sum * 0x1p-16f;
-          float vv = v + dv;
-          const float diff = vv - a.v_inf;
-          const float leak = diff * a.alpha;
-          vv = a.v_inf + leak;
-          if (vv >= a.v_th) {
-            spike = true;
-            vv = a.v_reset;
-            ref = a.ref_steps;
-          }
-          v = vv;
+        int32_t k = 0;
+        if (drive && ref <= 0) {
+          const uint32_t r = rnd.w[u];
+          const uint32_t gk = guide[r >> (32 - kGuideBits)];
+          k = (int32_t)(gk & 0xFFu);
+          const int32_t k_hi = (int32_t)(gk >> 8);
+          while (k < k_hi && tbl[k] <= r) ++k;
         }
+        spike = lif_advance(v, ref, acc[u], k, lif);
         if (a.plastic) {
           xp = xp * a.beta_plus;
           xq = xq * a.beta_minus;
@@ -589,6 +575,26 @@ hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t 
   if (plastic_w) k_deliver_atomic<true><<<grid, kAtomicBlock, 0, s>>>(a, steps);
   else k_deliver_atomic<false><<<grid, kAtomicBlock, 0, s>>>(a, steps);
   return hipGetLastError();
+}
+
+// Largest dynamic LDS (bytes) a tiled-delivery workgroup of this size may request on the
+// current device, after raising the kernel's dynamic-LDS attribute to that limit.
+hipError_t prepare_deliver_tiled(uint32_t block, size_t *max_dynamic_lds) {
+  int dev = 0, limit = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  const void *fn = block == 256   ? reinterpret_cast<const void *>(&k_deliver_tiled<256>)
+                   : block == 512 ? reinterpret_cast<const void *>(&k_deliver_tiled<512>)
+                                  : reinterpret_cast<const void *>(&k_deliver_tiled<1024>);
+  hipFuncAttributes attr{};
+  e = hipFuncGetAttributes(&attr, fn);
+  if (e != hipSuccess) return e;
+  const size_t dyn = (size_t)limit > attr.sharedSizeBytes ? (size_t)limit - attr.sharedSizeBytes : 0;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+  if (e != hipSuccess) return e;
+  *max_dynamic_lds = dyn;
+  return hipSuccess;
 }
 
 hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t block,

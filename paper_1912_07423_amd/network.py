@@ -38,6 +38,25 @@ def _ptr(a):
     return C.c_void_p(a.ctypes.data) if a is not None else None
 
 
+def _structs(spec, **extra):
+    """ctypes parameter, population and projection arrays of a workload spec."""
+    prm = spec["params"]
+    fields = {k: prm[k] for k, _ in L.PARAM_FIELDS
+              if k not in ("raster_steps", "window", "delivery", "tiles", "block", "grid")}
+    base = dict(raster_steps=0, window=0, delivery=0, tiles=0, block=0, grid=0)
+    base.update(extra)
+    p = L.Params(**fields, **base)
+    pops = (L.Population * len(spec["pops"]))(
+        *[L.Population(q["size"], q.get("excitatory", 1)) for q in spec["pops"]])
+    projs_in = spec.get("projs", [])
+    projs = (L.Projection * max(1, len(projs_in)))()
+    for k, q in enumerate(projs_in):
+        projs[k] = L.Projection(q["from"], q["to"], L.PROJ_KIND[q["kind"]], int(q.get("k", 0)),
+                                float(q.get("p", 0.0)), float(q["w_mV"]),
+                                int(q.get("plastic", 0)), int(q.get("to_span", 1)))
+    return p, pops, projs, len(projs_in)
+
+
 class Network:
     """A network built and simulated on the GPU from a workload spec (see workloads.py).
 
@@ -53,19 +72,9 @@ class Network:
         lib = L.load()
         self._lib = lib
         self._h = None
-        prm = spec["params"]
-        fields = {k: prm[k] for k, _ in L.PARAM_FIELDS
-                  if k not in ("raster_steps", "window", "delivery", "tiles", "block", "grid")}
-        p = L.Params(**fields, raster_steps=raster_steps, window=window,
-                     delivery=L.DELIVERY[delivery], tiles=tiles, block=block, grid=grid)
-        pops = (L.Population * len(spec["pops"]))(
-            *[L.Population(q["size"], q.get("excitatory", 1)) for q in spec["pops"]])
-        projs_in = spec.get("projs", [])
-        projs = (L.Projection * max(1, len(projs_in)))()
-        for k, q in enumerate(projs_in):
-            projs[k] = L.Projection(q["from"], q["to"], L.PROJ_KIND[q["kind"]], int(q.get("k", 0)),
-                                    float(q.get("p", 0.0)), float(q["w_mV"]),
-                                    int(q.get("plastic", 0)), int(q.get("to_span", 1)))
+        p, pops, projs, n_projs = _structs(spec, raster_steps=raster_steps, window=window,
+                                           delivery=L.DELIVERY[delivery], tiles=tiles,
+                                           block=block, grid=grid)
         self._keep = None
         stream_handle = None
         alloc_ptr = None
@@ -77,7 +86,7 @@ class Network:
                 alloc_ptr = C.byref(alloc)
                 stream_handle = stream.cuda_stream or None
         h = C.c_void_p()
-        L.check(lib.snn_build_network(C.byref(p), pops, len(spec["pops"]), projs, len(projs_in),
+        L.check(lib.snn_build_network(C.byref(p), pops, len(spec["pops"]), projs, n_projs,
                                       alloc_ptr, stream_handle, C.byref(h)))
         self._h = h
         self.spec = spec
@@ -86,10 +95,25 @@ class Network:
         self.words = inf["raster_words"]
         self.plastic = bool(inf["plastic"])
 
+    @classmethod
+    def _member(cls, batch, handle, spec):
+        """A handle to a network owned by a Batch (no ownership taken)."""
+        self = cls.__new__(cls)
+        self._lib = batch._lib
+        self._h = handle
+        self._keep = None
+        self._batch = batch        # keeps the batch alive while the handle is used
+        self.spec = spec
+        inf = self.info()
+        self.n = inf["n"]
+        self.words = inf["raster_words"]
+        self.plastic = bool(inf["plastic"])
+        return self
+
     # -- lifecycle --------------------------------------------------------------------
     def close(self):
         if self._h:
-            self._lib.snn_destroy(self._h)
+            self._lib.snn_destroy(self._h)   # no-op for a batch member
             self._h = None
 
     def __del__(self):
@@ -225,3 +249,90 @@ class Network:
         L.check(self._lib.snn_time_delivery(self._h, _ptr(ids), len(ids), steps, reps,
                                             C.byref(ms), C.byref(ev)))
         return ms.value, ev.value
+
+
+class Batch:
+    """Many independent static networks stepped together by one persistent launch per
+    run (include/snn.h, batched form).  `specs` is a list of workload specs; member k
+    is available as a Network handle through `network(k)` for every reader."""
+
+    def __init__(self, specs, raster_steps=1024, torch_memory=True, device=0):
+        lib = L.load()
+        self._lib = lib
+        self._h = None
+        self.specs = list(specs)
+        keep = []
+        members = (L.BatchMember * max(1, len(self.specs)))()
+        for k, spec in enumerate(self.specs):
+            p, pops, projs, n_projs = _structs(spec)
+            keep.append((p, pops, projs))
+            members[k] = L.BatchMember(C.pointer(p), pops, projs, len(spec["pops"]), n_projs)
+        self._keep = None
+        alloc_ptr, stream_handle = None, None
+        if torch_memory:
+            stream, alloc, kp = _torch_stream_and_allocator(device)
+            if stream is not None:
+                self._keep = kp
+                self._alloc = alloc
+                alloc_ptr = C.byref(alloc)
+                stream_handle = stream.cuda_stream or None
+        h = C.c_void_p()
+        L.check(lib.snn_build_batch(members, len(self.specs), raster_steps, alloc_ptr,
+                                    stream_handle, C.byref(h)))
+        self._h = h
+        self._members = {}
+
+    def __len__(self):
+        return len(self.specs)
+
+    def close(self):
+        if self._h:
+            for m in self._members.values():
+                m._h = None
+            self._members.clear()
+            self._lib.snn_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def run(self, n_steps):
+        L.check(self._lib.snn_batch_run(self._h, int(n_steps)))
+
+    def sync(self):
+        L.check(self._lib.snn_batch_sync(self._h))
+
+    def network(self, k):
+        if k not in self._members:
+            h = C.c_void_p()
+            L.check(self._lib.snn_batch_network(self._h, int(k), C.byref(h)))
+            self._members[k] = Network._member(self, h, self.specs[k])
+        return self._members[k]
+
+    @staticmethod
+    def _tuning_dict(t):
+        return {"block": t.block, "per_lane": t.per_lane, "degree_div": t.degree_div,
+                "ms_per_step": t.ms_per_step}
+
+    def autotune(self, trial_steps=200):
+        t = L.BatchTuning()
+        L.check(self._lib.snn_batch_autotune(self._h, int(trial_steps), C.byref(t)))
+        return self._tuning_dict(t)
+
+    def tuning(self):
+        t = L.BatchTuning()
+        L.check(self._lib.snn_batch_get_tuning(self._h, C.byref(t)))
+        return self._tuning_dict(t)
+
+    def set_tuning(self, block, degree_div):
+        t = L.BatchTuning(block=int(block), degree_div=int(degree_div))
+        L.check(self._lib.snn_batch_set_tuning(self._h, C.byref(t)))

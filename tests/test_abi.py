@@ -39,7 +39,8 @@ def test_exported_symbols_match_header():
 
 STRUCTS = {"snn_population": L.Population, "snn_projection": L.Projection,
            "snn_params": L.Params, "snn_allocator": L.Allocator, "snn_info": L.Info,
-           "snn_state": L.State, "snn_profile": L.Profile}
+           "snn_state": L.State, "snn_profile": L.Profile, "snn_batch_member": L.BatchMember,
+           "snn_batch_tuning": L.BatchTuning, "snn_bptt_desc": L.BpttDesc}
 
 
 def test_struct_layouts_match_header():
@@ -74,3 +75,10 @@ def test_null_arguments_rejected_without_gpu():
     assert lib.snn_run(None, 1) == L.SNN_E_INVALID
     assert lib.snn_get_info(None, None) == L.SNN_E_INVALID
     lib.snn_destroy(None)
+    assert lib.snn_build_batch(None, 3, 16, None, None, C.byref(h)) == L.SNN_E_INVALID
+    assert lib.snn_batch_run(None, 1) == L.SNN_E_INVALID
+    assert lib.snn_batch_network(None, 0, C.byref(h)) == L.SNN_E_INVALID
+    lib.snn_batch_destroy(None)
+    assert lib.snn_bptt_create(None, None, None, None, None, None, None, C.byref(h)) == L.SNN_E_INVALID
+    assert lib.snn_bptt_forward(None, None, None, None, None, None, None, None) == L.SNN_E_INVALID
+    lib.snn_bptt_destroy(None)
