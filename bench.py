@@ -1,21 +1,32 @@
 #!/usr/bin/env python
 """Throughput of the clock-driven work-queue SNN simulator on one MI355X.
 
-Workload: Brunel-style network of 200,000 LIF neurons (4:1 exc./inh.), fixed
-out-degree 5,000 with uniform random targets (1e9 synapses, int32 target + int32 Q16
-weight), J = 0.1 mV, g = 5, uniform delay 1.5 ms (15 steps), Poisson drive of 1,000
-virtual inputs per neuron at 20 Hz, dt = 0.1 ms.  Synthetic, generated on the device
-from a seed.  One "step" is one simulation time step of the whole pipeline (update
-neurons -> FIFO -> receive spikes); `--steps` steps are timed after `--warmup`.
+Default workload (the headline line): Brunel-style network of 200,000 LIF neurons (4:1
+exc./inh.), fixed out-degree 5,000 with uniform random targets (1e9 synapses, int32
+target + int32 Q16 weight), J = 0.1 mV, g = 5, uniform delay 1.5 ms (15 steps),
+Poisson drive of 1,000 virtual inputs per neuron at 20 Hz, dt = 0.1 ms.  Synthetic,
+generated on the device from a seed.  One "step" is one simulation time step of the
+whole pipeline (update neurons -> FIFO -> receive spikes); `--steps` steps are timed
+after `--warmup`.
 
 Prints one JSON line: synaptic events/s over the timed steps (inputs resident in HBM,
 network built before the clock starts), wall time per simulated second, the delivery
 kernel's achieved HBM bandwidth (algorithmic bytes / mean launch time from HIP events
-on the simulator's stream) against the 8 TB/s peak, and the CPU oracle's rate on a
-bounded sample of the same workload.
+on the simulator's stream) against the 8 TB/s peak, its measured HBM traffic when a
+counter summary of the current kernel source exists under profiles/, and the CPU
+oracle's rate on a bounded sample of the same workload.
+
+Other workloads (`--workload`, one JSON line each, not the headline):
+  stdp   100,000-neuron plastic network (2e8 synapses, STDP on E->E), 2,000 steps
+  sweep  512 independent networks (1k-20k neurons) in the batched persistent form,
+         5,000 steps, against the plain per-network simulator on the same GPU
+  bptt   surrogate-gradient BPTT (64 x 250 steps, 700 -> 1,024 -> 20), forward +
+         adjoint, against the forward alone and a dense PyTorch reference on the GPU
 """
 import argparse
+import hashlib
 import json
+import math
 import os
 import subprocess
 import sys
@@ -30,12 +41,30 @@ HBM_PEAK_GBS = 8000.0
 # (4 + 4 B), per dequeued spike its id and its row pointers (4 + 8 B)
 BYTES_PER_EVENT = 8
 BYTES_PER_SPIKE = 12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_deliver_tiled_brunel_200k_k5000_d15.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1912_07423_amd", "csrc", "step.hip")
 
 
 def workload_spec():
     from paper_1912_07423_amd import workloads as W
     return W.brunel_fixed_out(n=200_000, k=5000, delay_steps=15, rate_hz=20.0, n_ext=1000,
                               j_mV=0.1, g=5.0, seed=2, steps=1000)
+
+
+def kernel_source_sha():
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per delivery launch from the committed counter summary, if it was taken
+    of the current kernel source; otherwise None."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def cpu_baseline_child(steps):
@@ -51,32 +80,35 @@ def cpu_baseline_child(steps):
                       "steps": steps}), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=15)
-    ap.add_argument("--cpu-steps", type=int, default=1500,
-                    help="steps of the CPU-oracle sample (0 disables it)")
-    ap.add_argument("--delivery", default="auto")
-    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
-    args = ap.parse_args()
-    if args.cpu_baseline_child:
-        cpu_baseline_child(args.cpu_steps)
-        return
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} (WORLD_SIZE {world}) is not "
-              "supported by this build (the multi-GPU design is documented, not built)",
-              file=sys.stderr, flush=True)
-        sys.exit(2)
+def copy_calibration(mib):
+    """Plain device copies of a known size, for scaling the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: 3 copies of {mib} MiB", file=sys.stderr, flush=True)
+    del a, b
 
-    # the oracle sample runs on a host core while the GPU part runs
+
+def line(metric, value, unit, steps, warmup, ms_per_step, dtype, config, **extra):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+         "warmup": warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+         "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+         "config": config}
+    d.update(extra)
+    print(json.dumps(d), flush=True)
+
+
+def bench_brunel(args):
+    # the oracle sample runs on host cores while the GPU part runs
     child = None
     if args.cpu_steps > 0:
         child = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
                                   "--cpu-steps", str(args.cpu_steps)], stdout=subprocess.PIPE,
-                                 text=True, env=dict(os.environ, OMP_NUM_THREADS="1"))
+                                 text=True)
 
     import torch
     from paper_1912_07423_amd import Network
@@ -128,42 +160,275 @@ def main():
             cpu = {"value": r["events"] / r["seconds"], "unit": "events/s", "cores": 1,
                    "kind": "oracle",
                    "sample": f"the same 200k-neuron / 1e9-synapse network built by the oracle "
-                             f"({r['build_s']:.0f} s, untimed), first {r['steps']} steps timed "
-                             f"({r['seconds']:.1f} s, {r['events']} events), one host thread"}
-
-    line = {
-        "metric": METRIC,
-        "value": events / wall,
-        "unit": "events/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": "brunel_fixed_out_200k_k5000_d15_poisson20hz",
-                   "neurons": info["n"], "synapses": info["nnz"], "delay_steps": info["delay"],
-                   "dt_ms": dt_ms, "delivery": info["delivery_name"], "window": info["window"],
-                   "tiles": info["tiles"], "parallelism": "single-gpu"},
-        "wall_s_per_sim_s": wall / (args.steps * dt_ms * 1e-3),
-        "events": events,
-        "spikes_delivered": spikes,
-        "spikes_emitted": emitted,
-        "rate_hz": (emitted / info["n"] / (args.steps * dt_ms * 1e-3)) if emitted is not None else None,
-        "build_s": build_s,
-        "kernels": {"deliver_ms_mean": deliver_avg_ms, "deliver_launches": prof["deliver_launches"],
-                    "update_ms_mean": prof["update_ms"] / max(1, prof["update_launches"]),
-                    "update_launches": prof["update_launches"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_deliver_tiled" if info["delivery_name"] == "tiled" else "k_deliver_atomic"},
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(line), flush=True)
+                             f"({r['build_s']:.0f} s on all host threads, untimed), first "
+                             f"{r['steps']} steps timed ({r['seconds']:.1f} s, {r['events']} "
+                             f"events) on one host thread"}
+    kernel = "k_deliver_tiled" if info["delivery_name"] == "tiled" else "k_deliver_atomic"
+    traffic = measured_traffic() if kernel == "k_deliver_tiled" else None
+    line(METRIC, events / wall, "events/s", args.steps, args.warmup, wall * 1e3 / args.steps, "int32",
+         {"workload": "brunel_fixed_out_200k_k5000_d15_poisson20hz",
+          "neurons": info["n"], "synapses": info["nnz"], "delay_steps": info["delay"],
+          "dt_ms": dt_ms, "delivery": info["delivery_name"], "window": info["window"],
+          "tiles": info["tiles"], "parallelism": "single-gpu"},
+         wall_s_per_sim_s=wall / (args.steps * dt_ms * 1e-3), events=events,
+         spikes_delivered=spikes, spikes_emitted=emitted,
+         rate_hz=(emitted / info["n"] / (args.steps * dt_ms * 1e-3)) if emitted is not None else None,
+         build_s=build_s,
+         kernels={"deliver_ms_mean": deliver_avg_ms, "deliver_launches": prof["deliver_launches"],
+                  "update_ms_mean": prof["update_ms"] / max(1, prof["update_launches"]),
+                  "update_launches": prof["update_launches"]},
+         roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+                   "bytes_per_launch": bytes_per_launch},
+         cpu_baseline=cpu)
     net.close()
+
+
+def bench_stdp(args):
+    import torch
+    from paper_1912_07423_amd import Network
+    from paper_1912_07423_amd import workloads as W
+    spec = W.stdp_er()
+    steps = args.steps if args.steps != 1000 else spec["steps"]
+    net = Network(spec, raster_steps=4096)
+    net.run(args.warmup)
+    net.sync()
+    i0 = net.info()
+    net.set_profiling(True)
+    net.reset_profile()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.run(steps)
+    net.sync()
+    wall = time.perf_counter() - t0
+    prof = net.profile()
+    i1 = net.info()
+    events, touches = i1["events"] - i0["events"], i1["touches"] - i0["touches"]
+    spikes = i1["spikes"] - i0["spikes"]
+    dmean = prof["deliver_ms"] / max(1, prof["deliver_launches"])
+    smean = prof["stdp_ms"] / max(1, prof["stdp_launches"])
+    dbytes = (events * BYTES_PER_EVENT + spikes * BYTES_PER_SPIKE) / max(1, prof["deliver_launches"])
+    line("STDP network: synaptic events/sec, STDP synapse touches/sec, 1 GPU", events / wall, "events/s",
+         steps, args.warmup, wall * 1e3 / steps, "fp32",
+         {"workload": "stdp_er_100k_p0.02_d10_poisson10hz", "neurons": i1["n"], "synapses": i1["nnz"],
+          "delay_steps": i1["delay"], "delivery": i1["delivery_name"], "parallelism": "single-gpu"},
+         touches_per_s=touches / wall, events=events, touches=touches,
+         kernels={"deliver_ms_mean": dmean, "stdp_ms_mean": smean,
+                  "update_ms_mean": prof["update_ms"] / max(1, prof["update_launches"]),
+                  "launches_per_kernel": prof["deliver_launches"]},
+         roofline={"bound": "hbm", "achieved": dbytes / (dmean * 1e-3) / 1e9 if dmean > 0 else 0.0,
+                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": dbytes / (dmean * 1e-3) / 1e9 / HBM_PEAK_GBS if dmean > 0 else 0.0,
+                   "traffic": None, "kernel": "k_deliver_atomic"})
+    net.close()
+
+
+def bench_sweep(args):
+    import numpy as np
+    import torch
+    from paper_1912_07423_amd import Batch, Network
+    from paper_1912_07423_amd import workloads as W
+    specs = W.sweep()
+    steps = args.steps if args.steps != 1000 else specs[0]["steps"]
+    tb = time.perf_counter()
+    b = Batch(specs, raster_steps=max(16, min(steps, 5000)))
+    build_s = time.perf_counter() - tb
+    tuning = b.autotune(trial_steps=100)
+    print(f"[bench] sweep built in {build_s:.1f}s; tuning {tuning}", file=sys.stderr, flush=True)
+    b.run(args.warmup)
+    b.sync()
+    ev0 = sum(b.network(k).events for k in range(len(specs)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(steps)
+    b.sync()
+    wall = time.perf_counter() - t0
+    events = sum(b.network(k).events for k in range(len(specs))) - ev0
+    neurons = sum(b.network(k).n for k in range(len(specs)))
+    synapses = sum(b.network(k).info()["nnz"] for k in range(len(specs)))
+    b.close()
+    # the plain per-network simulator on a stratified sample (every 8th network by size)
+    order = np.argsort([s["pops"][0]["size"] + s["pops"][1]["size"] for s in specs])
+    sample = order[::8]
+    seq = 0.0
+    for k in sample:
+        g = Network(specs[k], raster_steps=16)
+        g.run(args.warmup)
+        g.sync()
+        t1 = time.perf_counter()
+        g.run(steps)
+        g.sync()
+        seq += time.perf_counter() - t1
+        g.close()
+    seq_all = seq * len(specs) / len(sample)
+    line("batched sweep: synaptic events/sec over 512 independent networks, 1 GPU", events / wall,
+         "events/s", steps, args.warmup, wall * 1e3 / steps, "int32",
+         {"workload": "sweep_512_cuba_lif_1k-20k_p0.01-0.05", "networks": len(specs), "neurons": neurons,
+          "synapses": synapses, "parallelism": "single-gpu"},
+         network_steps_per_s=len(specs) * steps / wall, wall_s=wall, build_s=build_s, tuning=tuning,
+         plain_sequential_s_estimate=seq_all,
+         plain_sample=f"{len(sample)} networks (every 8th by size) run one after another with the plain "
+                      f"simulator for {steps} steps: {seq:.2f} s, scaled by {len(specs) / len(sample):.0f}",
+         speedup_vs_plain=seq_all / wall)
+
+
+def bench_bptt(args):
+    import numpy as np
+    import torch
+    from paper_1912_07423_amd import workloads as W
+    from paper_1912_07423_amd.bptt import RecurrentLIF
+    d = W.bptt_inputs()
+    B, T, C = d["x"].shape
+    H, O = d["w_out"].shape
+    plan = RecurrentLIF(d["mask_in"], d["mask_rec"], O, B, T, checkpoint=25, dt_ms=d["dt_ms"])
+    v_in, v_rec = plan.csr_values(d["w_in"], d["w_rec"])
+    dev = plan.device
+    x = torch.tensor(d["x"], device=dev)
+    y = torch.tensor(d["labels"].astype(np.int32), device=dev)
+    w_in = torch.tensor(v_in, device=dev, requires_grad=True)
+    w_rec = torch.tensor(v_rec, device=dev, requires_grad=True)
+    w_out = torch.tensor(d["w_out"], device=dev, requires_grad=True)
+    iters = max(1, args.steps if args.steps != 1000 else 20)
+
+    def fwd_bwd():
+        w_in.grad = w_rec.grad = w_out.grad = None
+        plan.loss(x, w_in, w_rec, w_out, y).backward()
+
+    def fwd():
+        with torch.no_grad():
+            plan.forward(x, w_in, w_rec, w_out, y)
+
+    def timed(fn, n):
+        for _ in range(max(1, args.warmup // 5)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    t_fb = timed(fwd_bwd, iters)
+    t_f = timed(fwd, iters)
+
+    # dense PyTorch reference of the same model on the same GPU (float32, autograd with a
+    # surrogate spike function)
+    class Spike(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, z):
+            ctx.save_for_backward(z)
+            return (z >= 0).float()
+
+        @staticmethod
+        def backward(ctx, g):
+            (z,) = ctx.saved_tensors
+            return g / (1.0 + 25.0 * z.abs()) ** 2
+
+    beta = math.exp(-d["dt_ms"] / 20.0)
+    mi = torch.tensor(d["mask_in"], device=dev, dtype=torch.float32)
+    mr = torch.tensor(d["mask_rec"], device=dev, dtype=torch.float32)
+    Wi = torch.tensor(d["w_in"], device=dev, requires_grad=True)
+    Wr = torch.tensor(d["w_rec"], device=dev, requires_grad=True)
+    Wo = torch.tensor(d["w_out"], device=dev, requires_grad=True)
+    yl = y.long()
+
+    def dense():
+        Wi.grad = Wr.grad = Wo.grad = None
+        wi, wr = Wi * mi, Wr * mr
+        v = torch.zeros(B, H, device=dev)
+        s = torch.zeros(B, H, device=dev)
+        u = torch.zeros(B, O, device=dev)
+        m = None
+        for t in range(T):
+            v = beta * v + x[:, t] @ wi + s @ wr - s.detach()
+            s = Spike.apply(v - 1.0)
+            u = beta * u + s @ Wo
+            m = u if m is None else torch.maximum(m, u)
+        torch.nn.functional.cross_entropy(m, yl).backward()
+
+    t_dense = timed(dense, max(1, iters // 4))
+    line("surrogate-gradient BPTT: training iterations/sec (forward + adjoint), 1 GPU", 1.0 / t_fb,
+         "iterations/s", iters, args.warmup, t_fb * 1e3, "fp32",
+         {"workload": "bptt_rlif_b64_t250_in700_h1024_out20", "batch": B, "steps_per_sequence": T,
+          "synapses": plan.nnz_in + plan.nnz_rec, "checkpoint": 25, "parallelism": "single-gpu"},
+         forward_ms=t_f * 1e3, forward_backward_ms=t_fb * 1e3, dense_torch_ms=t_dense * 1e3,
+         speedup_vs_dense_torch=t_dense / t_fb)
+    plan.close()
+
+
+def summarize_pmc(fetch_dir, write_dir, copy_mib, command, skip=1):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) of
+    the same bench command into HBM bytes per tiled-delivery launch, each counter scaled
+    by what it reads for the plain device copy of `copy_mib` MiB in the same run.  The
+    first `skip` delivery dispatches (the untimed warm-up window) are left out, so the
+    mean covers the launches whose algorithmic bytes the bench line reports."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r.get("Counter_Name") == counter:
+                        rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        if not rows:
+            raise SystemExit(f"no {counter} rows under {d}")
+        return rows
+
+    out = {"kernel_source_sha": kernel_source_sha(), "command": command, "copy_mib": copy_mib}
+    known = copy_mib * (1 << 20)
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = read(d, counter)
+        # the three calibration copies are the largest copy dispatches of the run (the
+        # runtime's copy kernel also serves the small copies of the simulator's setup)
+        copies = sorted((v for k, v in rows if "copy" in k.lower()), reverse=True)[:3]
+        deliver = [v for k, v in rows if "k_deliver_tiled" in k][skip:]
+        if len(copies) < 3 or not deliver:
+            raise SystemExit(f"{counter}: need 3 copy and some k_deliver_tiled dispatches")
+        copy_kib = copies[1]
+        factor = known / (copy_kib * 1024.0)
+        out[f"{key}_copy_kib"] = copy_kib
+        out[f"{key}_factor"] = factor
+        out[f"{key}_bytes_per_launch"] = sum(deliver) / len(deliver) * 1024.0 * factor
+        out[f"{key}_dispatches"] = len(deliver)
+    out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=15)
+    ap.add_argument("--cpu-steps", type=int, default=1500,
+                    help="steps of the CPU-oracle sample (0 disables it)")
+    ap.add_argument("--delivery", default="auto")
+    ap.add_argument("--workload", default="brunel", choices=["brunel", "stdp", "sweep", "bptt"])
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run 3 plain device copies of this size first (HBM counter scaling)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic summary of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--pmc-command", default="", help="the profiled command, recorded in the summary")
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.copy_calibration_mib,
+                      args.pmc_command)
+        return
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args.cpu_steps)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} (WORLD_SIZE {world}) is not "
+              "supported by this build (the multi-GPU design is documented, not built)",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+    if args.copy_calibration_mib > 0:
+        copy_calibration(args.copy_calibration_mib)
+    {"brunel": bench_brunel, "stdp": bench_stdp, "sweep": bench_sweep, "bptt": bench_bptt}[args.workload](args)
 
 
 if __name__ == "__main__":
