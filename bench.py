@@ -37,10 +37,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "synaptic events/sec and % HBM roofline, 1 GPU; wall-time per simulated second"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes of spike delivery: per synaptic event the target id and the weight
-# (4 + 4 B), per dequeued spike its id and its row pointers (4 + 8 B)
-BYTES_PER_EVENT = 8
-BYTES_PER_SPIKE = 12
+# algorithmic bytes of spike delivery: per synaptic event the target id (4 B) and, when
+# weights are stored per synapse, the weight (4 B); per dequeued spike its id and its row
+# pointers (4 + 8 B) and, with one weight per source, that weight (4 B)
+
+
+def delivery_bytes(info):
+    """(bytes per event, bytes per dequeued spike) of the network's weight layout."""
+    return (4, 16) if info.get("source_weights") else (8, 12)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_deliver_tiled_brunel_200k_k5000_d15.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1912_07423_amd", "csrc", "step.hip")
 
@@ -103,13 +107,6 @@ def line(metric, value, unit, steps, warmup, ms_per_step, dtype, config, **extra
 
 
 def bench_brunel(args):
-    # the oracle sample runs on host cores while the GPU part runs
-    child = None
-    if args.cpu_steps > 0:
-        child = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
-                                  "--cpu-steps", str(args.cpu_steps)], stdout=subprocess.PIPE,
-                                 text=True)
-
     import torch
     from paper_1912_07423_amd import Network
 
@@ -117,7 +114,7 @@ def bench_brunel(args):
     print(f"[bench] building {spec['pops']} ...", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     tb = time.perf_counter()
-    net = Network(spec, raster_steps=4096, delivery=args.delivery)
+    net = Network(spec, raster_steps=4096, delivery=args.delivery, synapse_weights=args.synapse_weights)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - tb
     info = net.info()
@@ -145,15 +142,22 @@ def bench_brunel(args):
     dt_ms = spec["params"]["dt_ms"]
     launches = max(1, prof["deliver_launches"])
     deliver_avg_ms = prof["deliver_ms"] / launches
-    bytes_per_launch = (events * BYTES_PER_EVENT + spikes * BYTES_PER_SPIKE) / launches
+    b_ev, b_spk = delivery_bytes(info)
+    bytes_per_launch = (events * b_ev + spikes * b_spk) / launches
     achieved = bytes_per_launch / (deliver_avg_ms * 1e-3) / 1e9 if deliver_avg_ms > 0 else 0.0
     print(f"[bench] {args.steps} steps in {wall * 1e3:.2f} ms; {events} events; "
           f"deliver {deliver_avg_ms * 1e3:.1f} us x {launches}; update "
           f"{prof['update_ms'] / max(1, prof['update_launches']) * 1e3:.1f} us x "
           f"{prof['update_launches']}", file=sys.stderr, flush=True)
 
+    net.close()
+    # the oracle sample runs after the GPU part, so that it takes no host core from the
+    # launches being timed
     cpu = None
-    if child is not None:
+    if args.cpu_steps > 0:
+        child = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                                  "--cpu-steps", str(args.cpu_steps)], stdout=subprocess.PIPE,
+                                 text=True)
         out, _ = child.communicate()
         if child.returncode == 0 and out.strip():
             r = json.loads(out.strip().splitlines()[-1])
@@ -169,7 +173,8 @@ def bench_brunel(args):
          {"workload": "brunel_fixed_out_200k_k5000_d15_poisson20hz",
           "neurons": info["n"], "synapses": info["nnz"], "delay_steps": info["delay"],
           "dt_ms": dt_ms, "delivery": info["delivery_name"], "window": info["window"],
-          "tiles": info["tiles"], "parallelism": "single-gpu"},
+          "tiles": info["tiles"], "source_weights": bool(info["source_weights"]),
+          "parallelism": "single-gpu"},
          wall_s_per_sim_s=wall / (args.steps * dt_ms * 1e-3), events=events,
          spikes_delivered=spikes, spikes_emitted=emitted,
          rate_hz=(emitted / info["n"] / (args.steps * dt_ms * 1e-3)) if emitted is not None else None,
@@ -179,9 +184,9 @@ def bench_brunel(args):
                   "update_launches": prof["update_launches"]},
          roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
-                   "bytes_per_launch": bytes_per_launch},
+                   "bytes_per_launch": bytes_per_launch, "bytes_per_event": b_ev,
+                   "bytes_per_spike": b_spk},
          cpu_baseline=cpu)
-    net.close()
 
 
 def bench_stdp(args):
@@ -207,7 +212,8 @@ def bench_stdp(args):
     spikes = i1["spikes"] - i0["spikes"]
     dmean = prof["deliver_ms"] / max(1, prof["deliver_launches"])
     smean = prof["stdp_ms"] / max(1, prof["stdp_launches"])
-    dbytes = (events * BYTES_PER_EVENT + spikes * BYTES_PER_SPIKE) / max(1, prof["deliver_launches"])
+    b_ev, b_spk = delivery_bytes(i1)
+    dbytes = (events * b_ev + spikes * b_spk) / max(1, prof["deliver_launches"])
     line("STDP network: synaptic events/sec, STDP synapse touches/sec, 1 GPU", events / wall, "events/s",
          steps, args.warmup, wall * 1e3 / steps, "fp32",
          {"workload": "stdp_er_100k_p0.02_d10_poisson10hz", "neurons": i1["n"], "synapses": i1["nnz"],
@@ -405,6 +411,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=1500,
                     help="steps of the CPU-oracle sample (0 disables it)")
     ap.add_argument("--delivery", default="auto")
+    ap.add_argument("--synapse-weights", default="auto", choices=["auto", "per_synapse"])
     ap.add_argument("--workload", default="brunel", choices=["brunel", "stdp", "sweep", "bptt"])
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run 3 plain device copies of this size first (HBM counter scaling)")

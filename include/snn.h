@@ -93,6 +93,11 @@ typedef struct {
     uint32_t tiles;        /* target tiles of the tiled delivery (0: auto) */
     uint32_t block;        /* workgroup size of the tiled delivery: 256, 512, 1024 (0: auto) */
     uint32_t grid;         /* workgroups of the tiled delivery (0: auto) */
+    uint32_t synapse_weights; /* 0: auto -- when every projection from a source population
+                                 has the same weight, store only the 4-byte target per
+                                 synapse and one weight per source (Table I layout);
+                                 1: a Q16 weight per synapse as well (8 bytes per synapse) */
+    uint32_t pad_;
 } snn_params;
 
 /* Optional device-memory provider (e.g. a framework's caching allocator).  alloc
@@ -119,7 +124,7 @@ typedef struct {
     uint32_t table_len;     /* entries of the drive's inverse-CDF table */
     uint32_t queue_groups;  /* sub-queues per spike queue */
     uint32_t queue_stride;  /* entries per queue slot (queue_groups equal sub-queues) */
-    uint32_t pad_;
+    uint32_t source_weights; /* 1: one weight per source neuron, 4 bytes per synapse */
     uint64_t nnz;           /* synapses */
     uint64_t t;             /* steps simulated */
     uint64_t events;        /* synaptic events delivered (sum of out-degrees of delivered spikes) */

@@ -43,7 +43,7 @@ PARAM_FIELDS = [
     ("a_plus", C.c_double), ("a_minus", C.c_double), ("w_max_mV", C.c_double),
     ("seed", C.c_uint64), ("raster_steps", C.c_uint32), ("window", C.c_uint32),
     ("delivery", C.c_uint32), ("tiles", C.c_uint32), ("block", C.c_uint32),
-    ("grid", C.c_uint32),
+    ("grid", C.c_uint32), ("synapse_weights", C.c_uint32), ("pad_", C.c_uint32),
 ]
 
 
@@ -64,7 +64,8 @@ class Info(C.Structure):
                 ("input_buffers", C.c_uint32), ("window", C.c_uint32), ("delivery", C.c_uint32),
                 ("tiles", C.c_uint32), ("plastic", C.c_uint32), ("raster_steps", C.c_uint32),
                 ("raster_words", C.c_uint32), ("table_len", C.c_uint32),
-                ("queue_groups", C.c_uint32), ("queue_stride", C.c_uint32), ("pad_", C.c_uint32),
+                ("queue_groups", C.c_uint32), ("queue_stride", C.c_uint32),
+                ("source_weights", C.c_uint32),
                 ("nnz", C.c_uint64), ("t", C.c_uint64), ("events", C.c_uint64),
                 ("spikes", C.c_uint64), ("touches", C.c_uint64), ("device_bytes", C.c_uint64)]
 
@@ -151,9 +152,15 @@ class SnnError(RuntimeError):
 
 
 def load():
-    """The loaded library; raises if it has not been built."""
+    """The loaded library; raises if it has not been built.  PyTorch, when installed, is
+    imported first, so that the process has one HIP runtime: the one torch brings, which
+    libsnn.so then binds to, whatever order the caller imports things in."""
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1912_07423_amd.build` (hipcc, gfx950)")

@@ -100,17 +100,30 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchNet *nets, const ui
         spikes += 1;
       }
       uint64_t e = lo + gl;
-      for (; e + 3u * lanes < hi; e += 4u * lanes) {
-        const int32_t c0 = d.col[e], c1 = d.col[e + lanes];
-        const int32_t c2 = d.col[e + 2u * lanes], c3 = d.col[e + 3u * lanes];
-        const int32_t w0 = d.w_q16[e], w1 = d.w_q16[e + lanes];
-        const int32_t w2 = d.w_q16[e + 2u * lanes], w3 = d.w_q16[e + 3u * lanes];
-        atomicAdd(&in[c0], w0);
-        atomicAdd(&in[c1], w1);
-        atomicAdd(&in[c2], w2);
-        atomicAdd(&in[c3], w3);
+      if (d.w_src) {  // one weight per source: only the targets are streamed
+        const int32_t ws = d.w_src[src];
+        for (; e + 3u * lanes < hi; e += 4u * lanes) {
+          const int32_t c0 = d.col[e], c1 = d.col[e + lanes];
+          const int32_t c2 = d.col[e + 2u * lanes], c3 = d.col[e + 3u * lanes];
+          atomicAdd(&in[c0], ws);
+          atomicAdd(&in[c1], ws);
+          atomicAdd(&in[c2], ws);
+          atomicAdd(&in[c3], ws);
+        }
+        for (; e < hi; e += lanes) atomicAdd(&in[d.col[e]], ws);
+      } else {
+        for (; e + 3u * lanes < hi; e += 4u * lanes) {
+          const int32_t c0 = d.col[e], c1 = d.col[e + lanes];
+          const int32_t c2 = d.col[e + 2u * lanes], c3 = d.col[e + 3u * lanes];
+          const int32_t w0 = d.w_q16[e], w1 = d.w_q16[e + lanes];
+          const int32_t w2 = d.w_q16[e + 2u * lanes], w3 = d.w_q16[e + 3u * lanes];
+          atomicAdd(&in[c0], w0);
+          atomicAdd(&in[c1], w1);
+          atomicAdd(&in[c2], w2);
+          atomicAdd(&in[c3], w3);
+        }
+        for (; e < hi; e += lanes) atomicAdd(&in[d.col[e]], d.w_q16[e]);
       }
-      for (; e < hi; e += lanes) atomicAdd(&in[d.col[e]], d.w_q16[e]);
     }
     __syncthreads();
     slot = slot + 1u == delay ? 0u : slot + 1u;

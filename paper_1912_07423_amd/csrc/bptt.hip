@@ -48,6 +48,36 @@ __global__ void k_transpose_x(const float *x, float *xt, uint32_t B, uint32_t T,
   xt[idx] = b < B ? x[((uint64_t)b * T + t) * C + c] : 0.0f;
 }
 
+// Transposed-order copy of a CSR weight vector: w_t[e] = w[edge[e]].
+__global__ void k_gather_t(const float *w, const uint32_t *edge, float *w_t, uint64_t nnz) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) w_t[e] = w[edge[e]];
+}
+
+// sum += w[e] * val[src[e] * 64 + b] over [e0, e1), one term at a time in edge order;
+// the (wave-uniform) sources and weights of kChunk edges, then their presynaptic values,
+// are loaded before the chunk's terms are added, so the loads overlap.
+constexpr int kChunk = 16;
+__device__ __forceinline__ float ordered_gather_sum(float acc, uint64_t e0, uint64_t e1, const int32_t *src,
+                                                    const float *w, const float *val, uint32_t b) {
+  uint64_t e = e0;
+  for (; e + kChunk <= e1; e += kChunk) {
+    int32_t sr[kChunk];
+    float wv[kChunk], xv[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      sr[u] = src[e + u];
+      wv[u] = w[e + u];
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) xv[u] = val[(size_t)sr[u] * 64 + b];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) acc = acc + wv[u] * xv[u];
+  }
+  for (; e < e1; ++e) acc = acc + w[e] * val[(size_t)src[e] * 64 + b];
+  return acc;
+}
+
 // One step t of the hidden layer: one wavefront per hidden neuron j, lane = batch.
 // vprev/sprev are step t-1 (nullptr at t = 0).  Writes v_out[j][b] and, if s_out is
 // set, s_out[j][b].
@@ -57,17 +87,8 @@ __global__ __launch_bounds__(256) void k_hidden_step(BpttArgs a, uint32_t t, con
   if (j >= a.H) return;
   const uint32_t b = lane_id();
   const float *xt = a.xt + (size_t)t * a.C * 64;
-  float acc = 0.0f;
-  for (uint64_t e = a.in_t_ptr[j]; e < a.in_t_ptr[j + 1]; ++e) {
-    const float w = a.w_in[a.in_t_edge[e]];
-    acc = acc + w * xt[(size_t)a.in_t_src[e] * 64 + b];
-  }
-  if (sprev) {
-    for (uint64_t e = a.rec_t_ptr[j]; e < a.rec_t_ptr[j + 1]; ++e) {
-      const float w = a.w_rec[a.rec_t_edge[e]];
-      acc = acc + w * sprev[(size_t)a.rec_t_src[e] * 64 + b];
-    }
-  }
+  float acc = ordered_gather_sum(0.0f, a.in_t_ptr[j], a.in_t_ptr[j + 1], a.in_t_src, a.w_in_t, xt, b);
+  if (sprev) acc = ordered_gather_sum(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t, sprev, b);
   const float vp = vprev ? vprev[(size_t)j * 64 + b] : 0.0f;
   const float sp = sprev ? sprev[(size_t)j * 64 + b] : 0.0f;
   float v = a.beta * vp;
@@ -161,8 +182,7 @@ __global__ __launch_bounds__(256) void k_adjoint_step(BpttArgs a, uint32_t t, co
   const float *lu = a.lamu + (size_t)t * a.O * 64 + b;
   float ds = 0.0f;
   for (uint32_t o = 0; o < a.O; ++o) ds = ds + a.w_out[(size_t)i * a.O + o] * lu[(size_t)o * 64];
-  for (uint64_t e = a.rec_ptr[i]; e < a.rec_ptr[i + 1]; ++e)
-    ds = ds + a.w_rec[e] * lam_next[(size_t)a.rec_col[e] * 64 + b];
+  ds = ordered_gather_sum(ds, a.rec_ptr[i], a.rec_ptr[i + 1], a.rec_col, a.w_rec, lam_next, b);
   const float ln = lam_next[(size_t)i * 64 + b];
   if (!a.detach_reset) ds = ds - a.theta * ln;
   const float z = v_t[(size_t)i * 64 + b] - a.theta;
@@ -223,8 +243,18 @@ uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) 
 
 }  // namespace
 
+static void gather_weights(const BpttArgs &a, hipStream_t s) {
+  if (a.nnz_in)
+    hipLaunchKernelGGL(k_gather_t, dim3(blocks_for(a.nnz_in, 256)), dim3(256), 0, s, a.w_in, a.in_t_edge,
+                       a.w_in_t, a.nnz_in);
+  if (a.nnz_rec)
+    hipLaunchKernelGGL(k_gather_t, dim3(blocks_for(a.nnz_rec, 256)), dim3(256), 0, s, a.w_rec, a.rec_t_edge,
+                       a.w_rec_t, a.nnz_rec);
+}
+
 hipError_t bptt_forward(const BpttArgs &a, const float *x, const int32_t *labels, float *loss,
                         hipStream_t s) {
+  gather_weights(a, s);
   hipLaunchKernelGGL(k_transpose_x, dim3(blocks_for((uint64_t)a.T * a.C * 64, 256)), dim3(256), 0, s, x,
                      a.xt, a.B, a.T, a.C);
   const dim3 grid(blocks_for(a.H, 4));
@@ -246,6 +276,7 @@ hipError_t bptt_forward(const BpttArgs &a, const float *x, const int32_t *labels
 }
 
 hipError_t bptt_backward(const BpttArgs &a, const float *g_loss, hipStream_t s) {
+  gather_weights(a, s);
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(a.nnz_in, 256)), dim3(256), 0, s, a.g_w_in, a.nnz_in, 0.0f);
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(a.nnz_rec, 256)), dim3(256), 0, s, a.g_w_rec, a.nnz_rec, 0.0f);
   hipLaunchKernelGGL(k_fill, dim3(blocks_for((uint64_t)a.H * 64, 256)), dim3(256), 0, s, a.lam_carry,

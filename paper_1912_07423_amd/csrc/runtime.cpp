@@ -144,6 +144,7 @@ void validate_and_derive(snn_network *net) {
   const snn_params &p = net->prm;
   if (!(p.dt_ms > 0.0)) fail(SNN_E_INVALID, "dt_ms must be > 0");
   if (p.delay_steps < 1) fail(SNN_E_INVALID, "delay_steps must be >= 1");
+  if (p.synapse_weights > 1) fail(SNN_E_INVALID, "synapse_weights must be 0 (auto) or 1 (per synapse)");
   if (!(p.tau_m_ms > 0.0)) fail(SNN_E_INVALID, "tau_m_ms must be > 0");
   if (!(p.t_ref_ms >= 0.0)) fail(SNN_E_INVALID, "t_ref_ms must be >= 0");
   if (net->pops.empty()) fail(SNN_E_INVALID, "no populations");
@@ -334,9 +335,28 @@ void build(snn_network *net) {
   net->nnz_alloc = ((net->nnz + 3) & ~3ull) + 4;  // 16-byte groups of the atomic delivery
   net->col = dev_array<int32_t>(net, net->nnz_alloc);
   check(hipMemsetAsync(net->col, 0, net->nnz_alloc * 4, s), "clear col");
+  // Table I layout: when every projection from a source population carries the same
+  // weight, a synapse stores only its target and the weight is the source's
+  bool src_uniform = !net->plastic && net->prm.synapse_weights == 0;
+  std::vector<int32_t> pop_w(n_pops, 0);
+  for (uint32_t a = 0; a < n_pops && src_uniform; ++a) {
+    bool seen = false;
+    for (uint32_t q = pop_proj[a]; q < pop_proj[a + 1]; ++q) {
+      if (seen && gp[q].w_q16 != pop_w[a]) src_uniform = false;
+      pop_w[a] = gp[q].w_q16;
+      seen = true;
+    }
+  }
   if (net->plastic) {
     net->w_f32 = dev_array<float>(net, net->nnz_alloc);
     check(hipMemsetAsync(net->w_f32, 0, net->nnz_alloc * 4, s), "clear w");
+  } else if (src_uniform) {
+    net->w_src_host.assign(n, 0);
+    for (uint32_t a = 0; a < n_pops; ++a)
+      std::fill(net->w_src_host.begin() + net->pop_off[a], net->w_src_host.begin() + net->pop_off[a + 1], pop_w[a]);
+    net->w_src = dev_array<int32_t>(net, n);
+    check(hipMemcpyAsync(net->w_src, net->w_src_host.data(), (size_t)n * 4, hipMemcpyHostToDevice, s),
+          "copy source weights");
   } else {
     net->w_q16 = dev_array<int32_t>(net, net->nnz_alloc);
     check(hipMemsetAsync(net->w_q16, 0, net->nnz_alloc * 4, s), "clear w");
@@ -467,6 +487,7 @@ snn::DeliverArgs deliver_args(snn_network *net) {
   a.col = net->col;
   a.w_q16 = net->w_q16;
   a.w_f32 = net->w_f32;
+  a.w_src = net->w_src;
   a.q = queue_ref(net);
   a.input = net->input;
   a.tile_off = net->tile_off;
@@ -510,7 +531,7 @@ uint32_t atomic_grid(const snn_network *net) { return net->cu_count * 8; }
 hipError_t launch_delivery(snn_network *net, const snn::DeliverArgs &d, uint32_t steps) {
   if (net->delivery == SNN_DELIVERY_TILED)
     return snn::launch_deliver_tiled(d, steps, net->block, net->grid, net->stream);
-  return snn::launch_deliver_atomic(d, steps, atomic_grid(net), net->plastic, net->stream);
+  return snn::launch_deliver_atomic(d, steps, atomic_grid(net), net->stream);
 }
 
 hipEvent_t new_event() {
@@ -818,6 +839,7 @@ void build_batch(snn_batch *b, const snn_batch_member *members, uint32_t n_nets,
     d.row_ptr = m->row_ptr;
     d.col = m->col;
     d.w_q16 = m->w_q16;
+    d.w_src = m->w_src;
     d.v = m->v;
     d.ref = m->ref;
     d.input = m->input;
@@ -997,6 +1019,8 @@ void build_bptt(snn_bptt *p, const uint64_t *in_ptr, const int32_t *in_col, cons
   a.rec_ptr = upload(pool, std::vector<uint64_t>(rec_ptr, rec_ptr + d.n_hidden + 1));
   a.rec_col = upload(pool, std::vector<int32_t>(rec_col, rec_col + nnz_rec));
   const size_t HB = (size_t)a.H * 64, n_seg = (a.T + a.K - 1) / a.K;
+  a.w_in_t = dev_array<float>(pool, std::max<uint64_t>(1, nnz_in));
+  a.w_rec_t = dev_array<float>(pool, std::max<uint64_t>(1, nnz_rec));
   a.xt = dev_array<float>(pool, (size_t)a.T * a.C * 64);
   a.s = dev_array<float>(pool, (size_t)a.T * HB);
   a.vck = dev_array<float>(pool, n_seg * HB);
@@ -1125,6 +1149,7 @@ snn_status snn_get_info(snn_network *net, snn_info *info) {
     r.tiles = net->tiles;
     r.plastic = net->plastic ? 1u : 0u;
     r.raster_steps = net->raster_cap;
+    r.source_weights = net->w_src ? 1u : 0u;
     r.raster_words = net->words;
     r.table_len = net->table_len;
     r.nnz = net->nnz;
@@ -1203,8 +1228,9 @@ snn_status snn_get_row(snn_network *net, uint32_t i, int32_t *col, int32_t *w_q1
     if (*len == 0) return;
     if (col) check(hipMemcpyAsync(col, net->col + rp[0], *len * 4, hipMemcpyDeviceToHost, net->stream), "row");
     if (w_q16) {
-      if (!net->w_q16) fail(SNN_E_INVALID, "network has FP32 weights");
-      check(hipMemcpyAsync(w_q16, net->w_q16 + rp[0], *len * 4, hipMemcpyDeviceToHost, net->stream), "row");
+      if (net->w_src) std::fill(w_q16, w_q16 + *len, net->w_src_host[i]);
+      else if (!net->w_q16) fail(SNN_E_INVALID, "network has FP32 weights");
+      else check(hipMemcpyAsync(w_q16, net->w_q16 + rp[0], *len * 4, hipMemcpyDeviceToHost, net->stream), "row");
     }
     if (w_f32) {
       if (!net->w_f32) fail(SNN_E_INVALID, "network has Q16 weights");
@@ -1222,8 +1248,16 @@ snn_status snn_get_synapses(snn_network *net, uint64_t *row_ptr, int32_t *col, i
     if (row_ptr) check(hipMemcpyAsync(row_ptr, net->row_ptr, ((size_t)net->n + 1) * 8, hipMemcpyDeviceToHost, s), "copy");
     if (col) check(hipMemcpyAsync(col, net->col, net->nnz * 4, hipMemcpyDeviceToHost, s), "copy");
     if (w_q16) {
-      if (!net->w_q16) fail(SNN_E_INVALID, "network has FP32 weights");
-      check(hipMemcpyAsync(w_q16, net->w_q16, net->nnz * 4, hipMemcpyDeviceToHost, s), "copy");
+      if (net->w_src) {
+        std::vector<uint64_t> rp((size_t)net->n + 1);
+        check(hipMemcpyAsync(rp.data(), net->row_ptr, rp.size() * 8, hipMemcpyDeviceToHost, s), "copy");
+        sync(net);
+        for (uint32_t i = 0; i < net->n; ++i) std::fill(w_q16 + rp[i], w_q16 + rp[i + 1], net->w_src_host[i]);
+      } else if (!net->w_q16) {
+        fail(SNN_E_INVALID, "network has FP32 weights");
+      } else {
+        check(hipMemcpyAsync(w_q16, net->w_q16, net->nnz * 4, hipMemcpyDeviceToHost, s), "copy");
+      }
     }
     if (w_f32) {
       if (!net->w_f32) fail(SNN_E_INVALID, "network has Q16 weights");

@@ -91,8 +91,10 @@ struct UpdateArgs {
 struct DeliverArgs {
   const uint64_t *row_ptr;
   const int32_t *col;
-  const int32_t *w_q16;   // static networks
+  const int32_t *w_q16;   // static networks with a weight per synapse
   const float *w_f32;     // plastic networks
+  const int32_t *w_src;   // static networks with one weight per source population:
+                          // Q16 weight of every synapse of source i (no w_q16)
   QueueRef q;
   int32_t *input;
   const uint32_t *tile_off;  // [n][tiles + 1] relative tile boundaries of each row
@@ -123,6 +125,7 @@ struct StdpArgs {
 struct BatchNet {
   const uint64_t *row_ptr;
   const int32_t *col, *w_q16;
+  const int32_t *w_src;      // one weight per source neuron (then w_q16 is null)
   float *v;
   int32_t *ref;
   int32_t *input;            // [delay][n] Q16 accumulators, slot t mod delay
@@ -162,6 +165,7 @@ struct BpttArgs {
   const int32_t *rec_col;
   const float *w_in, *w_rec, *w_out;  // caller's weights: CSR order, CSR order, [H][O]
   float *g_w_in, *g_w_rec, *g_w_out;
+  float *w_in_t, *w_rec_t;     // weights gathered into transposed (per-target) order
   float *xt, *s, *vck, *vtmp, *vseg, *ro, *lamu, *lamv, *lam_carry, *m, *dm;
   int32_t *tmax;
 };
@@ -172,7 +176,7 @@ hipError_t bptt_backward(const BpttArgs &a, const float *g_loss, hipStream_t s);
 // kernel launchers (step.hip / generate.hip)
 hipError_t launch_update(const UpdateArgs &a, uint32_t steps, hipStream_t s);
 hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t grid,
-                                 bool plastic_w, hipStream_t s);
+                                 hipStream_t s);
 hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t block,
                                 uint32_t grid, hipStream_t s);
 constexpr uint32_t kTileGroupMax = 4;  // base tiles one tiled-delivery workgroup may own
@@ -229,6 +233,8 @@ struct snn_network {
   uint64_t *row_ptr = nullptr;
   int32_t *col = nullptr, *w_q16 = nullptr;
   float *w_f32 = nullptr;
+  int32_t *w_src = nullptr;             // per-source weights (Table I layout)
+  std::vector<int32_t> w_src_host;
   uint32_t *plast_rel = nullptr, *plast_len = nullptr;
   uint64_t *in_ptr = nullptr;
   int32_t *in_src = nullptr;

@@ -17,6 +17,8 @@
 //
 // Step bookkeeping lives on the device (Ctl) so that a captured HIP graph replays
 // correctly; no kernel waits on another workgroup of its own launch.
+#include <algorithm>
+
 #include "device_math.h"
 #include "snn_internal.h"
 
@@ -222,7 +224,10 @@ __device__ __forceinline__ void close_window(const DeliverArgs &a, uint64_t t0, 
 constexpr int kAtomicBlock = 256;
 constexpr int kAtomicWaves = kAtomicBlock / kWave;
 
-template <bool kPlasticW>
+constexpr int kWeightQ16 = 0, kWeightF32 = 1, kWeightSrc = 2;
+
+// kW: weights per synapse in Q16 (kWeightQ16) or FP32 (kWeightF32), or one per source (kWeightSrc)
+template <int kW>
 __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, uint32_t steps) {
   __shared__ uint32_t s_pre[kWave][kQueueGroups + 1];  // per step: sub-queue prefix
   __shared__ uint32_t s_slot[kWave];
@@ -265,10 +270,13 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
     if ((uint32_t)src >= a.n) continue;
     int32_t *in = a.input + (size_t)ring_add(in0, w, a.n_inbuf) * a.n;
     const uint64_t rs = a.row_ptr[src], re = a.row_ptr[src + 1];
+    const int32_t ws = kW == kWeightSrc ? a.w_src[src] : 0;
     for (uint64_t g = (rs >> 2) + lane; g < ((re + 3) >> 2); g += kWave) {
       const int4 c4 = reinterpret_cast<const int4 *>(a.col)[g];
       int32_t wv[4];
-      if constexpr (kPlasticW) {
+      if constexpr (kW == kWeightSrc) {
+        wv[0] = wv[1] = wv[2] = wv[3] = ws;
+      } else if constexpr (kW == kWeightF32) {
         const float4 f4 = reinterpret_cast<const float4 *>(a.w_f32)[g];
         wv[0] = __float2int_rn(f4.x * 65536.0f);
         wv[1] = __float2int_rn(f4.y * 65536.0f);
@@ -302,11 +310,13 @@ constexpr int kTiledUnroll = 8;
 
 // Loads kTiledUnroll elements of the flattened sub-row range, 64 apart, starting at
 // this lane's element `first`; `o` is the lane's current sub-row (monotone).
-template <int kU>
+// With source weights (kSrcW) only the target is loaded; the weight is the sub-row's
+// source weight held in LDS.
+template <int kU, bool kSrcW>
 __device__ __forceinline__ void tiled_load(const DeliverArgs &a, const uint64_t *s_lo,
-                                           const uint32_t *s_pre, uint32_t first, uint32_t end,
-                                           int32_t tile_lo, uint32_t &o, int32_t (&cv)[kU],
-                                           int32_t (&wv)[kU]) {
+                                           const uint32_t *s_pre, const int32_t *s_w, uint32_t first,
+                                           uint32_t end, int32_t tile_lo, uint32_t &o,
+                                           int32_t (&cv)[kU], int32_t (&wv)[kU]) {
 #pragma unroll
   for (int u = 0; u < kU; ++u) {
     const uint32_t idx = first + u * kWave;
@@ -316,7 +326,7 @@ __device__ __forceinline__ void tiled_load(const DeliverArgs &a, const uint64_t 
       while (s_pre[o + 1] <= idx) ++o;
       const uint64_t e = s_lo[o] + (idx - s_pre[o]);
       cv[u] = a.col[e];
-      wv[u] = a.w_q16[e];
+      wv[u] = kSrcW ? s_w[o] : a.w_q16[e];
     }
   }
 }
@@ -382,13 +392,14 @@ __device__ void make_schedule(const uint32_t *cnt, uint32_t steps, uint32_t tile
 // the range), a block scan lays the sub-rows end to end, and each wave streams a
 // contiguous share of the flattened edge range, 64 x kTiledUnroll elements at a time,
 // with the next batch's loads issued before the current batch's LDS atomics.
-template <int kBlock>
+template <int kBlock, bool kSrcW>
 __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_t steps) {
   extern __shared__ int32_t acc[];
   constexpr int kWaves = kBlock / kWave;
   constexpr int kU = kTiledUnroll;
   __shared__ uint64_t s_lo[kBlock];
   __shared__ uint32_t s_pre[kBlock + 1];
+  __shared__ int32_t s_w[kSrcW ? kBlock : 1];
   __shared__ uint32_t s_wave[kWaves];
   __shared__ uint32_t s_cnt[kWave];
   __shared__ uint32_t s_qpre[kWave][kQueueGroups + 1];
@@ -438,6 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
     // (1) sub-row bounds of this chunk's spikes
     uint32_t len = 0;
     uint64_t lo = 0;
+    int32_t ws = 0;
     if (threadIdx.x < mm) {
       const int32_t src = queue_entry(a.q, slot, qpre, c0 + threadIdx.x);
       if ((uint32_t)src < a.n) {
@@ -445,6 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
         const uint32_t o0 = to[tile_a], o1 = to[tile_b];
         lo = a.row_ptr[src] + o0;
         len = o1 - o0;
+        if (kSrcW) ws = a.w_src[src];
       }
     }
     // (2) block-wide exclusive scan of the sub-row lengths
@@ -461,6 +474,7 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
     if (threadIdx.x < mm) {
       s_pre[threadIdx.x] = pre;
       s_lo[threadIdx.x] = lo;
+      if (kSrcW) s_w[threadIdx.x] = ws;
     }
     if (threadIdx.x == kBlock - 1) s_pre[mm] = pre + len;
     __syncthreads();
@@ -478,10 +492,10 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
       }
       uint32_t o = lo_j;
       int32_t cv[kU], wv[kU], cn[kU], wn[kU];
-      tiled_load<kU>(a, s_lo, s_pre, beg + lane, end, (int32_t)tile_lo, o, cv, wv);
+      tiled_load<kU, kSrcW>(a, s_lo, s_pre, s_w, beg + lane, end, (int32_t)tile_lo, o, cv, wv);
       for (uint32_t b0 = beg; b0 < end; b0 += kWave * kU) {
         const uint32_t nb = b0 + kWave * kU;
-        if (nb < end) tiled_load<kU>(a, s_lo, s_pre, nb + lane, end, (int32_t)tile_lo, o, cn, wn);
+        if (nb < end) tiled_load<kU, kSrcW>(a, s_lo, s_pre, s_w, nb + lane, end, (int32_t)tile_lo, o, cn, wn);
 #pragma unroll
         for (int u = 0; u < kU; ++u)
           if (wv[u]) atomicAdd(&acc[cv[u] - (int32_t)tile_lo], wv[u]);
@@ -570,10 +584,10 @@ hipError_t launch_update(const UpdateArgs &a, uint32_t steps, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t grid,
-                                 bool plastic_w, hipStream_t s) {
-  if (plastic_w) k_deliver_atomic<true><<<grid, kAtomicBlock, 0, s>>>(a, steps);
-  else k_deliver_atomic<false><<<grid, kAtomicBlock, 0, s>>>(a, steps);
+hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t grid, hipStream_t s) {
+  if (a.w_f32) k_deliver_atomic<kWeightF32><<<grid, kAtomicBlock, 0, s>>>(a, steps);
+  else if (a.w_src) k_deliver_atomic<kWeightSrc><<<grid, kAtomicBlock, 0, s>>>(a, steps);
+  else k_deliver_atomic<kWeightQ16><<<grid, kAtomicBlock, 0, s>>>(a, steps);
   return hipGetLastError();
 }
 
@@ -584,15 +598,28 @@ hipError_t prepare_deliver_tiled(uint32_t block, size_t *max_dynamic_lds) {
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
-  const void *fn = block == 256   ? reinterpret_cast<const void *>(&k_deliver_tiled<256>)
-                   : block == 512 ? reinterpret_cast<const void *>(&k_deliver_tiled<512>)
-                                  : reinterpret_cast<const void *>(&k_deliver_tiled<1024>);
-  hipFuncAttributes attr{};
-  e = hipFuncGetAttributes(&attr, fn);
-  if (e != hipSuccess) return e;
-  const size_t dyn = (size_t)limit > attr.sharedSizeBytes ? (size_t)limit - attr.sharedSizeBytes : 0;
-  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-  if (e != hipSuccess) return e;
+  const void *fns[2];
+  if (block == 256) {
+    fns[0] = reinterpret_cast<const void *>(&k_deliver_tiled<256, false>);
+    fns[1] = reinterpret_cast<const void *>(&k_deliver_tiled<256, true>);
+  } else if (block == 512) {
+    fns[0] = reinterpret_cast<const void *>(&k_deliver_tiled<512, false>);
+    fns[1] = reinterpret_cast<const void *>(&k_deliver_tiled<512, true>);
+  } else {
+    fns[0] = reinterpret_cast<const void *>(&k_deliver_tiled<1024, false>);
+    fns[1] = reinterpret_cast<const void *>(&k_deliver_tiled<1024, true>);
+  }
+  size_t dyn = (size_t)limit;
+  for (const void *fn : fns) {
+    hipFuncAttributes attr{};
+    e = hipFuncGetAttributes(&attr, fn);
+    if (e != hipSuccess) return e;
+    dyn = std::min(dyn, (size_t)limit > attr.sharedSizeBytes ? (size_t)limit - attr.sharedSizeBytes : (size_t)0);
+  }
+  for (const void *fn : fns) {
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
+  }
   *max_dynamic_lds = dyn;
   return hipSuccess;
 }
@@ -603,10 +630,20 @@ hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t b
   const uint32_t floor_grid = steps * ((a.tiles + kMaxTileGroup - 1) / kMaxTileGroup);
   if (grid < floor_grid) grid = floor_grid;
   const size_t lds = (size_t)kMaxTileGroup * a.tile_size * sizeof(int32_t);
+  const bool src_w = a.w_src != nullptr;
   switch (block) {
-    case 256: k_deliver_tiled<256><<<grid, 256, lds, s>>>(a, steps); break;
-    case 512: k_deliver_tiled<512><<<grid, 512, lds, s>>>(a, steps); break;
-    default: k_deliver_tiled<1024><<<grid, 1024, lds, s>>>(a, steps); break;
+    case 256:
+      if (src_w) k_deliver_tiled<256, true><<<grid, 256, lds, s>>>(a, steps);
+      else k_deliver_tiled<256, false><<<grid, 256, lds, s>>>(a, steps);
+      break;
+    case 512:
+      if (src_w) k_deliver_tiled<512, true><<<grid, 512, lds, s>>>(a, steps);
+      else k_deliver_tiled<512, false><<<grid, 512, lds, s>>>(a, steps);
+      break;
+    default:
+      if (src_w) k_deliver_tiled<1024, true><<<grid, 1024, lds, s>>>(a, steps);
+      else k_deliver_tiled<1024, false><<<grid, 1024, lds, s>>>(a, steps);
+      break;
   }
   return hipGetLastError();
 }

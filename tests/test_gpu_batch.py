@@ -30,6 +30,9 @@ def _mixed_specs():
         W.brunel_fixed_out(n=999, k=250, delay_steps=5, rate_hz=30.0, seed=17),
         W.ei_er(300, 75, 0.1, 0.4, -4.5, v_bg_mV=11.0, delay_steps=2, seed=18),
     ]
+    mixed = W.ei_er(500, 125, 0.08, 0.3, -4.5, v_bg_mV=11.0, seed=19)
+    mixed["projs"][1]["w_mV"] = 0.45         # a weight per synapse for this member
+    specs.append(mixed)
     return specs
 
 

@@ -162,3 +162,22 @@ def test_invalid_parameters_rejected_gpu():
         g.raster_bits(0, 10)          # no longer held by the 4-step ring
     with pytest.raises(SnnError):
         g.raster_bits(8, 12)          # beyond the simulated steps
+
+
+@pytest.mark.parametrize("delivery", ["atomic", "tiled"])
+@pytest.mark.parametrize("synapse_weights", ["auto", "per_synapse"])
+def test_weight_layouts_identical(delivery, synapse_weights):
+    """One weight per source population (4 B per synapse) and a weight per synapse give
+    the oracle's results with either delivery kernel."""
+    spec = W.brunel_fixed_out(n=2500, k=250, delay_steps=15, steps=200)
+    print(f"[weights] {delivery} {synapse_weights}", flush=True)
+    rg, inf = _compare_run(spec, 200, delivery=delivery, synapse_weights=synapse_weights)
+    assert inf["source_weights"] == (1 if synapse_weights == "auto" else 0)
+
+
+def test_mixed_weights_of_one_source_population_use_per_synapse_weights():
+    spec = W.cuba_lif_4k(n_exc=900, n_inh=225, p=0.05, steps=400)
+    spec["projs"][1]["w_mV"] = 0.5          # E->I differs from E->E
+    rg, inf = _compare_run(spec, 400)
+    assert inf["source_weights"] == 0
+    assert rg.any()
