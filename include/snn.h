@@ -206,13 +206,36 @@ snn_status snn_get_profile(snn_network *net, snn_profile *prof);
 snn_status snn_reset_profile(snn_network *net);
 snn_status snn_sync(snn_network *net);
 
-/* Deliver a caller-given spike list with the network's delivery kernel, spread
- * round-robin over `steps` emission steps (0: the network's window) as one window,
- * into scratch accumulators, `reps` times; returns the mean kernel time in ms (HIP
- * events) and the events of one launch.  The network's own state is left unchanged.
- * Used to measure the delivery kernel alone at a chosen load. */
+/* Deliver a caller-given spike list with the network's delivery kernel as one window of
+ * `steps` emission steps (0: the network's window) into scratch accumulators, `reps`
+ * times; returns the mean kernel time in ms (HIP events) and the events of one launch.
+ * With step_counts == NULL the ids are spread round-robin over the steps; otherwise
+ * step w dequeues the next step_counts[w] ids (the counts sum to n_ids).  The network's
+ * own state is left unchanged.  Used to measure the delivery kernel alone at a chosen
+ * load. */
 snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_t n_ids,
-                             uint32_t steps, uint32_t reps, double *avg_ms, uint64_t *events);
+                             const uint32_t *step_counts, uint32_t steps, uint32_t reps,
+                             double *avg_ms, uint64_t *events);
+
+/* Switch a network's delivery variant (SNN_DELIVERY_*; AUTO picks by size and
+ * degree), its base tiles, workgroup size and grid (0 = auto), from the next step on.
+ * Rebuilds the tile boundaries; the simulation state is unchanged.  Plastic networks
+ * accept the atomic variant only.  SNN_E_INVALID for an impossible configuration. */
+snn_status snn_set_delivery(snn_network *net, uint32_t delivery, uint32_t tiles, uint32_t block,
+                            uint32_t grid);
+
+typedef struct {
+    uint32_t delivery, tiles, block, grid;  /* the configuration kept */
+    double ms_per_launch;                   /* its mean delivery time on the sample */
+    uint64_t events_per_launch;             /* synaptic events of the sample */
+} snn_delivery_tuning;
+
+/* Time the atomic variant and the tiled one over base tiles of about 3072, 4608 and
+ * 6144 targets x 512/1024-thread workgroups x 1, 2 and 3 workgroups per CU, each on the
+ * spikes of the network's latest window (taken from its raster), `reps` launches each;
+ * keep the fastest and return it.  The simulation state is unchanged.  SNN_E_STATE if
+ * fewer than `window` steps have run. */
+snn_status snn_autotune_delivery(snn_network *net, uint32_t reps, snn_delivery_tuning *chosen);
 
 void snn_destroy(snn_network *net);
 const char *snn_last_error(void);

@@ -82,6 +82,11 @@ class Profile(C.Structure):
                 ("stdp_launches", C.c_uint64)]
 
 
+class DeliveryTuning(C.Structure):
+    _fields_ = [("delivery", C.c_uint32), ("tiles", C.c_uint32), ("block", C.c_uint32),
+                ("grid", C.c_uint32), ("ms_per_launch", C.c_double), ("events_per_launch", C.c_uint64)]
+
+
 class BatchMember(C.Structure):
     _fields_ = [("params", C.POINTER(Params)), ("pops", C.POINTER(Population)),
                 ("proj", C.POINTER(Projection)), ("n_pops", C.c_uint32), ("n_proj", C.c_uint32)]
@@ -120,8 +125,10 @@ SIGNATURES = {
     "snn_get_profile": (C.c_int32, [C.c_void_p, C.POINTER(Profile)]),
     "snn_reset_profile": (C.c_int32, [C.c_void_p]),
     "snn_sync": (C.c_int32, [C.c_void_p]),
-    "snn_time_delivery": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
+    "snn_time_delivery": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_uint32,
                                       C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
+    "snn_set_delivery": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]),
+    "snn_autotune_delivery": (C.c_int32, [C.c_void_p, C.c_uint32, C.POINTER(DeliveryTuning)]),
     "snn_destroy": (None, [C.c_void_p]),
     "snn_last_error": (C.c_char_p, []),
     "snn_build_batch": (C.c_int32, [C.POINTER(BatchMember), C.c_uint32, C.c_uint32,

@@ -48,14 +48,20 @@ class RecurrentLIF:
         self.desc = d
         stream = torch.cuda.current_stream(self.device)
 
+        alloc_fn = torch.cuda.caching_allocator_alloc
+        delete_fn = torch.cuda.caching_allocator_delete
+
         def _alloc(nbytes, s, ctx):
             try:
-                return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+                return alloc_fn(int(nbytes), device, stream)
             except Exception:
                 return None
 
         def _free(ptr, nbytes, s, ctx):
-            torch.cuda.caching_allocator_delete(ptr)
+            try:
+                delete_fn(ptr)
+            except Exception:
+                pass  # interpreter shutdown: the process is releasing the device anyway
 
         self._keep = (L.ALLOC_FN(_alloc), L.FREE_FN(_free))
         self._alloc = L.Allocator(self._keep[0], self._keep[1], None)

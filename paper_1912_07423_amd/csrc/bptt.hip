@@ -54,31 +54,67 @@ __global__ void k_gather_t(const float *w, const uint32_t *edge, float *w_t, uin
   if (e < nnz) w_t[e] = w[edge[e]];
 }
 
-// sum += w[e] * val[src[e] * 64 + b] over [e0, e1), one term at a time in edge order;
-// the (wave-uniform) sources and weights of kChunk edges, then their presynaptic values,
-// are loaded before the chunk's terms are added, so the loads overlap.
+// sum += w[e] * val[src[e] * 64 + b] over [e0, e1), one term at a time in edge order.
+// The (wave-uniform) sources and weights of the next kChunk edges are fetched while the
+// presynaptic values of the current chunk are in flight, so each chunk costs about one
+// memory round trip.
 constexpr int kChunk = 16;
 __device__ __forceinline__ float ordered_gather_sum(float acc, uint64_t e0, uint64_t e1, const int32_t *src,
                                                     const float *w, const float *val, uint32_t b) {
   uint64_t e = e0;
-  for (; e + kChunk <= e1; e += kChunk) {
-    int32_t sr[kChunk];
-    float wv[kChunk], xv[kChunk];
+  int32_t sr[kChunk];
+  float wv[kChunk];
+  if (e + kChunk <= e1) {
 #pragma unroll
     for (int u = 0; u < kChunk; ++u) {
       sr[u] = src[e + u];
       wv[u] = w[e + u];
     }
+  }
+  while (e + kChunk <= e1) {
+    float xv[kChunk];
 #pragma unroll
     for (int u = 0; u < kChunk; ++u) xv[u] = val[(size_t)sr[u] * 64 + b];
+    int32_t sn[kChunk];
+    float wn[kChunk];
+    const bool more = e + 2 * kChunk <= e1;
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        sn[u] = src[e + kChunk + u];
+        wn[u] = w[e + kChunk + u];
+      }
+    }
 #pragma unroll
     for (int u = 0; u < kChunk; ++u) acc = acc + wv[u] * xv[u];
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        sr[u] = sn[u];
+        wv[u] = wn[u];
+      }
+    }
+    e += kChunk;
   }
   for (; e < e1; ++e) acc = acc + w[e] * val[(size_t)src[e] * 64 + b];
   return acc;
 }
 
-// One step t of the hidden layer: one wavefront per hidden neuron j, lane = batch.
+// Input-projection current of every step: iin[t][j][b] = sum over j's input in-edges,
+// sources ascending, from 0 -- the first part of the hidden current in its defined order.
+// It does not depend on the recurrent state, so all steps run in parallel (a wavefront
+// per (t, j)).
+__global__ __launch_bounds__(256) void k_input_current(BpttArgs a) {
+  const uint64_t w = (uint64_t)blockIdx.x * 4 + threadIdx.x / kWave;
+  if (w >= (uint64_t)a.T * a.H) return;
+  const uint32_t t = (uint32_t)(w / a.H), j = (uint32_t)(w % a.H);
+  const uint32_t b = lane_id();
+  const float *xt = a.xt + (size_t)t * a.C * 64;
+  a.iin[w * 64 + b] = ordered_gather_sum(0.0f, a.in_t_ptr[j], a.in_t_ptr[j + 1], a.in_t_src, a.w_in_t, xt, b);
+}
+
+// One step t of the hidden layer: one wavefront per hidden neuron j, lane = batch.  The
+// current continues the input part with j's recurrent in-edges (sources ascending).
 // vprev/sprev are step t-1 (nullptr at t = 0).  Writes v_out[j][b] and, if s_out is
 // set, s_out[j][b].
 __global__ __launch_bounds__(256) void k_hidden_step(BpttArgs a, uint32_t t, const float *vprev,
@@ -86,8 +122,7 @@ __global__ __launch_bounds__(256) void k_hidden_step(BpttArgs a, uint32_t t, con
   const uint32_t j = blockIdx.x * 4 + threadIdx.x / kWave;
   if (j >= a.H) return;
   const uint32_t b = lane_id();
-  const float *xt = a.xt + (size_t)t * a.C * 64;
-  float acc = ordered_gather_sum(0.0f, a.in_t_ptr[j], a.in_t_ptr[j + 1], a.in_t_src, a.w_in_t, xt, b);
+  float acc = a.iin[((size_t)t * a.H + j) * 64 + b];
   if (sprev) acc = ordered_gather_sum(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t, sprev, b);
   const float vp = vprev ? vprev[(size_t)j * 64 + b] : 0.0f;
   const float sp = sprev ? sprev[(size_t)j * 64 + b] : 0.0f;
@@ -98,7 +133,8 @@ __global__ __launch_bounds__(256) void k_hidden_step(BpttArgs a, uint32_t t, con
   if (s_out) s_out[(size_t)j * 64 + b] = spike_fn(v - a.theta, a.slope, a.smooth != 0);
 }
 
-// Readout drive of every step: ro[t][o][b] = sum_i s[t][i][b] w_out[i][o], ascending i.
+// Readout drive of every step: ro[t][o][b] = sum_i s[t][i][b] w_out[i][o], ascending i;
+// the loads of 16 consecutive i are issued before their terms are added in order.
 __global__ void k_readout_drive(BpttArgs a, float *ro) {
   const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (uint64_t)a.T * a.O * 64) return;
@@ -106,8 +142,20 @@ __global__ void k_readout_drive(BpttArgs a, float *ro) {
   const uint64_t to = idx >> 6;
   const uint32_t o = (uint32_t)(to % a.O), t = (uint32_t)(to / a.O);
   const float *st = a.s + (size_t)t * a.H * 64 + b;
+  const float *wo = a.w_out + o;
   float acc = 0.0f;
-  for (uint32_t i = 0; i < a.H; ++i) acc = acc + st[(size_t)i * 64] * a.w_out[(size_t)i * a.O + o];
+  uint32_t i = 0;
+  for (; i + 16 <= a.H; i += 16) {
+    float sv[16], wv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      sv[u] = st[(size_t)(i + u) * 64];
+      wv[u] = wo[(size_t)(i + u) * a.O];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc = acc + sv[u] * wv[u];
+  }
+  for (; i < a.H; ++i) acc = acc + st[(size_t)i * 64] * wo[(size_t)i * a.O];
   ro[idx] = acc;
 }
 
@@ -189,19 +237,21 @@ __global__ __launch_bounds__(256) void k_adjoint_step(BpttArgs a, uint32_t t, co
   lam_out[(size_t)i * 64 + b] = a.beta * ln + surrogate(z, a.slope, a.smooth != 0) * ds;
 }
 
-// Gradients of the sparse weights over one segment [t0, t0 + len): one wavefront per
-// target j; its membrane adjoints for the segment stay in registers; every in-edge is
-// reduced over (t, b) and added to its own gradient entry.
+// Gradients of the sparse weights over one segment [t0, t0 + len): a workgroup per
+// target j whose wavefronts share its in-edges; each holds j's membrane adjoints for the
+// segment in registers, reduces an in-edge over (t, b) and adds the result to the
+// edge's own gradient entry (one owner per entry).
 constexpr int kSegMax = 32;
+constexpr uint32_t kGradSplit = 4;  // wavefronts sharing one target's in-edges
 __global__ __launch_bounds__(256) void k_grad_sparse(BpttArgs a, uint32_t t0, uint32_t len,
                                                      const float *lam_seg) {
-  const uint32_t j = blockIdx.x * 4 + threadIdx.x / kWave;
-  if (j >= a.H) return;
+  const uint32_t j = blockIdx.x;
+  const uint32_t part = threadIdx.x / kWave;
   const uint32_t b = lane_id();
   float lam[kSegMax];
 #pragma unroll
   for (int k = 0; k < kSegMax; ++k) lam[k] = k < (int)len ? lam_seg[((size_t)k * a.H + j) * 64 + b] : 0.0f;
-  for (uint64_t e = a.in_t_ptr[j]; e < a.in_t_ptr[j + 1]; ++e) {
+  for (uint64_t e = a.in_t_ptr[j] + part; e < a.in_t_ptr[j + 1]; e += kGradSplit) {
     const float *xs = a.xt + (size_t)a.in_t_src[e] * 64 + b;
     float acc = 0.0f;
 #pragma unroll
@@ -210,7 +260,7 @@ __global__ __launch_bounds__(256) void k_grad_sparse(BpttArgs a, uint32_t t0, ui
     acc = wave_sum(acc);
     if (b == 0) a.g_w_in[a.in_t_edge[e]] += acc;
   }
-  for (uint64_t e = a.rec_t_ptr[j]; e < a.rec_t_ptr[j + 1]; ++e) {
+  for (uint64_t e = a.rec_t_ptr[j] + part; e < a.rec_t_ptr[j + 1]; e += kGradSplit) {
     const float *ss = a.s + (size_t)a.rec_t_src[e] * 64 + b;
     float acc = 0.0f;
 #pragma unroll
@@ -222,16 +272,23 @@ __global__ __launch_bounds__(256) void k_grad_sparse(BpttArgs a, uint32_t t0, ui
 }
 
 // Gradient of the dense readout weights over the whole sequence: one wavefront per
-// hidden neuron i and output o.
+// hidden neuron i and output o; four partial sums keep loads of later steps in flight.
 __global__ __launch_bounds__(256) void k_grad_out(BpttArgs a) {
   const uint32_t w = blockIdx.x * 4 + threadIdx.x / kWave;
   if (w >= a.H * a.O) return;
   const uint32_t i = w / a.O, o = w % a.O, b = lane_id();
-  float acc = 0.0f;
-  for (uint32_t t = 0; t < a.T; ++t)
-    acc += a.s[((size_t)t * a.H + i) * 64 + b] * a.lamu[((size_t)t * a.O + o) * 64 + b];
-  acc = wave_sum(acc);
-  if (b == 0) a.g_w_out[(size_t)i * a.O + o] = acc;
+  const float *sp = a.s + (size_t)i * 64 + b;
+  const float *lp = a.lamu + (size_t)o * 64 + b;
+  const size_t ss = (size_t)a.H * 64, ls = (size_t)a.O * 64;
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  uint32_t t = 0;
+  for (; t + 4 <= a.T; t += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += sp[(t + u) * ss] * lp[(t + u) * ls];
+  }
+  for (; t < a.T; ++t) acc[0] += sp[t * ss] * lp[t * ls];
+  const float sum = wave_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
+  if (b == 0) a.g_w_out[(size_t)i * a.O + o] = sum;
 }
 
 __global__ void k_fill(float *p, uint64_t n, float v) {
@@ -257,6 +314,7 @@ hipError_t bptt_forward(const BpttArgs &a, const float *x, const int32_t *labels
   gather_weights(a, s);
   hipLaunchKernelGGL(k_transpose_x, dim3(blocks_for((uint64_t)a.T * a.C * 64, 256)), dim3(256), 0, s, x,
                      a.xt, a.B, a.T, a.C);
+  hipLaunchKernelGGL(k_input_current, dim3(blocks_for((uint64_t)a.T * a.H, 4)), dim3(256), 0, s, a);
   const dim3 grid(blocks_for(a.H, 4));
   float *vprev = nullptr;
   for (uint32_t t = 0; t < a.T; ++t) {
@@ -302,7 +360,7 @@ hipError_t bptt_backward(const BpttArgs &a, const float *g_loss, hipStream_t s) 
       hipLaunchKernelGGL(k_adjoint_step, grid, dim3(256), 0, s, a, t0 + (uint32_t)k,
                          a.vseg + (size_t)k * a.H * 64, lam_next, a.lamv + (size_t)k * a.H * 64);
     }
-    hipLaunchKernelGGL(k_grad_sparse, grid, dim3(256), 0, s, a, t0, len, a.lamv);
+    hipLaunchKernelGGL(k_grad_sparse, dim3(a.H), dim3(kWave * kGradSplit), 0, s, a, t0, len, a.lamv);
     // lamV of the segment's first step is the next (earlier) segment's lamV_{t+1}
     (void)hipMemcpyAsync(a.lam_carry, a.lamv, (size_t)a.H * 64 * 4, hipMemcpyDeviceToDevice, s);
   }

@@ -296,21 +296,6 @@ __global__ __launch_bounds__(kGenBlock) void k_init_neurons(float *v, int32_t *r
   ref[i] = 0;
 }
 
-// A caller-given spike list as the queues of slots 0..steps-1: id k goes to slot
-// k % steps, and within the slot's kQueueGroups sub-queues round-robin.
-__global__ __launch_bounds__(kGenBlock) void k_scatter_ids(const uint32_t *ids, uint32_t n_ids,
-                                                           uint32_t steps, QueueRef q) {
-  const uint32_t k = blockIdx.x * kGenBlock + threadIdx.x;
-  if (k < n_ids) {
-    const uint32_t slot = k % steps, r = k / steps;
-    q.ids[(size_t)slot * q.stride + (r % kQueueGroups) * q.group_cap + r / kQueueGroups] = (int32_t)ids[k];
-  }
-  if (k < steps * kQueueGroups) {
-    const uint32_t slot = k / kQueueGroups, g = k % kQueueGroups;
-    const uint32_t in_slot = n_ids / steps + (slot < n_ids % steps ? 1u : 0u);
-    q.qlen[k * kQlenStride] = in_slot / kQueueGroups + (g < in_slot % kQueueGroups ? 1u : 0u);
-  }
-}
 
 uint32_t row_grid(uint32_t n) {
   const uint32_t blocks = (n + kGenWavesPerBlock - 1) / kGenWavesPerBlock;
@@ -376,12 +361,5 @@ hipError_t launch_init_neurons(float *v, int32_t *ref, uint32_t n, uint32_t key0
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_ids(const uint32_t *ids, uint32_t n_ids, uint32_t steps,
-                              const QueueRef &q, hipStream_t s) {
-  const uint32_t work = n_ids > steps * kQueueGroups ? n_ids : steps * kQueueGroups;
-  const uint32_t blocks = (work + kGenBlock - 1) / kGenBlock;
-  k_scatter_ids<<<blocks, kGenBlock, 0, s>>>(ids, n_ids, steps, q);
-  return hipGetLastError();
-}
 
 }  // namespace snn

@@ -252,21 +252,24 @@ void choose_delivery(snn_network *net) {
   if (net->delivery == SNN_DELIVERY_TILED) {
     const uint32_t b = net->prm.block;
     if (b != 0 && b != 256 && b != 512 && b != 1024) fail(SNN_E_INVALID, "block must be 256, 512 or 1024");
-    net->block = b ? b : 512;
+    net->block = b ? b : 1024;
     // A workgroup accumulates a range of up to kTileGroupMax base tiles in LDS.  The
     // largest base tile is set by the workgroup LDS limit (160 KB on gfx950, less the
-    // kernel's static arrays); the default base tile is kDefaultTile targets.
+    // kernel's static arrays); the default base tile is kDefaultTile targets (the fastest
+    // of the launch-shape sweep on the 1e9-synapse network, with 1,024-thread workgroups
+    // and one per CU).
     size_t lds_dyn = 0;
     check(snn::prepare_deliver_tiled(net->block, &lds_dyn), "tiled delivery LDS limit");
     const uint32_t tile_cap = (uint32_t)(lds_dyn / 4 / snn::kTileGroupMax);
-    constexpr uint32_t kDefaultTile = 3072;
+    constexpr uint32_t kDefaultTile = 4608;
     const uint32_t min_tiles = (net->n + tile_cap - 1) / tile_cap;
     uint32_t tiles = net->prm.tiles ? net->prm.tiles : (net->n + kDefaultTile - 1) / kDefaultTile;
     tiles = std::max(std::min(tiles, std::max(1u, net->n / 16u)), min_tiles);
     net->tile_size = (net->n + tiles - 1) / tiles;
     net->tiles = (net->n + net->tile_size - 1) / net->tile_size;
     if (net->tile_size > tile_cap) fail(SNN_E_INVALID, "tile too large for LDS");
-    net->grid = net->prm.grid ? net->prm.grid : 2 * net->cu_count;  // two resident per CU
+    // one 1,024-thread workgroup per CU (the kernel's registers allow one resident)
+    net->grid = net->prm.grid ? net->prm.grid : net->cu_count * (net->block == 1024 ? 1u : 2u);
   } else if (net->delivery == SNN_DELIVERY_ATOMIC) {
     net->tiles = 1;
     net->tile_size = net->n;
@@ -693,6 +696,190 @@ void copy_raster_rows(snn_network *net, uint64_t t0, uint64_t t1, uint64_t *out)
 }
 
 
+
+// ---- delivery reconfiguration, timing and autotuning --------------------------------
+void dev_free(snn_network *net, void *p) {
+  for (size_t k = 0; k < net->allocs.size(); ++k)
+    if (net->allocs[k].p == p) {
+      if (net->has_alloc) net->alloc.free(p, net->allocs[k].bytes, (void *)net->stream, net->alloc.ctx);
+      else (void)hipFree(p);
+      net->device_bytes -= net->allocs[k].bytes;
+      net->allocs.erase(net->allocs.begin() + (std::ptrdiff_t)k);
+      return;
+    }
+}
+
+void build_tile_offsets(snn_network *net) {
+  if (net->delivery != SNN_DELIVERY_TILED) return;
+  net->tile_off = dev_array<uint32_t>(net, (size_t)net->n * (net->tiles + 1));
+  check(snn::launch_tile_offsets(net->row_ptr, net->col, net->n, net->tiles, net->tile_size, net->tile_off,
+                                 net->stream),
+        "tile offsets");
+  check(hipStreamSynchronize(net->stream), "sync after tile offsets");
+}
+
+// A new delivery variant / tiling / launch shape, taking effect at the next window (the
+// input ring holds exactly the pending arrivals at every window boundary, whichever
+// variant filled it).
+void set_delivery(snn_network *net, uint32_t delivery, uint32_t tiles, uint32_t block, uint32_t grid) {
+  if (delivery > SNN_DELIVERY_TILED) fail(SNN_E_INVALID, "unknown delivery variant");
+  if (net->plastic && delivery == SNN_DELIVERY_TILED) fail(SNN_E_INVALID, "tiled delivery needs static weights");
+  check(hipStreamSynchronize(net->stream), "sync");
+  net->prm.delivery = delivery;
+  net->prm.tiles = tiles;
+  net->prm.block = block;
+  net->prm.grid = grid;
+  net->delivery = net->plastic ? SNN_DELIVERY_ATOMIC : delivery;
+  choose_delivery(net);
+  if (net->tile_off) {
+    dev_free(net, net->tile_off);
+    net->tile_off = nullptr;
+  }
+  build_tile_offsets(net);
+  if (net->graph) {
+    (void)hipGraphExecDestroy(net->graph);
+    net->graph = nullptr;
+  }
+}
+
+// Mean time (ms) of one delivery launch over one window whose step w dequeues
+// per_step[w], with scratch queues, accumulators and control block (the network's own
+// state is untouched); *events = synaptic events of one launch.
+double time_delivery(snn_network *net, const std::vector<std::vector<uint32_t>> &per_step, uint32_t reps,
+                     uint64_t *events) {
+  const uint32_t steps = (uint32_t)per_step.size();
+  if (steps == 0 || steps > net->window) fail(SNN_E_INVALID, "steps exceeds the network's window");
+  if (reps == 0) reps = 1;
+  hipStream_t s = net->stream;
+  // queue slots 0..steps-1, laid out as the update kernel appends: position p of a step
+  // goes to sub-queue p mod kQueueGroups at index p / kQueueGroups
+  std::vector<int32_t> queue((size_t)steps * net->queue_stride, 0);
+  std::vector<uint32_t> qlen((size_t)net->slots * snn::kQueueGroups * snn::kQlenStride, 0u);
+  for (uint32_t w = 0; w < steps; ++w) {
+    if (per_step[w].size() > net->n) fail(SNN_E_INVALID, "more ids in a step than neurons");
+    for (size_t p = 0; p < per_step[w].size(); ++p) {
+      const uint32_t id = per_step[w][p];
+      if (id >= net->n) fail(SNN_E_INVALID, "id out of range");
+      const uint32_t g = (uint32_t)(p % snn::kQueueGroups), pos = (uint32_t)(p / snn::kQueueGroups);
+      queue[(size_t)w * net->queue_stride + (size_t)g * net->group_cap + pos] = (int32_t)id;
+      qlen[((size_t)w * snn::kQueueGroups + g) * snn::kQlenStride]++;
+    }
+  }
+  std::vector<snn_network::Alloc> mark(net->allocs);
+  const uint64_t bytes_before = net->device_bytes;
+  double ms_out = 0.0;
+  try {
+    int32_t *d_queue = dev_array<int32_t>(net, (size_t)net->slots * net->queue_stride);
+    uint32_t *d_qlen = dev_array<uint32_t>(net, qlen.size());
+    int32_t *input = dev_array<int32_t>(net, (size_t)net->n_inbuf * net->n);
+    snn::Ctl *ctl = dev_array<snn::Ctl>(net, 1);
+    check(hipMemcpyAsync(d_queue, queue.data(), queue.size() * 4, hipMemcpyHostToDevice, s), "queue");
+    check(hipMemcpyAsync(d_qlen, qlen.data(), qlen.size() * 4, hipMemcpyHostToDevice, s), "queue lengths");
+    check(hipMemsetAsync(input, 0, (size_t)net->n_inbuf * net->n * 4, s), "clear");
+    // slots 0..steps-1 are the queues delivered by a window starting at t0 when
+    // t0 + n_inbuf - delay = 0 (mod slots)
+    std::vector<snn::Ctl> c0(1);
+    std::memset(c0.data(), 0, sizeof(snn::Ctl));
+    c0[0].t_deliver = (uint64_t)net->delay - net->n_inbuf;
+    check(hipMemcpyAsync(ctl, c0.data(), sizeof(snn::Ctl), hipMemcpyHostToDevice, s), "ctl");
+    check(hipStreamSynchronize(s), "sync");
+    snn::DeliverArgs d = deliver_args(net);
+    d.q = snn::QueueRef{d_queue, d_qlen, net->queue_stride, net->group_cap};
+    d.input = input;
+    d.ctl = ctl;
+    d.advance = 0;
+    check(launch_delivery(net, d, steps), "warm-up delivery");
+    net->prof_last = nullptr;
+    hipEvent_t a = new_event(), b = new_event();
+    check(hipEventRecord(a, s), "event");
+    for (uint32_t r = 0; r < reps; ++r) check(launch_delivery(net, d, steps), "delivery");
+    check(hipEventRecord(b, s), "event");
+    check(hipEventSynchronize(b), "event sync");
+    float ms = 0.f;
+    check(hipEventElapsedTime(&ms, a, b), "elapsed");
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    std::vector<snn::Ctl> c1(1);
+    check(hipMemcpy(c1.data(), ctl, sizeof(snn::Ctl), hipMemcpyDeviceToHost), "ctl");
+    ms_out = ms / reps;
+    if (events) *events = sum_ctl(c1[0]).events / (reps + 1);
+  } catch (...) {
+    for (size_t k = mark.size(); k < net->allocs.size(); ++k) {
+      if (net->has_alloc) net->alloc.free(net->allocs[k].p, net->allocs[k].bytes, (void *)s, net->alloc.ctx);
+      else (void)hipFree(net->allocs[k].p);
+    }
+    net->allocs.resize(mark.size());
+    net->device_bytes = bytes_before;
+    throw;
+  }
+  for (size_t k = mark.size(); k < net->allocs.size(); ++k) {
+    if (net->has_alloc) net->alloc.free(net->allocs[k].p, net->allocs[k].bytes, (void *)s, net->alloc.ctx);
+    else (void)hipFree(net->allocs[k].p);
+  }
+  net->allocs.resize(mark.size());
+  net->device_bytes = bytes_before;
+  return ms_out;
+}
+
+// Times every candidate delivery configuration on the spikes of the latest window (read
+// from the raster ring) and keeps the fastest.
+snn_delivery_tuning autotune_delivery(snn_network *net, uint32_t reps) {
+  const uint32_t W = net->window;
+  if (net->t_host < W) fail(SNN_E_STATE, "run at least one window before autotuning the delivery");
+  if (net->raster_cap < W) fail(SNN_E_STATE, "the raster ring holds less than one window");
+  sync(net);
+  std::vector<uint64_t> rows((size_t)W * net->words);
+  raster_range_check(net, net->t_host - W, net->t_host);
+  copy_raster_rows(net, net->t_host - W, net->t_host, rows.data());
+  std::vector<std::vector<uint32_t>> per_step(W);
+  for (uint32_t w = 0; w < W; ++w)
+    for (uint32_t k = 0; k < net->words; ++k) {
+      uint64_t m = rows[(size_t)w * net->words + k];
+      while (m) {
+        const uint32_t b = (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        per_step[w].push_back(k * 64 + b);
+      }
+    }
+  struct Cand {
+    uint32_t delivery, tiles, block, grid;
+  };
+  std::vector<Cand> cands;
+  cands.push_back({SNN_DELIVERY_ATOMIC, 0, 0, 0});
+  if (!net->plastic && net->n >= 1024) {
+    for (uint32_t tile : {3072u, 4608u, 6144u})
+      for (uint32_t block : {512u, 1024u})
+        for (uint32_t grid : {net->cu_count, 2 * net->cu_count, 3 * net->cu_count})
+          cands.push_back({SNN_DELIVERY_TILED, std::max(1u, (net->n + tile - 1) / tile), block, grid});
+  }
+  const Cand keep{net->delivery, net->prm.tiles, net->prm.block, net->prm.grid};
+  snn_delivery_tuning best{};
+  best.ms_per_launch = 1e300;
+  for (const Cand &c : cands) {
+    try {
+      set_delivery(net, c.delivery, c.tiles, c.block, c.grid);
+    } catch (const Failure &) {
+      continue;  // e.g. a tile larger than the LDS allows
+    }
+    uint64_t ev = 0;
+    const double ms = time_delivery(net, per_step, reps, &ev);
+    if (ms < best.ms_per_launch) {
+      best.ms_per_launch = ms;
+      best.delivery = net->delivery;
+      best.tiles = net->tiles;
+      best.block = net->block;
+      best.grid = net->grid;
+      best.events_per_launch = ev;
+    }
+  }
+  if (best.ms_per_launch == 1e300) {
+    set_delivery(net, keep.delivery, keep.tiles, keep.block, keep.grid);
+    fail(SNN_E_STATE, "no delivery configuration could be timed");
+  }
+  set_delivery(net, best.delivery, best.tiles, best.block, best.grid);
+  return best;
+}
+
 // ---- batched form ----------------------------------------------------------------
 }  // namespace
 
@@ -1022,6 +1209,7 @@ void build_bptt(snn_bptt *p, const uint64_t *in_ptr, const int32_t *in_col, cons
   a.w_in_t = dev_array<float>(pool, std::max<uint64_t>(1, nnz_in));
   a.w_rec_t = dev_array<float>(pool, std::max<uint64_t>(1, nnz_rec));
   a.xt = dev_array<float>(pool, (size_t)a.T * a.C * 64);
+  a.iin = dev_array<float>(pool, (size_t)a.T * HB);
   a.s = dev_array<float>(pool, (size_t)a.T * HB);
   a.vck = dev_array<float>(pool, n_seg * HB);
   a.vtmp = dev_array<float>(pool, 2 * HB);
@@ -1300,64 +1488,45 @@ snn_status snn_reset_profile(snn_network *net) {
 }
 
 snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_t n_ids,
-                             uint32_t steps, uint32_t reps, double *avg_ms, uint64_t *events) {
+                             const uint32_t *step_counts, uint32_t steps, uint32_t reps,
+                             double *avg_ms, uint64_t *events) {
   return guarded([&] {
     if (!net || (!ids_host && n_ids) || !avg_ms) fail(SNN_E_INVALID, "null argument");
     refuse_member(net);
     if (steps == 0) steps = net->window;
     if (steps > net->window) fail(SNN_E_INVALID, "steps exceeds the network's window");
-    if (n_ids > (uint64_t)net->n * steps) fail(SNN_E_INVALID, "more ids than the queues hold");
-    for (uint32_t k = 0; k < n_ids; ++k)
-      if (ids_host[k] >= net->n) fail(SNN_E_INVALID, "id out of range");
-    if (reps == 0) reps = 1;
-    hipStream_t s = net->stream;
-    // scratch FIFO, accumulators and control block; the network's state is untouched
-    std::vector<snn_network::Alloc> mark(net->allocs);
-    const uint64_t bytes_before = net->device_bytes;
-    uint32_t *ids = dev_array<uint32_t>(net, std::max<uint32_t>(n_ids, 1));
-    int32_t *queue = dev_array<int32_t>(net, (size_t)net->slots * net->queue_stride);
-    uint32_t *qlen = dev_array<uint32_t>(net, (size_t)net->slots * snn::kQueueGroups * snn::kQlenStride);
-    int32_t *input = dev_array<int32_t>(net, (size_t)net->n_inbuf * net->n);
-    snn::Ctl *ctl = dev_array<snn::Ctl>(net, 1);
-    check(hipMemsetAsync(qlen, 0, (size_t)net->slots * snn::kQueueGroups * snn::kQlenStride * 4, s), "clear");
-    check(hipMemsetAsync(input, 0, (size_t)net->n_inbuf * net->n * 4, s), "clear");
-    if (n_ids) check(hipMemcpyAsync(ids, ids_host, (size_t)n_ids * 4, hipMemcpyHostToDevice, s), "ids");
-    const snn::QueueRef sq{queue, qlen, net->queue_stride, net->group_cap};
-    check(snn::launch_scatter_ids(ids, n_ids, steps, sq, s), "scatter ids");
-    // slots 0..steps-1 are the queues delivered by a window starting at t0 when
-    // t0 + n_inbuf - delay = 0 (mod slots)
-    std::vector<snn::Ctl> c0(1);
-    std::memset(c0.data(), 0, sizeof(snn::Ctl));
-    c0[0].t_deliver = (uint64_t)net->delay - net->n_inbuf;
-    check(hipMemcpyAsync(ctl, c0.data(), sizeof(snn::Ctl), hipMemcpyHostToDevice, s), "ctl");
-    check(hipStreamSynchronize(s), "sync");
-    snn::DeliverArgs d = deliver_args(net);
-    d.q = sq;
-    d.input = input;
-    d.ctl = ctl;
-    d.advance = 0;
-    check(launch_delivery(net, d, steps), "warm-up delivery");
-    net->prof_last = nullptr;
-    hipEvent_t a = new_event(), b = new_event();
-    check(hipEventRecord(a, s), "event");
-    for (uint32_t r = 0; r < reps; ++r) check(launch_delivery(net, d, steps), "delivery");
-    check(hipEventRecord(b, s), "event");
-    check(hipEventSynchronize(b), "event sync");
-    float ms = 0.f;
-    check(hipEventElapsedTime(&ms, a, b), "elapsed");
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    std::vector<snn::Ctl> c1(1);
-    check(hipMemcpy(c1.data(), ctl, sizeof(snn::Ctl), hipMemcpyDeviceToHost), "ctl");
-    *avg_ms = ms / reps;
-    if (events) *events = sum_ctl(c1[0]).events / (reps + 1);
-    // return the scratch memory
-    for (size_t k = mark.size(); k < net->allocs.size(); ++k) {
-      if (net->has_alloc) net->alloc.free(net->allocs[k].p, net->allocs[k].bytes, (void *)s, net->alloc.ctx);
-      else (void)hipFree(net->allocs[k].p);
+    std::vector<std::vector<uint32_t>> per_step(steps);
+    if (step_counts) {
+      uint64_t k = 0;
+      for (uint32_t w = 0; w < steps; ++w) {
+        if (k + step_counts[w] > n_ids) fail(SNN_E_INVALID, "step counts exceed the ids");
+        per_step[w].assign(ids_host + k, ids_host + k + step_counts[w]);
+        k += step_counts[w];
+      }
+      if (k != n_ids) fail(SNN_E_INVALID, "step counts do not sum to n_ids");
+    } else {
+      for (uint32_t k = 0; k < n_ids; ++k) per_step[k % steps].push_back(ids_host[k]);
     }
-    net->allocs.resize(mark.size());
-    net->device_bytes = bytes_before;
+    uint64_t ev = 0;
+    *avg_ms = time_delivery(net, per_step, reps, &ev);
+    if (events) *events = ev;
+  });
+}
+
+snn_status snn_set_delivery(snn_network *net, uint32_t delivery, uint32_t tiles, uint32_t block, uint32_t grid) {
+  return guarded([&] {
+    if (!net) fail(SNN_E_INVALID, "null network");
+    refuse_member(net);
+    set_delivery(net, delivery, tiles, block, grid);
+  });
+}
+
+snn_status snn_autotune_delivery(snn_network *net, uint32_t reps, snn_delivery_tuning *chosen) {
+  return guarded([&] {
+    if (!net) fail(SNN_E_INVALID, "null network");
+    refuse_member(net);
+    const snn_delivery_tuning t = autotune_delivery(net, reps);
+    if (chosen) *chosen = t;
   });
 }
 

@@ -166,6 +166,7 @@ struct BpttArgs {
   const float *w_in, *w_rec, *w_out;  // caller's weights: CSR order, CSR order, [H][O]
   float *g_w_in, *g_w_rec, *g_w_out;
   float *w_in_t, *w_rec_t;     // weights gathered into transposed (per-target) order
+  float *iin;                  // [T][H][64] input-projection current of every step
   float *xt, *s, *vck, *vtmp, *vseg, *ro, *lamu, *lamv, *lam_carry, *m, *dm;
   int32_t *tmax;
 };
@@ -201,8 +202,6 @@ hipError_t launch_tile_offsets(const uint64_t *row_ptr, const int32_t *col, uint
                                hipStream_t s);
 hipError_t launch_init_neurons(float *v, int32_t *ref, uint32_t n, uint32_t key0, uint32_t key1,
                                float lo, float span, hipStream_t s);
-hipError_t launch_scatter_ids(const uint32_t *ids, uint32_t n_ids, uint32_t steps,
-                              const QueueRef &q, hipStream_t s);
 
 }  // namespace snn
 

@@ -78,9 +78,11 @@ constexpr int kPrefetch = 16;  // steps of input in flight (4 quads)
 // the top 12 bits of r, which holds the count at both ends of each bucket, plus a
 // short scan when a threshold falls inside the bucket.
 __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t steps) {
-  __shared__ uint32_t tbl[kTableCap];
-  __shared__ uint16_t guide[kGuideBuckets];
+  __shared__ __align__(16) uint32_t tbl[kTableCap];
+  __shared__ __align__(16) uint16_t guide[kGuideBuckets];
   __shared__ uint32_t s_base[kUpdateWaves][kWave];
+  static_assert(kTableCap / 4 <= kUpdateBlock && kGuideBuckets / 8 == 2 * kUpdateBlock,
+                "one 16-byte table load per lane, two guide loads");
 
   const uint64_t t0 = a.ctl->t;
   if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->t_deliver = t0;
@@ -110,7 +112,14 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
     return x;
   };
 
-  // ---- one round trip: state, drive tables, first kPrefetch inputs ----
+  // ---- one round trip: drive tables (16-byte loads, issued first so that waiting for
+  //      them leaves the later loads in flight), state, first kPrefetch inputs ----
+  int4 tv = {0, 0, 0, 0}, gv0 = {0, 0, 0, 0}, gv1 = {0, 0, 0, 0};
+  if (drive) {
+    if (threadIdx.x < kTableCap / 4) tv = reinterpret_cast<const int4 *>(a.table32)[threadIdx.x];
+    gv0 = reinterpret_cast<const int4 *>(a.guide)[threadIdx.x];
+    gv1 = reinterpret_cast<const int4 *>(a.guide)[threadIdx.x + kUpdateBlock];
+  }
   float v = 0.f, xp = 0.f, xq = 0.f;
   int32_t ref = 0;
   if (active) {
@@ -125,8 +134,9 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
 #pragma unroll
   for (int j = 0; j < kPrefetch; ++j) acc[j] = load_input(j);
   if (drive) {
-    for (uint32_t j = threadIdx.x; j < a.table_len; j += kUpdateBlock) tbl[j] = a.table32[j];
-    for (uint32_t j = threadIdx.x; j < kGuideBuckets; j += kUpdateBlock) guide[j] = a.guide[j];
+    if (threadIdx.x < kTableCap / 4) reinterpret_cast<int4 *>(tbl)[threadIdx.x] = tv;
+    reinterpret_cast<int4 *>(guide)[threadIdx.x] = gv0;
+    reinterpret_cast<int4 *>(guide)[threadIdx.x + kUpdateBlock] = gv1;
   }
   __syncthreads();
 
@@ -306,27 +316,38 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
   }
 }
 
-constexpr int kTiledUnroll = 8;
+constexpr int kTiledGroups = 4;  // 16-byte groups per lane per batch (16 synapses)
 
-// Loads kTiledUnroll elements of the flattened sub-row range, 64 apart, starting at
-// this lane's element `first`; `o` is the lane's current sub-row (monotone).
-// With source weights (kSrcW) only the target is loaded; the weight is the sub-row's
-// source weight held in LDS.
+// Sub-rows are streamed as 16-byte aligned groups of 4 synapses (one int4 load of
+// targets, and of weights when they are stored per synapse); the elements of a group
+// outside its sub-row are masked off.  Loads kU groups of the flattened group range,
+// 64 apart, from this lane's group `first`; `o` is the lane's current sub-row
+// (monotone).  With source weights (kSrcW) the weight is the sub-row's, held in LDS.
 template <int kU, bool kSrcW>
 __device__ __forceinline__ void tiled_load(const DeliverArgs &a, const uint64_t *s_lo,
-                                           const uint32_t *s_pre, const int32_t *s_w, uint32_t first,
-                                           uint32_t end, int32_t tile_lo, uint32_t &o,
-                                           int32_t (&cv)[kU], int32_t (&wv)[kU]) {
+                                           const uint32_t *s_len, const uint32_t *s_pre,
+                                           const int32_t *s_w, uint32_t first, uint32_t end,
+                                           uint32_t &o, int4 (&cv)[kU], int4 (&wv)[kU],
+                                           uint32_t (&mask)[kU]) {
 #pragma unroll
   for (int u = 0; u < kU; ++u) {
     const uint32_t idx = first + u * kWave;
-    cv[u] = tile_lo;
-    wv[u] = 0;
+    mask[u] = 0;
     if (idx < end) {
       while (s_pre[o + 1] <= idx) ++o;
-      const uint64_t e = s_lo[o] + (idx - s_pre[o]);
-      cv[u] = a.col[e];
-      wv[u] = kSrcW ? s_w[o] : a.w_q16[e];
+      const uint64_t lo = s_lo[o], hi = lo + s_len[o];
+      const uint64_t g = (lo >> 2) + (idx - s_pre[o]);
+      cv[u] = reinterpret_cast<const int4 *>(a.col)[g];
+      if constexpr (kSrcW) {
+        const int32_t x = s_w[o];
+        wv[u] = make_int4(x, x, x, x);
+      } else {
+        wv[u] = reinterpret_cast<const int4 *>(a.w_q16)[g];
+      }
+      const uint64_t e0 = g << 2;
+      const uint32_t first_q = lo > e0 ? (uint32_t)(lo - e0) : 0u;
+      const uint32_t last_q = hi - e0 < 4 ? (uint32_t)(hi - e0) : 4u;
+      mask[u] = ((1u << last_q) - 1u) & ~((1u << first_q) - 1u);
     }
   }
 }
@@ -396,10 +417,12 @@ template <int kBlock, bool kSrcW>
 __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_t steps) {
   extern __shared__ int32_t acc[];
   constexpr int kWaves = kBlock / kWave;
-  constexpr int kU = kTiledUnroll;
+  constexpr int kU = kTiledGroups;
   __shared__ uint64_t s_lo[kBlock];
+  __shared__ uint32_t s_len[kBlock];
   __shared__ uint32_t s_pre[kBlock + 1];
   __shared__ int32_t s_w[kSrcW ? kBlock : 1];
+  __shared__ unsigned long long s_ev;
   __shared__ uint32_t s_wave[kWaves];
   __shared__ uint32_t s_cnt[kWave];
   __shared__ uint32_t s_qpre[kWave][kQueueGroups + 1];
@@ -442,12 +465,13 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
 #pragma unroll
   for (uint32_t g = 0; g <= kQueueGroups; ++g) qpre[g] = s_qpre[w][g];
   const uint32_t cnt = qpre[kQueueGroups];
-  uint64_t ev = 0;
+  uint64_t ev = 0;  // synapses of the sub-rows this thread fetched
+  if (threadIdx.x == 0) s_ev = 0;
   __syncthreads();
   for (uint32_t c0 = 0; c0 < cnt; c0 += kBlock) {
     const uint32_t mm = min((uint32_t)kBlock, cnt - c0);
-    // (1) sub-row bounds of this chunk's spikes
-    uint32_t len = 0;
+    // (1) sub-row bounds of this chunk's spikes and their 16-byte group counts
+    uint32_t len = 0, groups = 0;
     uint64_t lo = 0;
     int32_t ws = 0;
     if (threadIdx.x < mm) {
@@ -457,11 +481,13 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
         const uint32_t o0 = to[tile_a], o1 = to[tile_b];
         lo = a.row_ptr[src] + o0;
         len = o1 - o0;
+        groups = len ? (uint32_t)(((lo + len + 3) >> 2) - (lo >> 2)) : 0u;
         if (kSrcW) ws = a.w_src[src];
       }
     }
-    // (2) block-wide exclusive scan of the sub-row lengths
-    const uint32_t incl = wave_inclusive_scan(len);
+    ev += len;
+    // (2) block-wide exclusive scan of the group counts
+    const uint32_t incl = wave_inclusive_scan(groups);
     if (lane == kWave - 1) s_wave[wave] = incl;
     __syncthreads();
     if (wave == 0) {
@@ -470,49 +496,57 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
       if (lane < kWaves) s_wave[lane] = xi - x;
     }
     __syncthreads();
-    const uint32_t pre = s_wave[wave] + incl - len;
+    const uint32_t pre = s_wave[wave] + incl - groups;
     if (threadIdx.x < mm) {
       s_pre[threadIdx.x] = pre;
       s_lo[threadIdx.x] = lo;
+      s_len[threadIdx.x] = len;
       if (kSrcW) s_w[threadIdx.x] = ws;
     }
-    if (threadIdx.x == kBlock - 1) s_pre[mm] = pre + len;
+    if (threadIdx.x == kBlock - 1) s_pre[mm] = pre + groups;
     __syncthreads();
     const uint32_t total = s_pre[mm];
-    ev += total;
-    // (3) this wave's contiguous share of the flattened edges
+    // (3) this wave's contiguous share of the flattened groups
     const uint32_t share = (total + kWaves - 1) / kWaves;
     const uint32_t beg = min(wave * share, total), end = min(beg + share, total);
     if (beg < end) {
-      uint32_t lo_j = 0, hi_j = mm;  // sub-row holding element beg
+      uint32_t lo_j = 0, hi_j = mm;  // sub-row holding group beg
       while (hi_j - lo_j > 1) {
         const uint32_t mid = (lo_j + hi_j) >> 1;
         if (s_pre[mid] <= beg) lo_j = mid;
         else hi_j = mid;
       }
       uint32_t o = lo_j;
-      int32_t cv[kU], wv[kU], cn[kU], wn[kU];
-      tiled_load<kU, kSrcW>(a, s_lo, s_pre, s_w, beg + lane, end, (int32_t)tile_lo, o, cv, wv);
+      int4 cv[kU], wv[kU], cn[kU], wn[kU];
+      uint32_t mk[kU], mn[kU] = {};
+      tiled_load<kU, kSrcW>(a, s_lo, s_len, s_pre, s_w, beg + lane, end, o, cv, wv, mk);
       for (uint32_t b0 = beg; b0 < end; b0 += kWave * kU) {
         const uint32_t nb = b0 + kWave * kU;
-        if (nb < end) tiled_load<kU, kSrcW>(a, s_lo, s_pre, s_w, nb + lane, end, (int32_t)tile_lo, o, cn, wn);
+        if (nb < end) tiled_load<kU, kSrcW>(a, s_lo, s_len, s_pre, s_w, nb + lane, end, o, cn, wn, mn);
 #pragma unroll
-        for (int u = 0; u < kU; ++u)
-          if (wv[u]) atomicAdd(&acc[cv[u] - (int32_t)tile_lo], wv[u]);
+        for (int u = 0; u < kU; ++u) {
+          if (mk[u] & 1u) atomicAdd(&acc[cv[u].x - (int32_t)tile_lo], wv[u].x);
+          if (mk[u] & 2u) atomicAdd(&acc[cv[u].y - (int32_t)tile_lo], wv[u].y);
+          if (mk[u] & 4u) atomicAdd(&acc[cv[u].z - (int32_t)tile_lo], wv[u].z);
+          if (mk[u] & 8u) atomicAdd(&acc[cv[u].w - (int32_t)tile_lo], wv[u].w);
+        }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           cv[u] = cn[u];
           wv[u] = wn[u];
+          mk[u] = mn[u];
         }
       }
     }
     __syncthreads();
   }
+  ev = wave_sum(ev);
+  if (lane == 0 && ev) atomicAdd(&s_ev, (unsigned long long)ev);
   __syncthreads();
   int32_t *out = a.input + (size_t)ring_add((uint32_t)(t0 % a.n_inbuf), w, a.n_inbuf) * a.n + tile_lo;
   for (uint32_t j = threadIdx.x; j < tile_n; j += kBlock) out[j] = acc[j];
   if (threadIdx.x == 0) {
-    add_part(a.ctl->events, blockIdx.x, ev);
+    add_part(a.ctl->events, blockIdx.x, s_ev);
     if (tile_a == 0) add_part(a.ctl->spikes, blockIdx.x, cnt);
   }
 }

@@ -19,15 +19,20 @@ def _torch_stream_and_allocator(device):
     if not torch.cuda.is_available():
         return None, None, None
     stream = torch.cuda.current_stream(device)
+    alloc_fn = torch.cuda.caching_allocator_alloc
+    delete_fn = torch.cuda.caching_allocator_delete
 
     def _alloc(nbytes, s, ctx):
         try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+            return alloc_fn(int(nbytes), device, stream)
         except Exception:
             return None
 
     def _free(ptr, nbytes, s, ctx):
-        torch.cuda.caching_allocator_delete(ptr)
+        try:
+            delete_fn(ptr)
+        except Exception:
+            pass  # interpreter shutdown: the process is releasing the device anyway
 
     keep = (L.ALLOC_FN(_alloc), L.FREE_FN(_free))
     alloc = L.Allocator(keep[0], keep[1], None)
@@ -244,13 +249,28 @@ class Network:
     def reset_profile(self):
         L.check(self._lib.snn_reset_profile(self._h))
 
-    def time_delivery(self, ids, reps=10, steps=0):
-        """Mean time (ms) of one delivery launch over the given spike ids spread evenly over
-        `steps` emission steps (0: the network's window), and the events per launch."""
+    def set_delivery(self, delivery="auto", tiles=0, block=0, grid=0):
+        L.check(self._lib.snn_set_delivery(self._h, L.DELIVERY[delivery], tiles, block, grid))
+
+    def autotune_delivery(self, reps=5):
+        """Time the delivery configurations on the latest window's spikes; keep the
+        fastest (returned as a dict)."""
+        t = L.DeliveryTuning()
+        L.check(self._lib.snn_autotune_delivery(self._h, reps, C.byref(t)))
+        return {"delivery": L.DELIVERY_NAME.get(t.delivery, "?"), "tiles": t.tiles, "block": t.block,
+                "grid": t.grid, "ms_per_launch": t.ms_per_launch, "events_per_launch": t.events_per_launch}
+
+    def time_delivery(self, ids, reps=10, steps=0, step_counts=None):
+        """Mean time (ms) of one delivery launch over the given spike ids as one window of
+        `steps` emission steps (0: the network's window) -- spread evenly, or step w
+        taking the next step_counts[w] ids -- and the events per launch."""
         ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        counts = None if step_counts is None else np.ascontiguousarray(step_counts, dtype=np.uint32)
+        if counts is not None and steps == 0:
+            steps = len(counts)
         ms = C.c_double()
         ev = C.c_uint64()
-        L.check(self._lib.snn_time_delivery(self._h, _ptr(ids), len(ids), steps, reps,
+        L.check(self._lib.snn_time_delivery(self._h, _ptr(ids), len(ids), _ptr(counts), steps, reps,
                                             C.byref(ms), C.byref(ev)))
         return ms.value, ev.value
 

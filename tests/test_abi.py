@@ -40,7 +40,8 @@ def test_exported_symbols_match_header():
 STRUCTS = {"snn_population": L.Population, "snn_projection": L.Projection,
            "snn_params": L.Params, "snn_allocator": L.Allocator, "snn_info": L.Info,
            "snn_state": L.State, "snn_profile": L.Profile, "snn_batch_member": L.BatchMember,
-           "snn_batch_tuning": L.BatchTuning, "snn_bptt_desc": L.BpttDesc}
+           "snn_batch_tuning": L.BatchTuning, "snn_bptt_desc": L.BpttDesc,
+           "snn_delivery_tuning": L.DeliveryTuning}
 
 
 def test_struct_layouts_match_header():

@@ -144,6 +144,8 @@ def test_time_delivery_counts_events():
         ids = np.arange(0, 3000, 7, dtype=np.uint32)
         ms, ev = g.time_delivery(ids, reps=3, steps=1)
         assert ev == 200 * len(ids) and ms > 0
+        ms, ev = g.time_delivery(ids, reps=2, step_counts=[len(ids) - 50, 0, 50])
+        assert ev == 200 * len(ids) and ms > 0
         assert g.t == 0 and g.events == 0
 
 
@@ -181,3 +183,40 @@ def test_mixed_weights_of_one_source_population_use_per_synapse_weights():
     rg, inf = _compare_run(spec, 400)
     assert inf["source_weights"] == 0
     assert rg.any()
+
+
+def test_delivery_switched_between_windows_keeps_parity():
+    """Changing the delivery variant and tiling between runs leaves the results equal
+    to the oracle's (the input ring holds exactly the pending arrivals at a window
+    boundary, whichever variant filled it)."""
+    spec = W.brunel_fixed_out(n=2500, k=250, delay_steps=15, steps=150)
+    g = _net(spec, raster_steps=150, delivery="tiled")
+    g.run(45)
+    g.set_delivery("atomic")
+    g.run(45)
+    g.set_delivery("tiled", tiles=7, block=1024, grid=64)
+    g.run(30)
+    g.set_delivery("auto")
+    g.run(30)
+    o = oracle.OracleNet(spec, raster_cap=150)
+    o.run(150)
+    assert np.array_equal(g.raster_bits(0, 150), o.raster_words()[:150])
+    assert np.array_equal(_bits(g.state()["v"]), _bits(o.v()))
+
+
+def test_autotune_delivery_keeps_state_and_parity():
+    spec = W.brunel_fixed_out(n=4000, k=400, delay_steps=15, steps=150)
+    g = _net(spec, raster_steps=150)
+    g.run(60)
+    before = g.state()
+    t = g.autotune_delivery(reps=2)
+    print(f"[autotune] {t}", flush=True)
+    assert t["delivery"] in ("atomic", "tiled") and t["ms_per_launch"] > 0 and t["events_per_launch"] > 0
+    after = g.state()
+    assert np.array_equal(_bits(before["v"]), _bits(after["v"]))
+    assert np.array_equal(before["input"], after["input"]) and g.t == 60
+    g.run(90)
+    o = oracle.OracleNet(spec, raster_cap=150)
+    o.run(150)
+    assert np.array_equal(g.raster_bits(0, 150), o.raster_words()[:150])
+    assert np.array_equal(_bits(g.state()["v"]), _bits(o.v()))
