@@ -22,6 +22,8 @@ Other workloads (`--workload`, one JSON line each, not the headline):
          5,000 steps, against the plain per-network simulator on the same GPU
   bptt   surrogate-gradient BPTT (64 x 250 steps, 700 -> 1,024 -> 20), forward +
          adjoint, against the forward alone and a dense PyTorch reference on the GPU
+  scaling  both models grown with the weight scaling of Eq. 1 (Vogels 4k-128k, Brunel
+         20k-400k neurons), wall time per simulated second vs synapse count
 """
 import argparse
 import hashlib
@@ -403,6 +405,43 @@ def summarize_pmc(fetch_dir, write_dir, copy_mib, command, skip=1):
     print(json.dumps(out, indent=1))
 
 
+def bench_scaling(args):
+    """Eq. 1 size sweep (Sec. IV, the runtime-vs-synapses comparison): both models grown
+    with their weights scaled so that the firing regime is kept."""
+    import torch
+    from paper_1912_07423_amd import Network
+    from paper_1912_07423_amd import workloads as W
+    steps = args.steps
+    points = []
+    for model, sizes in (("vogels", (4000, 16000, 64000, 128000)),
+                         ("brunel", (20000, 50000, 100000, 200000, 400000))):
+        for n in sizes:
+            spec = W.vogels_scaled(n) if model == "vogels" else W.brunel_scaled(n)
+            net = Network(spec, raster_steps=max(16, steps))
+            net.run(args.warmup)
+            net.sync()
+            i0 = net.info()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            net.run(steps)
+            net.sync()
+            wall = time.perf_counter() - t0
+            i1 = net.info()
+            spikes = int(net.raster(args.warmup, args.warmup + steps).sum())
+            dt = spec["params"]["dt_ms"] * 1e-3
+            p = {"model": model, "neurons": n, "synapses": i1["nnz"], "c": W.eq1_scale(model, n),
+                 "wall_s_per_sim_s": wall / (steps * dt), "events_per_s": (i1["events"] - i0["events"]) / wall,
+                 "rate_hz": spikes / n / (steps * dt), "delivery": i1["delivery_name"]}
+            points.append(p)
+            print(f"[bench] {json.dumps(p)}", file=sys.stderr, flush=True)
+            net.close()
+    top = points[-1]
+    line("Eq. 1 size sweep: wall time per simulated second and synaptic events/sec vs synapse count, 1 GPU",
+         top["events_per_s"], "events/s", steps, args.warmup, top["wall_s_per_sim_s"] * 0.1, "int32",
+         {"workload": "eq1_size_sweep_vogels_4k-128k_brunel_20k-400k", "parallelism": "single-gpu"},
+         points=points)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -412,7 +451,7 @@ def main():
                     help="steps of the CPU-oracle sample (0 disables it)")
     ap.add_argument("--delivery", default="auto")
     ap.add_argument("--synapse-weights", default="auto", choices=["auto", "per_synapse"])
-    ap.add_argument("--workload", default="brunel", choices=["brunel", "stdp", "sweep", "bptt"])
+    ap.add_argument("--workload", default="brunel", choices=["brunel", "stdp", "sweep", "bptt", "scaling"])
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run 3 plain device copies of this size first (HBM counter scaling)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -435,7 +474,8 @@ def main():
         sys.exit(2)
     if args.copy_calibration_mib > 0:
         copy_calibration(args.copy_calibration_mib)
-    {"brunel": bench_brunel, "stdp": bench_stdp, "sweep": bench_sweep, "bptt": bench_bptt}[args.workload](args)
+    {"brunel": bench_brunel, "stdp": bench_stdp, "sweep": bench_sweep, "bptt": bench_bptt,
+     "scaling": bench_scaling}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -14,6 +14,8 @@
 // the forward current is a gather over the transposed index (per target, sources in
 // ascending order, input projection first), the adjoint's dL/ds a gather over the
 // forward rows, and every weight gradient has exactly one owner.
+#include <rocblas/rocblas.h>
+
 #include <algorithm>
 
 #include "device_math.h"
@@ -237,38 +239,35 @@ __global__ __launch_bounds__(256) void k_adjoint_step(BpttArgs a, uint32_t t, co
   lam_out[(size_t)i * 64 + b] = a.beta * ln + surrogate(z, a.slope, a.smooth != 0) * ds;
 }
 
-// Gradients of the sparse weights over one segment [t0, t0 + len): a workgroup per
-// target j whose wavefronts share its in-edges; each holds j's membrane adjoints for the
-// segment in registers, reduces an in-edge over (t, b) and adds the result to the
-// edge's own gradient entry (one owner per entry).
-constexpr int kSegMax = 32;
-constexpr uint32_t kGradSplit = 4;  // wavefronts sharing one target's in-edges
-__global__ __launch_bounds__(256) void k_grad_sparse(BpttArgs a, uint32_t t0, uint32_t len,
-                                                     const float *lam_seg) {
-  const uint32_t j = blockIdx.x;
-  const uint32_t part = threadIdx.x / kWave;
-  const uint32_t b = lane_id();
-  float lam[kSegMax];
-#pragma unroll
-  for (int k = 0; k < kSegMax; ++k) lam[k] = k < (int)len ? lam_seg[((size_t)k * a.H + j) * 64 + b] : 0.0f;
-  for (uint64_t e = a.in_t_ptr[j] + part; e < a.in_t_ptr[j + 1]; e += kGradSplit) {
-    const float *xs = a.xt + (size_t)a.in_t_src[e] * 64 + b;
-    float acc = 0.0f;
-#pragma unroll
-    for (int k = 0; k < kSegMax; ++k)
-      if (k < (int)len) acc += xs[(size_t)(t0 + k) * a.C * 64] * lam[k];
-    acc = wave_sum(acc);
-    if (b == 0) a.g_w_in[a.in_t_edge[e]] += acc;
-  }
-  for (uint64_t e = a.rec_t_ptr[j] + part; e < a.rec_t_ptr[j + 1]; e += kGradSplit) {
-    const float *ss = a.s + (size_t)a.rec_t_src[e] * 64 + b;
-    float acc = 0.0f;
-#pragma unroll
-    for (int k = 0; k < kSegMax; ++k)
-      if (k < (int)len && t0 + k >= 1) acc += ss[(size_t)(t0 + k - 1) * a.H * 64] * lam[k];
-    acc = wave_sum(acc);
-    if (b == 0) a.g_w_rec[a.rec_t_edge[e]] += acc;
-  }
+// Gradients of the sparse weights are masked dense contractions over (t, b):
+//   dW_in[c][j]  = sum_{t,b} x_t[c][b] lamV_t[j][b]
+//   dW_rec[i][j] = sum_{t,b} s_{t-1}[i][b] lamV_t[j][b]
+// Each checkpoint segment lays its trajectories out as [row][(t, b)] matrices and adds
+// its contribution with one FP32 GEMM per projection (rocBLAS, accumulating over the
+// segments); the entries on the masks are then gathered into the CSR-ordered gradients.
+//
+// seg[r][k * 64 + b] = src[t0 + k - shift][r][b] (zero before step 0), k < len, for a
+// [T][rows][64] trajectory; row stride kcols.
+__global__ void k_seg_rows(const float *src, float *seg, uint32_t rows, uint32_t t0, uint32_t len,
+                           uint32_t kcols, uint32_t shift) {
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)rows * len * 64) return;
+  const uint32_t b = (uint32_t)(idx & 63u);
+  const uint64_t rk = idx >> 6;
+  const uint32_t k = (uint32_t)(rk % len), r = (uint32_t)(rk / len);
+  const int64_t t = (int64_t)t0 + k - shift;
+  seg[(size_t)r * kcols + (size_t)k * 64 + b] = t >= 0 ? src[((size_t)t * rows + r) * 64 + b] : 0.0f;
+}
+
+// g[edge] = dense[src][j] for every in-edge (src -> j) of the transposed index; a
+// wavefront per target j.
+__global__ __launch_bounds__(256) void k_mask_gather(const uint64_t *t_ptr, const int32_t *t_src,
+                                                     const uint32_t *t_edge, const float *dense, uint32_t cols,
+                                                     uint32_t n_targets, float *g) {
+  const uint32_t j = blockIdx.x * 4 + threadIdx.x / kWave;
+  if (j >= n_targets) return;
+  for (uint64_t e = t_ptr[j] + lane_id(); e < t_ptr[j + 1]; e += kWave)
+    g[t_edge[e]] = dense[(size_t)t_src[e] * cols + j];
 }
 
 // Gradient of the dense readout weights over the whole sequence: one wavefront per
@@ -333,10 +332,9 @@ hipError_t bptt_forward(const BpttArgs &a, const float *x, const int32_t *labels
   return hipGetLastError();
 }
 
-hipError_t bptt_backward(const BpttArgs &a, const float *g_loss, hipStream_t s) {
+hipError_t bptt_backward(const BpttArgs &a, const float *g_loss, rocblas_handle blas, hipStream_t s) {
+  if (rocblas_set_stream(blas, s) != rocblas_status_success) return hipErrorUnknown;
   gather_weights(a, s);
-  hipLaunchKernelGGL(k_fill, dim3(blocks_for(a.nnz_in, 256)), dim3(256), 0, s, a.g_w_in, a.nnz_in, 0.0f);
-  hipLaunchKernelGGL(k_fill, dim3(blocks_for(a.nnz_rec, 256)), dim3(256), 0, s, a.g_w_rec, a.nnz_rec, 0.0f);
   hipLaunchKernelGGL(k_fill, dim3(blocks_for((uint64_t)a.H * 64, 256)), dim3(256), 0, s, a.lam_carry,
                      (uint64_t)a.H * 64, 0.0f);
   hipLaunchKernelGGL(k_lam_u, dim3(a.O), dim3(64), 0, s, a, g_loss);
@@ -360,10 +358,31 @@ hipError_t bptt_backward(const BpttArgs &a, const float *g_loss, hipStream_t s) 
       hipLaunchKernelGGL(k_adjoint_step, grid, dim3(256), 0, s, a, t0 + (uint32_t)k,
                          a.vseg + (size_t)k * a.H * 64, lam_next, a.lamv + (size_t)k * a.H * 64);
     }
-    hipLaunchKernelGGL(k_grad_sparse, dim3(a.H), dim3(kWave * kGradSplit), 0, s, a, t0, len, a.lamv);
+    // this segment's share of the sparse-weight gradients (two GEMMs over k = (t, b))
+    const uint32_t kcols = a.K * 64, kk = len * 64;
+    hipLaunchKernelGGL(k_seg_rows, dim3(blocks_for((uint64_t)a.H * len * 64, 256)), dim3(256), 0, s, a.lamv,
+                       a.lseg, a.H, 0u, len, kcols, 0u);
+    hipLaunchKernelGGL(k_seg_rows, dim3(blocks_for((uint64_t)a.C * len * 64, 256)), dim3(256), 0, s, a.xt,
+                       a.xseg, a.C, t0, len, kcols, 0u);
+    hipLaunchKernelGGL(k_seg_rows, dim3(blocks_for((uint64_t)a.H * len * 64, 256)), dim3(256), 0, s, a.s,
+                       a.sseg, a.H, t0, len, kcols, 1u);
+    const float one = 1.0f, beta = (uint32_t)g == n_seg - 1 ? 0.0f : 1.0f;
+    rocblas_status bs = rocblas_sgemm(blas, rocblas_operation_transpose, rocblas_operation_none, (int)a.H,
+                                      (int)a.C, (int)kk, &one, a.lseg, (int)kcols, a.xseg, (int)kcols, &beta,
+                                      a.dw_in, (int)a.H);
+    if (bs == rocblas_status_success)
+      bs = rocblas_sgemm(blas, rocblas_operation_transpose, rocblas_operation_none, (int)a.H, (int)a.H,
+                         (int)kk, &one, a.lseg, (int)kcols, a.sseg, (int)kcols, &beta, a.dw_rec, (int)a.H);
+    if (bs != rocblas_status_success) return hipErrorUnknown;
     // lamV of the segment's first step is the next (earlier) segment's lamV_{t+1}
     (void)hipMemcpyAsync(a.lam_carry, a.lamv, (size_t)a.H * 64 * 4, hipMemcpyDeviceToDevice, s);
   }
+  if (a.nnz_in)
+    hipLaunchKernelGGL(k_mask_gather, grid, dim3(256), 0, s, a.in_t_ptr, a.in_t_src, a.in_t_edge, a.dw_in, a.H,
+                       a.H, a.g_w_in);
+  if (a.nnz_rec)
+    hipLaunchKernelGGL(k_mask_gather, grid, dim3(256), 0, s, a.rec_t_ptr, a.rec_t_src, a.rec_t_edge, a.dw_rec,
+                       a.H, a.H, a.g_w_rec);
   return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 // constants, device allocation, on-device network construction, the window schedule
 // of the step pipeline, HIP graph replay, profiling and state/raster readback.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -539,7 +540,9 @@ hipError_t launch_delivery(snn_network *net, const snn::DeliverArgs &d, uint32_t
 
 hipEvent_t new_event() {
   hipEvent_t e;
-  check(hipEventCreate(&e), "hipEventCreate");
+  // timing markers only: no system-scope fence when the event is recorded, so that a
+  // marker between two launches costs as little as possible
+  check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
   return e;
 }
 
@@ -1120,6 +1123,7 @@ struct snn_bptt {
   snn_network pool;          // holds the plan's allocations and default stream
   snn::BpttArgs args{};
   uint64_t forwards = 0;     // forward passes run (the backward uses the latest)
+  rocblas_handle blas = nullptr;  // the GEMMs of the sparse-weight gradients
 };
 
 namespace {
@@ -1206,6 +1210,12 @@ void build_bptt(snn_bptt *p, const uint64_t *in_ptr, const int32_t *in_col, cons
   a.rec_ptr = upload(pool, std::vector<uint64_t>(rec_ptr, rec_ptr + d.n_hidden + 1));
   a.rec_col = upload(pool, std::vector<int32_t>(rec_col, rec_col + nnz_rec));
   const size_t HB = (size_t)a.H * 64, n_seg = (a.T + a.K - 1) / a.K;
+  a.xseg = dev_array<float>(pool, (size_t)a.C * a.K * 64);
+  a.sseg = dev_array<float>(pool, (size_t)a.H * a.K * 64);
+  a.lseg = dev_array<float>(pool, (size_t)a.H * a.K * 64);
+  a.dw_in = dev_array<float>(pool, (size_t)a.C * a.H);
+  a.dw_rec = dev_array<float>(pool, (size_t)a.H * a.H);
+  if (rocblas_create_handle(&p->blas) != rocblas_status_success) fail(SNN_E_HIP, "rocblas_create_handle failed");
   a.w_in_t = dev_array<float>(pool, std::max<uint64_t>(1, nnz_in));
   a.w_rec_t = dev_array<float>(pool, std::max<uint64_t>(1, nnz_rec));
   a.xt = dev_array<float>(pool, (size_t)a.T * a.C * 64);
@@ -1647,6 +1657,7 @@ snn_status snn_bptt_create(const snn_bptt_desc *desc, const uint64_t *in_row_ptr
       }
       build_bptt(p, in_row_ptr, in_col, rec_row_ptr, rec_col);
     } catch (...) {
+      if (p->blas) (void)rocblas_destroy_handle(p->blas);
       release(&p->pool);
       delete p;
       throw;
@@ -1686,7 +1697,7 @@ snn_status snn_bptt_backward(snn_bptt *p, const float *w_in, const float *w_rec,
     a.g_w_rec = g_w_rec;
     a.g_w_out = g_w_out;
     hipStream_t s = stream ? (hipStream_t)stream : p->pool.stream;
-    check(snn::bptt_backward(a, g_loss, s), "bptt backward");
+    check(snn::bptt_backward(a, g_loss, p->blas, s), "bptt backward");
   });
 }
 
@@ -1708,6 +1719,8 @@ snn_status snn_bptt_get_trace(snn_bptt *p, float *spikes, float *v_checkpoints, 
 
 void snn_bptt_destroy(snn_bptt *p) {
   if (!p) return;
+  if (p->pool.stream) (void)hipStreamSynchronize(p->pool.stream);
+  if (p->blas) (void)rocblas_destroy_handle(p->blas);
   release(&p->pool);
   delete p;
 }

@@ -167,12 +167,15 @@ struct BpttArgs {
   float *g_w_in, *g_w_rec, *g_w_out;
   float *w_in_t, *w_rec_t;     // weights gathered into transposed (per-target) order
   float *iin;                  // [T][H][64] input-projection current of every step
+  float *xseg, *sseg, *lseg;   // one segment as [row][(t, b)] matrices (row stride K * 64)
+  float *dw_in, *dw_rec;       // dense gradient accumulators [C][H], [H][H]
   float *xt, *s, *vck, *vtmp, *vseg, *ro, *lamu, *lamv, *lam_carry, *m, *dm;
   int32_t *tmax;
 };
 hipError_t bptt_forward(const BpttArgs &a, const float *x, const int32_t *labels, float *loss,
                         hipStream_t s);
-hipError_t bptt_backward(const BpttArgs &a, const float *g_loss, hipStream_t s);
+typedef struct _rocblas_handle *rocblas_handle_t;
+hipError_t bptt_backward(const BpttArgs &a, const float *g_loss, rocblas_handle_t blas, hipStream_t s);
 
 // kernel launchers (step.hip / generate.hip)
 hipError_t launch_update(const UpdateArgs &a, uint32_t steps, hipStream_t s);

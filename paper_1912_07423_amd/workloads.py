@@ -88,6 +88,36 @@ def stdp_er(n=100_000, p=0.02, delay_steps=10, rate_hz=10.0, n_ext=1000, seed=3,
     return s
 
 
+def eq1_scale(model, n):
+    """Synaptic weight scale c of Eq. 1 (Sec. IV): 16e6 / N^2 for the Vogels model and
+    20,000 / N for the Brunel model, so that both keep their firing regime when N grows
+    (c = 1 at the models' original sizes of 4,000 and 20,000 neurons)."""
+    if model == "vogels":
+        return 16e6 / float(n) ** 2
+    if model == "brunel":
+        return 20000.0 / float(n)
+    raise ValueError(model)
+
+
+def vogels_scaled(n, steps=1000, seed=31):
+    """The 4,000-neuron CUBA network grown to n neurons (4:1, ER p = 0.02) with its
+    weights scaled by Eq. 1."""
+    c = eq1_scale("vogels", n)
+    n_exc = (4 * n) // 5
+    s = ei_er(n_exc, n - n_exc, 0.02, 0.27 * c, -4.5 * c, v_bg_mV=11.0, seed=seed, delay_steps=1)
+    s["steps"] = steps
+    return s
+
+
+def brunel_scaled(n, steps=1000, seed=32):
+    """A Brunel network of n neurons (4:1) with fixed out-degree 0.1 n (uniform targets),
+    J = 0.1 mV and g = 5 scaled by Eq. 1, a 1.5 ms delay and the 20 Hz Poisson drive."""
+    s = brunel_fixed_out(n=n, k=max(1, n // 10), j_mV=0.1 * eq1_scale("brunel", n), seed=seed,
+                         steps=steps)
+    s["params"]["w_ext_mV"] = 0.1
+    return s
+
+
 def sweep(n_nets=512, seed=4, steps=5000, n_lo=1000, n_hi=20_000, p_lo=0.01, p_hi=0.05,
           w_lo=0.1, w_hi=0.4):
     """Independent CUBA LIF networks of uneven size for a parameter sweep: N
