@@ -107,24 +107,20 @@ struct LifConst {
 // refractory neuron counts down and discards its input; otherwise the Q16 input plus
 // k drive inputs (int32, wrapping) is added to V, V leaks towards v_inf by alpha, and
 // V >= V_th emits a spike, resets V and starts the refractory count.  Returns the spike.
+// Written without branches: the candidate V is computed for every lane and a
+// refractory lane keeps its old V (the same values as skipping the computation).
 __device__ __forceinline__ bool lif_advance(float &v, int32_t &ref, int32_t input, int32_t k,
                                             const LifConst &c) {
-  if (ref > 0) {
-    ref -= 1;
-    return false;
-  }
+  const bool refractory = ref > 0;
   const uint32_t sum = (uint32_t)input + (uint32_t)k * (uint32_t)c.w_ext_q16;
   const float dv = (float)(int32_t)sum * 0x1p-16f;
   float vv = v + dv;
   const float diff = vv - c.v_inf;
   const float leak = diff * c.alpha;
   vv = c.v_inf + leak;
-  const bool spike = vv >= c.v_th;
-  if (spike) {
-    vv = c.v_reset;
-    ref = c.ref_steps;
-  }
-  v = vv;
+  const bool spike = !refractory && vv >= c.v_th;
+  v = refractory ? v : (spike ? c.v_reset : vv);
+  ref = refractory ? ref - 1 : (spike ? c.ref_steps : ref);
   return spike;
 }
 

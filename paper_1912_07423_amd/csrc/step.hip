@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
       bool spike = false;
       if (active) {
         int32_t k = 0;
-        if (drive && ref <= 0) {
+        if (drive && ref <= 0) {  // a refractory neuron discards its drive
           const uint32_t r = rnd.w[u];
           const uint32_t gk = guide[r >> (32 - kGuideBits)];
           k = (int32_t)(gk & 0xFFu);
@@ -394,16 +394,18 @@ __device__ void make_schedule(const uint32_t *cnt, uint32_t steps, uint32_t tile
   uint32_t best = need <= grid ? x : 0xFFFFFFFFu;
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) best = min(best, (uint32_t)__shfl_xor(best, d, kWave));
-  if (lane == 0) {
-    uint32_t acc = 0;
-    for (uint32_t w = 0; w < steps; ++w) {
-      const uint32_t g = best == 0xFFFFFFFFu ? kMaxTileGroup : group_for(best, cnt[w]);
-      sch.m[w] = g;
-      sch.first[w] = acc;
-      acc += (tiles + g - 1) / g;
-    }
-    sch.first[steps] = acc;
+  // lane w: the tiles per range and the range count of step w; their prefix over the
+  // steps gives each step's first workgroup
+  uint32_t g = 0, r = 0;
+  if (lane < steps) {
+    g = best == 0xFFFFFFFFu ? kMaxTileGroup : group_for(best, cnt[lane]);
+#pragma unroll
+    for (uint32_t m = 1; m <= kMaxTileGroup; ++m) r += g == m ? ranges[m] : 0u;
   }
+  const uint32_t incl = wave_inclusive_scan(r);
+  sch.m[lane] = g;
+  sch.first[lane + 1] = incl;
+  if (lane == 0) sch.first[0] = 0;
 }
 
 // A workgroup owns (a range of consecutive base tiles, one emission step): it
@@ -553,6 +555,9 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
 
 constexpr int kStdpBlock = 256;
 constexpr int kStdpWaves = kStdpBlock / kWave;
+// wavefronts sharing one queued spike's synapses (disjoint parts: still one writer per
+// synapse); a step has few spikes, so this is what fills the GPU
+constexpr uint32_t kStdpSplit = 16;
 
 __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltd(StdpArgs a) {
   const uint64_t t = a.ctl->t;
@@ -565,20 +570,23 @@ __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltd(StdpArgs a) {
   const uint32_t gwave = blockIdx.x * kStdpWaves + threadIdx.x / kWave;
   const uint32_t n_gwaves = gridDim.x * kStdpWaves;
   uint64_t touched = 0;
-  for (uint32_t s = gwave; s < cnt; s += n_gwaves) {
+  for (uint64_t item = gwave; item < (uint64_t)cnt * kStdpSplit; item += n_gwaves) {
+    const uint32_t s = (uint32_t)(item / kStdpSplit), part = (uint32_t)(item % kStdpSplit);
     const int32_t i = queue_entry(a.q, slot, pre, s);
     if ((uint32_t)i >= a.n) continue;
-    if (lane == 0) a.x_pre[i] = a.x_pre[i] + 1.0f;
+    if (part == 0 && lane == 0) a.x_pre[i] = a.x_pre[i] + 1.0f;
     const uint64_t lo = a.row_ptr[i] + a.plast_rel[i];
     const uint32_t len = a.plast_len[i];
-    for (uint32_t k = lane; k < len; k += kWave) {
+    const uint32_t chunk = (len + kStdpSplit - 1) / kStdpSplit;
+    const uint32_t k0 = part * chunk, k1 = min(len, k0 + chunk);
+    for (uint32_t k = k0 + lane; k < k1; k += kWave) {
       const uint64_t e = lo + k;
       const float dw = a.a_minus * a.x_post[a.col[e]];
       float wv = a.w_f32[e] - dw;
       if (wv < 0.0f) wv = 0.0f;
       a.w_f32[e] = wv;
     }
-    touched += len;
+    touched += k1 > k0 ? k1 - k0 : 0;
   }
   if (lane == 0) add_part(a.ctl->touches, gwave, touched);
 }
@@ -593,19 +601,22 @@ __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltp(StdpArgs a) {
   const uint32_t gwave = blockIdx.x * kStdpWaves + threadIdx.x / kWave;
   const uint32_t n_gwaves = gridDim.x * kStdpWaves;
   uint64_t touched = 0;
-  for (uint32_t s = gwave; s < cnt; s += n_gwaves) {
+  for (uint64_t item = gwave; item < (uint64_t)cnt * kStdpSplit; item += n_gwaves) {
+    const uint32_t s = (uint32_t)(item / kStdpSplit), part = (uint32_t)(item % kStdpSplit);
     const int32_t j = queue_entry(a.q, slot, pre, s);
     if ((uint32_t)j >= a.n) continue;
-    if (lane == 0) a.x_post[j] = a.x_post[j] + 1.0f;
-    const uint64_t lo = a.in_ptr[j], hi = a.in_ptr[j + 1];
-    for (uint64_t m = lo + lane; m < hi; m += kWave) {
+    if (part == 0 && lane == 0) a.x_post[j] = a.x_post[j] + 1.0f;
+    const uint64_t lo = a.in_ptr[j], len = a.in_ptr[j + 1] - lo;
+    const uint64_t chunk = (len + kStdpSplit - 1) / kStdpSplit;
+    const uint64_t m0 = lo + part * chunk, m1 = min(lo + len, m0 + chunk);
+    for (uint64_t m = m0 + lane; m < m1; m += kWave) {
       const uint32_t e = a.in_edge[m];
       const float dw = a.a_plus * a.x_pre[a.in_src[m]];
       float wv = a.w_f32[e] + dw;
       if (wv > a.w_max) wv = a.w_max;
       a.w_f32[e] = wv;
     }
-    touched += hi - lo;
+    touched += m1 > m0 ? m1 - m0 : 0;
   }
   if (lane == 0) add_part(a.ctl->touches, gwave, touched);
 }
