@@ -97,6 +97,16 @@ __device__ uint64_t er_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uin
   return pos;
 }
 
+// floor(num / den), den > 0, num + den < 2^64: a binary64 estimate (within one of the
+// quotient while the quotient is below 2^51) corrected to the exact integer quotient.
+// Far cheaper on the GPU than a 64-bit integer division.
+__device__ __forceinline__ uint64_t div_floor_u64(uint64_t num, uint64_t den) {
+  uint64_t q = (uint64_t)((double)num / (double)den);
+  while (q * den > num) --q;
+  while ((q + 1) * den <= num) ++q;
+  return q;
+}
+
 __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint64_t pos,
                            int32_t *col, int32_t *w_q16, float *w_f32) {
   const uint32_t k_out = pj.k;
@@ -135,7 +145,7 @@ __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint
       s += gap[q];  // S_{k+1}
       if (b < n_blocks && k < k_out) {
         uint64_t x = k;
-        if (total != 0) x = (2u * s * pj.spare + total) / two_total + k;
+        if (total != 0) x = div_floor_u64(2u * s * pj.spare + total, two_total) + k;
         uint32_t local = (uint32_t)x;
         if (local >= self_local) local += 1;
         const uint64_t p = pos + k;
