@@ -24,6 +24,10 @@ Other workloads (`--workload`, one JSON line each, not the headline):
          adjoint, against the forward alone and a dense PyTorch reference on the GPU
   scaling  both models grown with the weight scaling of Eq. 1 (Vogels 4k-128k, Brunel
          20k-400k neurons), wall time per simulated second vs synapse count
+  setup  network setup time vs size (Brunel, 1e7-1.6e10 synapses), cold and warm
+         allocator, with the synapse fill's write bandwidth
+  layout the delivery's bandwidth with CSR rows against 128-byte aligned rows, and with
+         one weight per source against a weight per synapse
 """
 import argparse
 import hashlib
@@ -442,6 +446,95 @@ def bench_scaling(args):
          points=points)
 
 
+def bench_layout(args):
+    """Adjacency-layout A/B on the headline network (Sec. III-A.2 and Table I): CSR rows of
+    5,000 targets (20,000 B, so row starts fall anywhere inside a 128-byte line) against
+    rows of 5,024 targets (20,096 B = 157 lines: every row starts on a 128-byte boundary,
+    the geometry of the paper's aligned 2-D adjacency array), each with one weight per
+    source (4 B per synapse) and with a weight per synapse (8 B), through the tiled and
+    the atomic delivery.  Reported: each delivery's algorithmic bytes per second."""
+    from paper_1912_07423_amd import Network
+    from paper_1912_07423_amd import workloads as W
+    steps = min(args.steps, 300)
+    points = []
+    for k in (5000, 5024):
+        spec = W.brunel_fixed_out(n=200_000, k=k, delay_steps=15, rate_hz=20.0, n_ext=1000,
+                                  j_mV=0.1, g=5.0, seed=2, steps=steps)
+        for weights in ("auto", "per_synapse"):
+            net = Network(spec, raster_steps=16, synapse_weights=weights)
+            for delivery in ("tiled", "atomic"):
+                net.set_delivery(delivery)
+                net.run(args.warmup)
+                net.sync()
+                i0 = net.info()
+                net.set_profiling(True)
+                net.reset_profile()
+                net.run(steps)
+                net.sync()
+                prof = net.profile()
+                i1 = net.info()
+                net.set_profiling(False)
+                b_ev, b_spk = delivery_bytes(i1)
+                events, spikes = i1["events"] - i0["events"], i1["spikes"] - i0["spikes"]
+                launches = max(1, prof["deliver_launches"])
+                ms = prof["deliver_ms"] / launches
+                gbs = (events * b_ev + spikes * b_spk) / launches / (ms * 1e-3) / 1e9
+                p = {"row_targets": k, "row_bytes": 4 * k, "rows_128b_aligned": (4 * k) % 128 == 0,
+                     "weights": "per_source" if i1["source_weights"] else "per_synapse",
+                     "delivery": delivery, "deliver_us_mean": ms * 1e3, "launches": launches,
+                     "events": events, "algorithmic_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+                points.append(p)
+                print(f"[bench] {json.dumps(p)}", file=sys.stderr, flush=True)
+            net.close()
+    best = max(points, key=lambda p: p["algorithmic_gbs"])
+    line("delivery bandwidth by adjacency layout (CSR vs 128-B aligned rows; 4 vs 8 B per synapse), 1 GPU",
+         best["algorithmic_gbs"], "GB/s", steps, args.warmup, None, "int32",
+         {"workload": "layout_ab_brunel_200k_k5000_vs_k5024_d15", "parallelism": "single-gpu"},
+         points=points)
+
+
+def bench_setup(args):
+    """Setup time vs network size (Sec. IV, the setup-time benchmark): Brunel networks,
+    which carry no synapse state, so that setup is dominated by graph construction.  Each
+    size is built three times back to back: the first build takes fresh device memory, the
+    later ones reuse the blocks the caching allocator kept from the previous build (only
+    growth allocates).  Reported per build: host wall time of the whole setup, and the
+    device time of the row-length pass, the synapse fill and the delivery index, with the
+    fill's write bandwidth (target ids, 4 B per synapse, and per-synapse weights when
+    stored) against the HBM peak."""
+    import torch
+    from paper_1912_07423_amd import Network
+    from paper_1912_07423_amd import workloads as W
+    points = []
+    cases = [("brunel_k5000", 200_000, W.brunel_fixed_out())]
+    cases += [("brunel_eq1", n, W.brunel_scaled(n)) for n in (10_000, 20_000, 50_000, 100_000, 200_000, 400_000)]
+    for name, n, spec in cases:
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            net = Network(spec, raster_steps=16)
+            torch.cuda.synchronize()
+            wall_ms = (time.perf_counter() - t0) * 1e3
+            i = net.info()
+            net.close()
+            written = i["nnz"] * (4 if i["source_weights"] else 8)
+            p = {"model": name, "neurons": n, "synapses": i["nnz"], "build": "cold" if rep == 0 else "warm",
+                 "setup_ms": wall_ms, "library_ms": i["build_ms"], "rows_ms": i["gen_rows_ms"],
+                 "fill_ms": i["gen_fill_ms"], "index_ms": i["index_ms"],
+                 "fill_write_gbs": written / (i["gen_fill_ms"] * 1e-3) / 1e9 if i["gen_fill_ms"] > 0 else None,
+                 "synapses_per_s": i["nnz"] / (wall_ms * 1e-3)}
+            points.append(p)
+            print(f"[bench] {json.dumps(p)}", file=sys.stderr, flush=True)
+    head = [p for p in points if p["model"] == "brunel_k5000" and p["build"] == "warm"]
+    best = min(head, key=lambda p: p["setup_ms"])
+    line("network setup: synapses generated/sec (whole setup, warm allocator), 1 GPU",
+         best["synapses_per_s"], "synapses/s", 1, 0, best["setup_ms"], "int32",
+         {"workload": "setup_brunel_200k_k5000_and_eq1_brunel_10k-400k", "parallelism": "single-gpu"},
+         fill_write_gbs=best["fill_write_gbs"],
+         fill_hbm_frac=best["fill_write_gbs"] / HBM_PEAK_GBS if best["fill_write_gbs"] else None,
+         points=points)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -451,7 +544,7 @@ def main():
                     help="steps of the CPU-oracle sample (0 disables it)")
     ap.add_argument("--delivery", default="auto")
     ap.add_argument("--synapse-weights", default="auto", choices=["auto", "per_synapse"])
-    ap.add_argument("--workload", default="brunel", choices=["brunel", "stdp", "sweep", "bptt", "scaling"])
+    ap.add_argument("--workload", default="brunel", choices=["brunel", "stdp", "sweep", "bptt", "scaling", "setup", "layout"])
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run 3 plain device copies of this size first (HBM counter scaling)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -469,13 +562,13 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} (WORLD_SIZE {world}) is not "
-              "supported by this build (the multi-GPU design is documented, not built)",
-              file=sys.stderr, flush=True)
+              "supported: multi-GPU execution is not implemented (its sharding design is "
+              "documented only)", file=sys.stderr, flush=True)
         sys.exit(2)
     if args.copy_calibration_mib > 0:
         copy_calibration(args.copy_calibration_mib)
     {"brunel": bench_brunel, "stdp": bench_stdp, "sweep": bench_sweep, "bptt": bench_bptt,
-     "scaling": bench_scaling}[args.workload](args)
+     "scaling": bench_scaling, "setup": bench_setup, "layout": bench_layout}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -131,6 +131,13 @@ typedef struct {
     uint64_t spikes;        /* spikes dequeued and delivered */
     uint64_t touches;       /* plastic synapse updates */
     uint64_t device_bytes;  /* device memory held */
+    double build_ms;        /* host wall time of snn_build_network (allocation included) */
+    float gen_rows_ms;      /* device time of the row-length pass and its scan */
+    float gen_fill_ms;      /* device time of the synapse fill */
+    float index_ms;         /* device time of the delivery indexes (in-edge index with STDP,
+                               tile offsets of the tiled delivery; stream time between two
+                               events, host allocation gaps included) */
+    float pad2_;
 } snn_info;
 
 /* Host views for reading or writing the dynamic state; NULL members are skipped.

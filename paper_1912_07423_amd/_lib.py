@@ -67,7 +67,9 @@ class Info(C.Structure):
                 ("queue_groups", C.c_uint32), ("queue_stride", C.c_uint32),
                 ("source_weights", C.c_uint32),
                 ("nnz", C.c_uint64), ("t", C.c_uint64), ("events", C.c_uint64),
-                ("spikes", C.c_uint64), ("touches", C.c_uint64), ("device_bytes", C.c_uint64)]
+                ("spikes", C.c_uint64), ("touches", C.c_uint64), ("device_bytes", C.c_uint64),
+                ("build_ms", C.c_double), ("gen_rows_ms", C.c_float), ("gen_fill_ms", C.c_float),
+                ("index_ms", C.c_float), ("pad2_", C.c_float)]
 
 
 class State(C.Structure):

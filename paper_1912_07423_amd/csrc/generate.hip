@@ -7,6 +7,8 @@
 //  * fixed out-degree projections: the exponential-spacing generator of Fig. 2 with
 //    the gaps truncated to 2^-24 fixed point, so the prefix sum, normalisation,
 //    scaling, rounding and the +k step are exact integer arithmetic.
+#include <algorithm>
+
 #include "device_math.h"
 #include "snn_internal.h"
 
@@ -97,33 +99,50 @@ __device__ uint64_t er_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uin
   return pos;
 }
 
-// floor(num / den), den > 0, num + den < 2^64: a binary64 estimate (within one of the
-// quotient while the quotient is below 2^51) corrected to the exact integer quotient.
-// Far cheaper on the GPU than a 64-bit integer division.
-__device__ __forceinline__ uint64_t div_floor_u64(uint64_t num, uint64_t den) {
-  uint64_t q = (uint64_t)((double)num / (double)den);
+// floor(num / den) for den > 0 and num + 2 den < 2^64, given inv = 1 / den in binary64:
+// the estimate num * inv is within one of the quotient while the quotient is below 2^51,
+// and is corrected to the exact integer quotient.  Far cheaper on the GPU than a 64-bit
+// integer division.
+__device__ __forceinline__ uint64_t div_floor_u64(uint64_t num, uint64_t den, double inv) {
+  uint64_t q = (uint64_t)((double)num * inv);
   while (q * den > num) --q;
   while ((q + 1) * den <= num) ++q;
   return q;
 }
 
+// Gaps of one fixed out-degree row kept in LDS between the two passes (the first pass of
+// Sec. III-A.2 runs in shared memory): the first 4 x cache_blocks gaps of a row are
+// stored as uint32 (a gap is below 2^29: -ln(2^-24) 2^24 < 2.8e8) and read back by the
+// second pass; gaps past the cache are regenerated.  The cache is sized at launch to the
+// longest fixed out-degree row, at most kGapCacheMax gaps (20 KiB) per wavefront.
+constexpr uint32_t kGapCacheMax = 5120;
+
 __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint64_t pos,
-                           int32_t *col, int32_t *w_q16, float *w_f32) {
+                           int32_t *col, int32_t *w_q16, float *w_f32, uint4 *cache,
+                           uint32_t cache_blocks) {
   const uint32_t k_out = pj.k;
   if (k_out == 0) return;
   const uint32_t stream_word2 = 1u + pj.first_pop;
   const uint32_t n_blocks = (k_out + 1 + 3) / 4;  // gaps 0..k_out
   const uint32_t n_iter = (n_blocks + kWave - 1) / kWave;
-  // pass 1: total of the k_out + 1 gaps
+  // pass 1: total of the k_out + 1 gaps; the first kGapCache of them go to LDS.  Each
+  // block of four gaps is written and read back by the same lane, so no barrier.
   uint64_t part = 0;
   for (uint32_t b = lane_id(); b < n_blocks; b += kWave) {
     const Words4 r = philox(i, b, stream_word2, kStreamConn, g.key0, g.key1);
+    uint32_t gq[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (4u * b + q <= k_out) part += spacing_gap(r.w[q]);
+    for (int q = 0; q < 4; ++q) {
+      gq[q] = 4u * b + q <= k_out ? (uint32_t)spacing_gap(r.w[q]) : 0u;
+      part += gq[q];
+    }
+    if (b < cache_blocks) cache[b] = make_uint4(gq[0], gq[1], gq[2], gq[3]);
   }
   const uint64_t total = wave_sum(part);
   const uint64_t two_total = 2u * total;
+  const double inv_two_total = total != 0 ? 1.0 / (double)two_total : 0.0;
+  const double inv_total = total != 0 ? 1.0 / (double)total : 0.0;
+  const double half_total_d = 0.5 * (double)total, spare_d = (double)pj.spare;
   const uint32_t self_local = pj.self_in ? (i - pj.off) : 0xFFFFFFFFu;
   // pass 2: running sum S_{k+1}, round-half-up of S_{k+1} * spare / total, + k
   uint64_t carry = 0;
@@ -131,10 +150,18 @@ __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint
     const uint32_t b = it * kWave + lane_id();
     uint64_t gap[4] = {0, 0, 0, 0};
     if (b < n_blocks) {
-      const Words4 r = philox(i, b, stream_word2, kStreamConn, g.key0, g.key1);
+      if (b < cache_blocks) {
+        const uint4 c = cache[b];
+        gap[0] = c.x;
+        gap[1] = c.y;
+        gap[2] = c.z;
+        gap[3] = c.w;
+      } else {
+        const Words4 r = philox(i, b, stream_word2, kStreamConn, g.key0, g.key1);
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (4u * b + q <= k_out) gap[q] = spacing_gap(r.w[q]);
+        for (int q = 0; q < 4; ++q)
+          if (4u * b + q <= k_out) gap[q] = spacing_gap(r.w[q]);
+      }
     }
     const uint64_t lane_total = gap[0] + gap[1] + gap[2] + gap[3];
     const uint64_t incl = wave_inclusive_scan(lane_total);
@@ -145,7 +172,18 @@ __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint
       s += gap[q];  // S_{k+1}
       if (b < n_blocks && k < k_out) {
         uint64_t x = k;
-        if (total != 0) x = div_floor_u64(2u * s * pj.spare + total, two_total) + k;
+        if (total != 0) {
+          // q = floor(s spare / total + 1/2) < 2^32 from binary64: the six roundings
+          // below (s, total, fma, 1 / total, product) leave a relative error under
+          // 2^-50, i.e. under 2^-18 absolute, so the floor of the estimate is exact
+          // unless it lies that close to an integer; then the exact integer quotient.
+          const double est = fma((double)s, spare_d, half_total_d) * inv_total;
+          const double fl = floor(est), fr = est - fl;
+          const uint64_t q = (fr >= 0x1p-18 && fr <= 1.0 - 0x1p-18)
+                                 ? (uint64_t)fl
+                                 : div_floor_u64(2u * s * pj.spare + total, two_total, inv_two_total);
+          x = q + k;
+        }
         uint32_t local = (uint32_t)x;
         if (local >= self_local) local += 1;
         const uint64_t p = pos + k;
@@ -160,7 +198,9 @@ __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint
 
 __global__ __launch_bounds__(kGenBlock) void k_fill_rows(GenArgs g, const uint64_t *row_ptr,
                                                          int32_t *col, int32_t *w_q16,
-                                                         float *w_f32) {
+                                                         float *w_f32, uint32_t cache_blocks) {
+  extern __shared__ uint4 gap_cache[];  // [kGenWavesPerBlock][cache_blocks]
+  uint4 *cache = gap_cache + (threadIdx.x / kWave) * cache_blocks;
   const uint32_t wave = blockIdx.x * kGenWavesPerBlock + threadIdx.x / kWave;
   const uint32_t n_waves = gridDim.x * kGenWavesPerBlock;
   for (uint32_t i = wave; i < g.n; i += n_waves) {
@@ -171,7 +211,7 @@ __global__ __launch_bounds__(kGenBlock) void k_fill_rows(GenArgs g, const uint64
       if (pj.kind == SNN_PROJ_ER) {
         pos = er_fill(g, pj, i, pos, col, w_q16, w_f32);
       } else {
-        fixed_fill(g, pj, i, pos, col, w_q16, w_f32);
+        fixed_fill(g, pj, i, pos, col, w_q16, w_f32, cache, cache_blocks);
         pos += pj.k;
       }
     }
@@ -320,9 +360,22 @@ hipError_t launch_row_lengths(const GenArgs &g, uint32_t *len, uint32_t *plast_r
   return hipGetLastError();
 }
 
-hipError_t launch_fill_rows(const GenArgs &g, const uint64_t *row_ptr, int32_t *col,
-                            int32_t *w_q16, float *w_f32, hipStream_t s) {
-  k_fill_rows<<<row_grid(g.n), kGenBlock, 0, s>>>(g, row_ptr, col, w_q16, w_f32);
+hipError_t launch_fill_rows(const GenArgs &g, uint32_t max_fixed_k, const uint64_t *row_ptr,
+                            int32_t *col, int32_t *w_q16, float *w_f32, hipStream_t s) {
+  const uint32_t gaps = max_fixed_k ? std::min(max_fixed_k + 1, kGapCacheMax) : 0u;
+  uint32_t cache_blocks = (gaps + 3) / 4;
+  int dev = 0, lds_max = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  cache_blocks = std::min<uint32_t>(cache_blocks, (uint32_t)lds_max / (kGenWavesPerBlock * sizeof(uint4)));
+  const size_t lds = (size_t)kGenWavesPerBlock * cache_blocks * sizeof(uint4);
+  if (lds > 65536) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fill_rows),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  k_fill_rows<<<row_grid(g.n), kGenBlock, lds, s>>>(g, row_ptr, col, w_q16, w_f32, cache_blocks);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -280,6 +281,14 @@ void choose_delivery(snn_network *net) {
 }
 
 // ---- construction ----------------------------------------------------------------
+hipEvent_t new_event() {
+  hipEvent_t e;
+  // timing markers only: no system-scope fence when the event is recorded, so that a
+  // marker between two launches costs as little as possible
+  check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
+  return e;
+}
+
 void build(snn_network *net) {
   validate_and_derive(net);
   choose_schedule(net);
@@ -329,16 +338,29 @@ void build(snn_network *net) {
     net->plast_rel = dev_array<uint32_t>(net, n);
     net->plast_len = dev_array<uint32_t>(net, n);
   }
+  // setup timing: HIP events on the build stream around the generation phases
+  hipEvent_t ev[6];
+  for (hipEvent_t &e : ev) e = new_event();
+  struct EventGuard {
+    hipEvent_t *e;
+    ~EventGuard() {
+      for (int k = 0; k < 6; ++k) (void)hipEventDestroy(e[k]);
+    }
+  } ev_guard{ev};
+  check(hipEventRecord(ev[0], s), "hipEventRecord");
   check(snn::launch_row_lengths(g, len, net->plast_rel, net->plast_len, s), "row lengths");
   net->row_ptr = dev_array<uint64_t>(net, (size_t)n + 1);
   uint64_t *scan_tmp = dev_array<uint64_t>(net, snn::scan_scratch_elems(n));
   check(snn::launch_scan_u32_to_u64(len, net->row_ptr, n, scan_tmp, s), "row scan");
+  check(hipEventRecord(ev[1], s), "hipEventRecord");
   check(hipMemcpyAsync(&net->nnz, net->row_ptr + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s), "read nnz");
   check(hipStreamSynchronize(s), "sync after row scan");
   if (net->plastic && net->nnz >= (1ull << 32)) fail(SNN_E_INVALID, "plastic networks are limited to 2^32 synapses");
   net->nnz_alloc = ((net->nnz + 3) & ~3ull) + 4;  // 16-byte groups of the atomic delivery
   net->col = dev_array<int32_t>(net, net->nnz_alloc);
-  check(hipMemsetAsync(net->col, 0, net->nnz_alloc * 4, s), "clear col");
+  // the fill writes every synapse: only the padding past the last one is cleared here
+  const size_t pad_bytes = (net->nnz_alloc - net->nnz) * 4;
+  check(hipMemsetAsync(net->col + net->nnz, 0, pad_bytes, s), "clear col padding");
   // Table I layout: when every projection from a source population carries the same
   // weight, a synapse stores only its target and the weight is the source's
   bool src_uniform = !net->plastic && net->prm.synapse_weights == 0;
@@ -353,7 +375,7 @@ void build(snn_network *net) {
   }
   if (net->plastic) {
     net->w_f32 = dev_array<float>(net, net->nnz_alloc);
-    check(hipMemsetAsync(net->w_f32, 0, net->nnz_alloc * 4, s), "clear w");
+    check(hipMemsetAsync(net->w_f32 + net->nnz, 0, pad_bytes, s), "clear w padding");
   } else if (src_uniform) {
     net->w_src_host.assign(n, 0);
     for (uint32_t a = 0; a < n_pops; ++a)
@@ -363,9 +385,16 @@ void build(snn_network *net) {
           "copy source weights");
   } else {
     net->w_q16 = dev_array<int32_t>(net, net->nnz_alloc);
-    check(hipMemsetAsync(net->w_q16, 0, net->nnz_alloc * 4, s), "clear w");
+    check(hipMemsetAsync(net->w_q16 + net->nnz, 0, pad_bytes, s), "clear w padding");
   }
-  check(snn::launch_fill_rows(g, net->row_ptr, net->col, net->w_q16, net->w_f32, s), "fill rows");
+  uint32_t max_fixed_k = 0;
+  for (const snn::GenProj &q : gp)
+    if (q.kind == SNN_PROJ_FIXED_OUT) max_fixed_k = std::max(max_fixed_k, q.k);
+  check(hipEventRecord(ev[2], s), "hipEventRecord");
+  check(snn::launch_fill_rows(g, max_fixed_k, net->row_ptr, net->col, net->w_q16, net->w_f32, s),
+        "fill rows");
+  check(hipEventRecord(ev[3], s), "hipEventRecord");
+  check(hipEventRecord(ev[4], s), "hipEventRecord");
 
   if (net->plastic) {
     // plastic in-edges grouped by target: counting sort by target
@@ -391,6 +420,7 @@ void build(snn_network *net) {
     check(snn::launch_tile_offsets(net->row_ptr, net->col, n, net->tiles, net->tile_size, net->tile_off, s),
           "tile offsets");
   }
+  check(hipEventRecord(ev[5], s), "hipEventRecord");
 
   // neuron state, FIFO, raster, control block
   net->v = dev_array<float>(net, n);
@@ -444,6 +474,9 @@ void build(snn_network *net) {
   const float span = (float)(net->prm.v0_hi_mV - net->prm.v0_lo_mV);
   check(snn::launch_init_neurons(net->v, net->ref, n, net->key0, net->key1, lo, span, s), "init neurons");
   check(hipStreamSynchronize(s), "sync after build");
+  check(hipEventElapsedTime(&net->gen_rows_ms, ev[0], ev[1]), "hipEventElapsedTime");
+  check(hipEventElapsedTime(&net->gen_fill_ms, ev[2], ev[3]), "hipEventElapsedTime");
+  check(hipEventElapsedTime(&net->index_ms, ev[4], ev[5]), "hipEventElapsedTime");
 }
 
 // ---- the step pipeline --------------------------------------------------------------
@@ -536,14 +569,6 @@ hipError_t launch_delivery(snn_network *net, const snn::DeliverArgs &d, uint32_t
   if (net->delivery == SNN_DELIVERY_TILED)
     return snn::launch_deliver_tiled(d, steps, net->block, net->grid, net->stream);
   return snn::launch_deliver_atomic(d, steps, atomic_grid(net), net->stream);
-}
-
-hipEvent_t new_event() {
-  hipEvent_t e;
-  // timing markers only: no system-scope fence when the event is recorded, so that a
-  // marker between two launches costs as little as possible
-  check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
-  return e;
 }
 
 hipEvent_t pooled_event(snn_network *net) {
@@ -1263,7 +1288,9 @@ snn_status snn_build_network(const snn_params *prm, const snn_population *pops, 
         check(hipStreamCreateWithFlags(&net->stream, hipStreamNonBlocking), "hipStreamCreate");
         net->own_stream = true;
       }
+      const auto t0 = std::chrono::steady_clock::now();
       build(net);
+      net->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     } catch (...) {
       release(net);
       delete net;
@@ -1356,6 +1383,10 @@ snn_status snn_get_info(snn_network *net, snn_info *info) {
     r.spikes = c.spikes;
     r.touches = c.touches;
     r.device_bytes = net->device_bytes;
+    r.build_ms = net->build_ms;
+    r.gen_rows_ms = net->gen_rows_ms;
+    r.gen_fill_ms = net->gen_fill_ms;
+    r.index_ms = net->index_ms;
     if (c.t != net->t_host) fail(SNN_E_STATE, "device step counter disagrees with the host");
     *info = r;
   });

@@ -188,8 +188,8 @@ hipError_t prepare_deliver_tiled(uint32_t block, size_t *max_dynamic_lds);
 hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_row_lengths(const GenArgs &g, uint32_t *len, uint32_t *plast_rel,
                               uint32_t *plast_len, hipStream_t s);
-hipError_t launch_fill_rows(const GenArgs &g, const uint64_t *row_ptr, int32_t *col,
-                            int32_t *w_q16, float *w_f32, hipStream_t s);
+hipError_t launch_fill_rows(const GenArgs &g, uint32_t max_fixed_k, const uint64_t *row_ptr,
+                            int32_t *col, int32_t *w_q16, float *w_f32, hipStream_t s);
 hipError_t launch_scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint32_t n,
                                   uint64_t *block_sums, hipStream_t s);
 size_t scan_scratch_elems(uint32_t n);
@@ -215,6 +215,9 @@ struct snn_network {
   std::vector<snn_projection> proj;
   std::vector<uint32_t> pop_off;
   snn_params prm;
+  // setup timing (host wall time of the build; device time of its generation phases)
+  double build_ms = 0;
+  float gen_rows_ms = 0, gen_fill_ms = 0, index_ms = 0;
   uint32_t key0 = 0, key1 = 0;
 
   // sizes and schedule

@@ -151,7 +151,7 @@ class Network:
     def info(self):
         i = L.Info()
         L.check(self._lib.snn_get_info(self._h, C.byref(i)))
-        d = {k: getattr(i, k) for k, _ in L.Info._fields_ if k != "pad_"}
+        d = {k: getattr(i, k) for k, _ in L.Info._fields_ if not k.startswith("pad")}
         d["delivery_name"] = L.DELIVERY_NAME.get(d["delivery"], "?")
         return d
 

@@ -52,6 +52,21 @@ def test_generated_synapses_match_oracle(name):
         assert np.array_equal(w, o.w_q16())
 
 
+@pytest.mark.parametrize("k", [5119, 5120, 6001, 12000])
+def test_long_fixed_rows_match_oracle(k):
+    """Rows of k + 1 gaps around and past the generator's LDS gap cache (5,120 gaps per
+    row): the gaps beyond it are regenerated in the second pass."""
+    spec = W.brunel_fixed_out(n=max(6400, k + 400), k=k, delay_steps=3, steps=10)
+    print(f"[gen] fixed out-degree k={k}", flush=True)
+    g = _net(spec, raster_steps=16)
+    o = oracle.OracleNet(spec)
+    rp, col, _ = g.synapses()
+    assert np.array_equal(rp, o.row_ptr())
+    assert np.array_equal(col, o.col())
+    i = g.info()
+    assert i["build_ms"] > 0 and i["gen_fill_ms"] > 0 and i["gen_rows_ms"] > 0 and i["index_ms"] >= 0
+
+
 @pytest.mark.parametrize("name", list(_small_specs()))
 def test_initial_state_matches_oracle(name):
     spec = _small_specs()[name]
