@@ -408,6 +408,20 @@ __device__ void make_schedule(const uint32_t *cnt, uint32_t steps, uint32_t tile
   if (lane == 0) sch.first[0] = 0;
 }
 
+constexpr uint32_t kXcds = 8;  // accelerator complex dies, each with its own L2
+
+// Work unit of workgroup b among `units` (<= grid).  Workgroups are dispatched to the
+// XCDs round-robin (b on XCD b mod 8); units are numbered so that each XCD takes one
+// contiguous run of them.  Neighbouring tiles of a step then share, in one L2, the
+// cache lines that straddle their sub-rows and the step's row pointers and tile offsets.
+// Units past `units` are idle (returned as >= units).
+__device__ __forceinline__ uint32_t xcd_unit(uint32_t b, uint32_t grid, uint32_t units) {
+  if (grid % kXcds != 0) return b;
+  const uint32_t per = (units + kXcds - 1) / kXcds;  // <= grid / kXcds
+  const uint32_t j = b / kXcds;
+  return j < per ? (b % kXcds) * per + j : units;
+}
+
 // A workgroup owns (a range of consecutive base tiles, one emission step): it
 // accumulates that step's deliveries to the range's targets in LDS and then writes the
 // range's input accumulators.  Spikes are processed in chunks of kBlock: every thread
@@ -453,11 +467,12 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
   for (uint32_t j = threadIdx.x; j < kMaxTileGroup * a.tile_size; j += kBlock) acc[j] = 0;
   if (wave == 0) make_schedule(s_cnt, steps, a.tiles, gridDim.x, sch);
   __syncthreads();
-  if (blockIdx.x >= sch.first[steps]) return;  // more workgroups than ranges this window
+  const uint32_t unit = xcd_unit(blockIdx.x, gridDim.x, sch.first[steps]);
+  if (unit >= sch.first[steps]) return;  // more workgroups than ranges this window
   uint32_t w = 0;
-  while (sch.first[w + 1] <= blockIdx.x) ++w;
+  while (sch.first[w + 1] <= unit) ++w;
   const uint32_t m = sch.m[w];
-  const uint32_t tile_a = (blockIdx.x - sch.first[w]) * m;
+  const uint32_t tile_a = (unit - sch.first[w]) * m;
   const uint32_t tile_b = min(tile_a + m, a.tiles);
   const uint32_t tile_lo = tile_a * a.tile_size;
   const uint32_t tile_n = min(tile_b * a.tile_size, a.n) - tile_lo;
