@@ -223,6 +223,14 @@ def bench_stdp(args):
     smean = prof["stdp_ms"] / max(1, prof["stdp_launches"])
     b_ev, b_spk = delivery_bytes(i1)
     dbytes = (events * b_ev + spikes * b_spk) / max(1, prof["deliver_launches"])
+    # atomic throughput: one device-scope int32 add per synaptic event.  The run's rate
+    # inside the delivery kernel, against the same kernel saturated by one step of
+    # 20,000 spikes (about 4e7 events) over the same rows
+    import numpy as np
+    ids = np.random.default_rng(7).choice(i1["n"], 20_000, replace=False).astype(np.uint32)
+    ms_sat, ev_sat = net.time_delivery(ids, reps=5, steps=1)
+    achieved = events / (prof["deliver_ms"] * 1e-3) if prof["deliver_ms"] > 0 else 0.0
+    saturated = ev_sat / (ms_sat * 1e-3) if ms_sat > 0 else 0.0
     line("STDP network: synaptic events/sec, STDP synapse touches/sec, 1 GPU", events / wall, "events/s",
          steps, args.warmup, wall * 1e3 / steps, "fp32",
          {"workload": "stdp_er_100k_p0.02_d10_poisson10hz", "neurons": i1["n"], "synapses": i1["nnz"],
@@ -234,7 +242,11 @@ def bench_stdp(args):
          roofline={"bound": "hbm", "achieved": dbytes / (dmean * 1e-3) / 1e9 if dmean > 0 else 0.0,
                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
                    "frac": dbytes / (dmean * 1e-3) / 1e9 / HBM_PEAK_GBS if dmean > 0 else 0.0,
-                   "traffic": None, "kernel": "k_deliver_atomic"})
+                   "traffic": None, "kernel": "k_deliver_atomic"},
+         atomics={"kernel": "k_deliver_atomic", "per_event": "one device-scope int32 add",
+                  "achieved_per_s": achieved, "saturated_per_s": saturated,
+                  "frac": achieved / saturated if saturated > 0 else None,
+                  "saturated_by": f"one step of {len(ids)} spikes ({ev_sat} events)"})
     net.close()
 
 

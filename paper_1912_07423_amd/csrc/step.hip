@@ -231,8 +231,17 @@ __device__ __forceinline__ void close_window(const DeliverArgs &a, uint64_t t0, 
   }
 }
 
+// Disjoint parts per queued spike, one wavefront each, so that a launch's wavefronts
+// cover the spikes about once: a step of a plastic network has only ~100 spikes, which
+// one wavefront each would leave most of the GPU idle and walk each row serially.
+__device__ __forceinline__ uint32_t parts_for(uint32_t spikes, uint32_t waves, uint32_t max_parts) {
+  const uint32_t p = spikes ? waves / spikes : 1u;
+  return p < 1u ? 1u : (p > max_parts ? max_parts : p);
+}
+
 constexpr int kAtomicBlock = 256;
 constexpr int kAtomicWaves = kAtomicBlock / kWave;
+constexpr uint32_t kAtomicMaxParts = 32;
 
 constexpr int kWeightQ16 = 0, kWeightF32 = 1, kWeightSrc = 2;
 
@@ -269,7 +278,9 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
   const uint32_t gwave = blockIdx.x * kAtomicWaves + threadIdx.x / kWave;
   const uint32_t n_gwaves = gridDim.x * kAtomicWaves;
   uint64_t ev = 0, n_spk = 0;
-  for (uint32_t f = gwave; f < total; f += n_gwaves) {
+  const uint32_t parts = parts_for(total, n_gwaves, kAtomicMaxParts);
+  for (uint64_t item = gwave; item < (uint64_t)total * parts; item += n_gwaves) {
+    const uint32_t f = (uint32_t)(item / parts), part = (uint32_t)(item % parts);
     uint32_t w = 0;  // step of spike f: last w with s_step[w] <= f
     for (uint32_t half = kWave / 2; half > 0; half >>= 1)
       if (s_step[w + half] <= f) w += half;
@@ -281,7 +292,11 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
     int32_t *in = a.input + (size_t)ring_add(in0, w, a.n_inbuf) * a.n;
     const uint64_t rs = a.row_ptr[src], re = a.row_ptr[src + 1];
     const int32_t ws = kW == kWeightSrc ? a.w_src[src] : 0;
-    for (uint64_t g = (rs >> 2) + lane; g < ((re + 3) >> 2); g += kWave) {
+    // this part's contiguous share of the row's 16-byte groups
+    const uint64_t g_lo = rs >> 2, g_hi = (re + 3) >> 2;
+    const uint64_t share = (g_hi - g_lo + parts - 1) / parts;
+    const uint64_t p_lo = g_lo + part * share, p_hi = min(g_hi, p_lo + share);
+    for (uint64_t g = p_lo + lane; g < p_hi; g += kWave) {
       const int4 c4 = reinterpret_cast<const int4 *>(a.col)[g];
       int32_t wv[4];
       if constexpr (kW == kWeightSrc) {
@@ -307,8 +322,10 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
           __hip_atomic_fetch_add(in + cv[q], wv[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-    ev += re - rs;
-    ++n_spk;
+    if (part == 0) {
+      ev += re - rs;
+      ++n_spk;
+    }
   }
   if (lane == 0) {
     add_part(a.ctl->events, gwave, ev);
@@ -570,9 +587,9 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
 
 constexpr int kStdpBlock = 256;
 constexpr int kStdpWaves = kStdpBlock / kWave;
-// wavefronts sharing one queued spike's synapses (disjoint parts: still one writer per
-// synapse); a step has few spikes, so this is what fills the GPU
-constexpr uint32_t kStdpSplit = 16;
+// at most this many wavefronts share one queued spike's synapses (disjoint parts: still
+// one writer per synapse); a step has few spikes, so this is what fills the GPU
+constexpr uint32_t kStdpMaxSplit = 64;
 
 __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltd(StdpArgs a) {
   const uint64_t t = a.ctl->t;
@@ -584,15 +601,16 @@ __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltd(StdpArgs a) {
   const uint32_t lane = lane_id();
   const uint32_t gwave = blockIdx.x * kStdpWaves + threadIdx.x / kWave;
   const uint32_t n_gwaves = gridDim.x * kStdpWaves;
+  const uint32_t split = parts_for(cnt, n_gwaves, kStdpMaxSplit);
   uint64_t touched = 0;
-  for (uint64_t item = gwave; item < (uint64_t)cnt * kStdpSplit; item += n_gwaves) {
-    const uint32_t s = (uint32_t)(item / kStdpSplit), part = (uint32_t)(item % kStdpSplit);
+  for (uint64_t item = gwave; item < (uint64_t)cnt * split; item += n_gwaves) {
+    const uint32_t s = (uint32_t)(item / split), part = (uint32_t)(item % split);
     const int32_t i = queue_entry(a.q, slot, pre, s);
     if ((uint32_t)i >= a.n) continue;
     if (part == 0 && lane == 0) a.x_pre[i] = a.x_pre[i] + 1.0f;
     const uint64_t lo = a.row_ptr[i] + a.plast_rel[i];
     const uint32_t len = a.plast_len[i];
-    const uint32_t chunk = (len + kStdpSplit - 1) / kStdpSplit;
+    const uint32_t chunk = (len + split - 1) / split;
     const uint32_t k0 = part * chunk, k1 = min(len, k0 + chunk);
     for (uint32_t k = k0 + lane; k < k1; k += kWave) {
       const uint64_t e = lo + k;
@@ -615,14 +633,15 @@ __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltp(StdpArgs a) {
   const uint32_t lane = lane_id();
   const uint32_t gwave = blockIdx.x * kStdpWaves + threadIdx.x / kWave;
   const uint32_t n_gwaves = gridDim.x * kStdpWaves;
+  const uint32_t split = parts_for(cnt, n_gwaves, kStdpMaxSplit);
   uint64_t touched = 0;
-  for (uint64_t item = gwave; item < (uint64_t)cnt * kStdpSplit; item += n_gwaves) {
-    const uint32_t s = (uint32_t)(item / kStdpSplit), part = (uint32_t)(item % kStdpSplit);
+  for (uint64_t item = gwave; item < (uint64_t)cnt * split; item += n_gwaves) {
+    const uint32_t s = (uint32_t)(item / split), part = (uint32_t)(item % split);
     const int32_t j = queue_entry(a.q, slot, pre, s);
     if ((uint32_t)j >= a.n) continue;
     if (part == 0 && lane == 0) a.x_post[j] = a.x_post[j] + 1.0f;
     const uint64_t lo = a.in_ptr[j], len = a.in_ptr[j + 1] - lo;
-    const uint64_t chunk = (len + kStdpSplit - 1) / kStdpSplit;
+    const uint64_t chunk = (len + split - 1) / split;
     const uint64_t m0 = lo + part * chunk, m1 = min(lo + len, m0 + chunk);
     for (uint64_t m = m0 + lane; m < m1; m += kWave) {
       const uint32_t e = a.in_edge[m];
