@@ -1,7 +1,9 @@
 """Pins of the oracle's random-number, logarithm, spacing and drive-table functions
 against values fixed outside the oracle (published vectors, the paper's worked
 example, libm, scipy)."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -10,15 +12,15 @@ import scipy.stats
 import oracle
 
 # Known-answer vectors published with the Random123 library for Philox4x32 with 10
-# rounds: (counter words, key words) -> output words.
-PHILOX_KAT = [
-    ([0x00000000, 0x00000000, 0x00000000, 0x00000000], [0x00000000, 0x00000000],
-     [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]),
-    ([0xffffffff, 0xffffffff, 0xffffffff, 0xffffffff], [0xffffffff, 0xffffffff],
-     [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]),
-    ([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], [0xa4093822, 0x299f31d0],
-     [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]),
-]
+# rounds: (counter words, key words) -> output words; tests/golden/philox4x32_10_kat.json.
+def _kat():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.json")) as f:
+        vec = json.load(f)["vectors"]
+    return [([int(x, 16) for x in v["counter"]], [int(x, 16) for x in v["key"]],
+             [int(x, 16) for x in v["output"]]) for v in vec]
+
+
+PHILOX_KAT = _kat()
 
 
 @pytest.mark.parametrize("ctr,key,expected", PHILOX_KAT)
@@ -49,14 +51,18 @@ def test_neg_log_matches_libm():
 
 
 def test_fig2_worked_example():
-    """Fig. 2: n = 6 sorted distinct integers from [0, 100) out of the uniforms (a)."""
-    a = [0.46, 0.97, 0.22, 0.81, 0.98, 0.38, 0.70, 0.18]
-    b_printed = [0.78, 0.03, 1.51, 0.21, 0.02, 0.97, 0.36, 1.71]
-    c_printed = [0.0, 0.78, 0.81, 2.32, 2.53, 2.55, 3.52, 3.88]
-    d_printed = [0.0, 0.2, 0.21, 0.4, 0.6, 0.65, 0.9, 1.0]
-    e_printed = [0, 19, 20, 38, 56, 61, 85, 94]
-    g_printed = [19, 21, 40, 59, 65, 90]
-    n, lo, hi = 6, 0, 100
+    """Fig. 2: n = 6 sorted distinct integers from [0, 100) out of the uniforms (a); the
+    printed rows are in tests/golden/fig2_worked_example.json."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fig2_worked_example.json")) as f:
+        fx = json.load(f)
+    a = fx["a_uniforms"]
+    b_printed = fx["b_neg_log"]
+    c_printed = fx["c_exclusive_sum"]
+    d_printed = fx["d_normalised"]
+    e_printed = fx["e_scaled_rounded"]
+    g_printed = fx["g_result"]
+    n = fx["n"]
+    lo, hi = fx["range"]
     # (a) -> (b): -log, to the two printed decimals
     for u, b in zip(a, b_printed):
         assert abs(oracle.neg_log(u) - b) <= 0.0051
