@@ -326,7 +326,7 @@ def bench_bptt(args):
             plan.forward(x, w_in, w_rec, w_out, y)
 
     def timed(fn, n):
-        for _ in range(max(1, args.warmup // 5)):
+        for _ in range(max(1, min(10, args.warmup // 5))):  # untimed iterations
             fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
