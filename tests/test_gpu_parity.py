@@ -235,3 +235,44 @@ def test_autotune_delivery_keeps_state_and_parity():
     o.run(150)
     assert np.array_equal(g.raster_bits(0, 150), o.raster_words()[:150])
     assert np.array_equal(_bits(g.state()["v"]), _bits(o.v()))
+
+
+@pytest.mark.parametrize("delivery", ["atomic", "tiled"])
+def test_network_without_synapses(delivery):
+    """p = 0: every row is empty; the drive alone makes the neurons fire."""
+    spec = W.cuba_lif_4k(n_exc=700, n_inh=190, p=0.0, steps=200)
+    spec["params"].update(n_ext=500, rate_ext_hz=40.0, w_ext_mV=0.4)
+    print(f"[edge] no synapses, {delivery}", flush=True)
+    rg, inf = _compare_run(spec, 200, delivery=delivery)
+    assert inf["nnz"] == 0 and rg.any() and inf["events"] == 0
+
+
+@pytest.mark.parametrize("delivery", ["atomic", "tiled"])
+def test_delay_of_one_step(delivery):
+    """d = 1: one-step windows, every spike delivered by the very next update."""
+    spec = W.brunel_fixed_out(n=1500, k=120, delay_steps=1, steps=300)
+    print(f"[edge] d = 1, {delivery}", flush=True)
+    _, inf = _compare_run(spec, 300, delivery=delivery)
+    assert inf["window"] == 1
+
+
+def test_two_single_neuron_populations():
+    """The smallest network: two populations of one neuron, all-to-all between them."""
+    spec = W.cuba_lif_4k(n_exc=1, n_inh=1, p=1.0, steps=300)
+    spec["params"].update(n_ext=50, rate_ext_hz=500.0, w_ext_mV=0.6)
+    print("[edge] 1 + 1 neurons", flush=True)
+    rg, inf = _compare_run(spec, 300)
+    assert inf["nnz"] == 2
+
+
+def test_fixed_out_degree_to_every_other_neuron():
+    """K = n - 1 over all n neurons: no spare slot, every row is every other neuron
+    (the spacing generator's degenerate case)."""
+    spec = W.brunel_fixed_out(n=400, k=399, delay_steps=3, steps=150)
+    print("[edge] K = n - 1", flush=True)
+    g = _net(spec)
+    o = oracle.OracleNet(spec)
+    rp, col, _ = g.synapses()
+    assert np.array_equal(rp, o.row_ptr())
+    assert np.array_equal(col, o.col())
+    _compare_run(spec, 150)
