@@ -448,9 +448,25 @@ def bench_scaling(args):
             i1 = net.info()
             spikes = int(net.raster(args.warmup, args.warmup + steps).sum())
             dt = spec["params"]["dt_ms"] * 1e-3
+            # the delivery kernel's roofline, from a separate profiled pass (HIP events
+            # between the launches, which the timed run above does without)
+            net.set_profiling(True)
+            net.reset_profile()
+            ip = net.info()
+            net.run(min(steps, 300))
+            net.sync()
+            prof = net.profile()
+            iq = net.info()
+            net.set_profiling(False)
+            b_ev, b_spk = delivery_bytes(iq)
+            launches = max(1, prof["deliver_launches"])
+            d_ms = prof["deliver_ms"] / launches
+            d_bytes = ((iq["events"] - ip["events"]) * b_ev + (iq["spikes"] - ip["spikes"]) * b_spk) / launches
+            d_gbs = d_bytes / (d_ms * 1e-3) / 1e9 if d_ms > 0 else 0.0
             p = {"model": model, "neurons": n, "synapses": i1["nnz"], "c": W.eq1_scale(model, n),
                  "wall_s_per_sim_s": wall / (steps * dt), "events_per_s": (i1["events"] - i0["events"]) / wall,
-                 "rate_hz": spikes / n / (steps * dt), "delivery": i1["delivery_name"]}
+                 "rate_hz": spikes / n / (steps * dt), "delivery": i1["delivery_name"],
+                 "deliver_us_mean": d_ms * 1e3, "deliver_gbs": d_gbs, "deliver_hbm_frac": d_gbs / HBM_PEAK_GBS}
             points.append(p)
             print(f"[bench] {json.dumps(p)}", file=sys.stderr, flush=True)
             net.close()
