@@ -8,6 +8,8 @@ times: the whole HIP path against the oracle's complete run of the same network.
     schedule, exactly as benchmarked.
   * 100,000-neuron plastic network (ER p = 0.02, 2e8 synapses, STDP on E->E, 10-step
     delay): all 2,000 steps, final FP32 weights of every synapse compared bit for bit.
+  * the largest Eq. 1 Brunel network (400,000 neurons, 1.6e10 synapses): sampled rows,
+    and two steps' deliveries (after 300 steps) recomputed by the oracle from the GPU's own spikes.
 
 Spike rasters, refractory counters, pending Q16 inputs and event/touch counts must be
 identical, and binary32 state (V, traces, weights) bit-identical.  The oracle builds
@@ -70,3 +72,39 @@ def test_stdp_100k_all_2000_steps():
     assert inf["plastic"] and inf["touches"] > 0
     print(f"[full] stdp: {int(np.unpackbits(rg.view(np.uint8)).sum())} spikes, "
           f"{inf['events']} events, {inf['touches']} touches", flush=True)
+
+
+def _ids(row_words, n):
+    return np.nonzero(np.unpackbits(np.ascontiguousarray(row_words).view(np.uint8), bitorder="little")[:n])[0]
+
+
+def test_eq1_brunel_400k_1_6e10_synapses():
+    """The largest network of the Eq. 1 size sweep (400,000 neurons, out-degree 40,000,
+    1.6e10 synapses, 64 GB), too large for the oracle to hold: sampled rows against the
+    oracle's row generator, and after 20 windows the pending input of two arrival
+    steps against the oracle delivering the GPU's own spikes of their emission steps
+    row by row; every delivered spike counts exactly 40,000 events."""
+    n, k = 400_000, 40_000
+    spec = W.brunel_scaled(n)
+    g = net(spec, raster_steps=64)
+    inf = g.info()
+    assert inf["nnz"] == n * k and inf["delivery"] == 2
+    rng = np.random.default_rng(11)
+    for i in [0, 319_999, 320_000, 399_999] + [int(x) for x in rng.integers(0, n, 4)]:
+        col, w = g.row(i)
+        ocol, owq, _ = oracle.gen_row(spec, i)
+        assert np.array_equal(col, ocol) and np.array_equal(w, owq), f"row {i}"
+    d = inf["delay"]
+    steps = 20 * inf["window"]  # past the start-up burst
+    print(f"[full] brunel_scaled n={n}: {steps} steps", flush=True)
+    g.run(steps)
+    inf = g.info()
+    assert inf["events"] == k * inf["spikes"] and inf["spikes"] > 0
+    s = g.state()
+    raster = g.raster_bits(steps - d, steps)
+    for e in (steps - d, steps - 1):
+        ids = _ids(raster[e - (steps - d)], n)
+        ref, ev = oracle.deliver_generated(spec, ids, n)
+        assert ev == k * len(ids)
+        assert np.array_equal(s["input"][(e + d) % inf["input_buffers"]], ref), f"emission step {e}"
+        print(f"[full] step {e}: {len(ids)} spikes delivered identically", flush=True)
