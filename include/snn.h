@@ -247,6 +247,24 @@ snn_status snn_autotune_delivery(snn_network *net, uint32_t reps, snn_delivery_t
 void snn_destroy(snn_network *net);
 const char *snn_last_error(void);
 
+/* ---- Device-memory cache (Sec. IV: allocate only when necessary, with hysteresis) ---
+ *
+ * Networks, batches and BPTT plans built without an allocator callback take device
+ * memory from the library's cache.  Destroying them keeps their blocks.  A later
+ * request on the same device is served by the smallest kept block that is at least as
+ * large and at most twice as large (plus 1 MiB); otherwise it is served by hipMalloc.
+ * So back-to-back experiments pay for allocation once.  When hipMalloc fails, the
+ * device's kept blocks are released and the request is retried once.  Blocks are kept
+ * only after their stream has drained.
+ *
+ * snn_memory_cache_stats: bytes and blocks kept on `device`, and the requests served
+ * from the cache (hits) and by hipMalloc (misses) since the process started; NULL
+ * outputs are skipped.  snn_memory_cache_release: return the kept blocks of `device`
+ * (every device if negative) to HIP.  Neither call touches memory that is in use. */
+snn_status snn_memory_cache_stats(int device, uint64_t *bytes, uint64_t *blocks, uint64_t *hits,
+                                  uint64_t *misses);
+snn_status snn_memory_cache_release(int device);
+
 /* ---- Batched form: many independent static networks, one persistent launch -------
  *
  * Parameter sweeps and seed studies run hundreds of small networks of uneven size.

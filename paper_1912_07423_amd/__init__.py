@@ -6,7 +6,7 @@ The simulation runs in hand-written HIP kernels behind the C ABI of include/snn.
 persistent launch) are its Python binding.  `workloads` holds the synthetic network
 descriptions.
 """
-__all__ = ["Network", "Batch", "SnnError", "library_path"]
+__all__ = ["Network", "Batch", "SnnError", "library_path", "memory_cache_stats", "memory_cache_release"]
 
 
 def __getattr__(name):
@@ -16,6 +16,9 @@ def __getattr__(name):
     if name == "Batch":
         from .network import Batch
         return Batch
+    if name in ("memory_cache_stats", "memory_cache_release"):
+        from . import network
+        return getattr(network, name)
     if name == "SnnError":
         from ._lib import SnnError
         return SnnError

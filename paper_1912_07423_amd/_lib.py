@@ -127,6 +127,9 @@ SIGNATURES = {
     "snn_get_profile": (C.c_int32, [C.c_void_p, C.POINTER(Profile)]),
     "snn_reset_profile": (C.c_int32, [C.c_void_p]),
     "snn_sync": (C.c_int32, [C.c_void_p]),
+    "snn_memory_cache_stats": (C.c_int32, [C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                           C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "snn_memory_cache_release": (C.c_int32, [C.c_int]),
     "snn_time_delivery": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_uint32,
                                       C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "snn_set_delivery": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]),

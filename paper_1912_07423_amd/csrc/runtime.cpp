@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -54,6 +56,76 @@ snn_status guarded(F &&f) {
 }
 
 // ---- device memory --------------------------------------------------------------
+// Without an allocator callback, device memory comes from the library's own cache
+// (Sec. IV: memory is allocated only when necessary, with hysteresis, so back-to-back
+// experiments pay for allocation once).  A freed block is kept per device; a request is
+// served by the smallest kept block that is at least as large and at most twice as
+// large (plus 1 MiB), else by hipMalloc.  When hipMalloc fails, the device's kept blocks
+// are returned to HIP and the request is tried once more.  Blocks are handed back only
+// after their network's stream has drained (every caller frees after a stream sync), so
+// no work can still touch a reused block.
+struct PoolBlock {
+  int device;
+  void *p;
+  size_t bytes;
+};
+std::mutex g_pool_mutex;
+std::vector<PoolBlock> g_pool;  // kept blocks
+struct PoolStats {
+  uint64_t hits = 0, misses = 0;
+};
+std::map<int, PoolStats> g_pool_stats;
+
+// Returns the kept blocks of `device` (every device if negative) to HIP.
+void pool_release(int device) {
+  std::vector<PoolBlock> drop;
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mutex);
+    std::vector<PoolBlock> keep;
+    for (const PoolBlock &b : g_pool) (device < 0 || b.device == device ? drop : keep).push_back(b);
+    g_pool.swap(keep);
+  }
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return;
+  for (const PoolBlock &b : drop) {
+    if (b.device != cur) (void)hipSetDevice(b.device);
+    (void)hipFree(b.p);
+    if (b.device != cur) (void)hipSetDevice(cur);
+  }
+}
+
+void *pool_alloc(int device, size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mutex);
+    size_t best = g_pool.size();
+    for (size_t k = 0; k < g_pool.size(); ++k) {
+      const PoolBlock &b = g_pool[k];
+      if (b.device != device || b.bytes < bytes || b.bytes > 2 * bytes + (1u << 20)) continue;
+      if (best == g_pool.size() || b.bytes < g_pool[best].bytes) best = k;
+    }
+    if (best != g_pool.size()) {
+      void *p = g_pool[best].p;
+      g_pool.erase(g_pool.begin() + (std::ptrdiff_t)best);
+      ++g_pool_stats[device].hits;
+      return p;
+    }
+    ++g_pool_stats[device].misses;
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) == hipSuccess) return p;
+  (void)hipGetLastError();
+  pool_release(device);
+  if (hipMalloc(&p, bytes) == hipSuccess) return p;
+  (void)hipGetLastError();
+  return nullptr;
+}
+
+// Keeps a block for reuse; its size is the rounded size it was allocated with.
+void pool_free(int device, void *p, size_t bytes) {
+  std::lock_guard<std::mutex> lock(g_pool_mutex);
+  g_pool.push_back({device, p, bytes});
+}
+
 void *dev_alloc(snn_network *net, size_t bytes) {
   if (bytes == 0) bytes = 16;
   bytes = (bytes + 255) & ~(size_t)255;
@@ -62,11 +134,8 @@ void *dev_alloc(snn_network *net, size_t bytes) {
     p = net->alloc.alloc(bytes, (void *)net->stream, net->alloc.ctx);
     if (!p) fail(SNN_E_OOM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
   } else {
-    const hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      fail(SNN_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-    }
+    p = pool_alloc(net->device, bytes);
+    if (!p) fail(SNN_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
   net->allocs.push_back({p, bytes});
   net->device_bytes += bytes;
@@ -83,7 +152,7 @@ void release(snn_network *net) {
   if (net->graph) (void)hipGraphExecDestroy(net->graph);
   for (auto &a : net->allocs) {
     if (net->has_alloc) net->alloc.free(a.p, a.bytes, (void *)net->stream, net->alloc.ctx);
-    else (void)hipFree(a.p);
+    else pool_free(net->device, a.p, a.bytes);
   }
   net->allocs.clear();
   std::vector<hipEvent_t> pend;
@@ -730,7 +799,7 @@ void dev_free(snn_network *net, void *p) {
   for (size_t k = 0; k < net->allocs.size(); ++k)
     if (net->allocs[k].p == p) {
       if (net->has_alloc) net->alloc.free(p, net->allocs[k].bytes, (void *)net->stream, net->alloc.ctx);
-      else (void)hipFree(p);
+      else pool_free(net->device, p, net->allocs[k].bytes);
       net->device_bytes -= net->allocs[k].bytes;
       net->allocs.erase(net->allocs.begin() + (std::ptrdiff_t)k);
       return;
@@ -832,9 +901,10 @@ double time_delivery(snn_network *net, const std::vector<std::vector<uint32_t>> 
     ms_out = ms / reps;
     if (events) *events = sum_ctl(c1[0]).events / (reps + 1);
   } catch (...) {
+    (void)hipStreamSynchronize(s);  // no launch may still use the scratch handed back below
     for (size_t k = mark.size(); k < net->allocs.size(); ++k) {
       if (net->has_alloc) net->alloc.free(net->allocs[k].p, net->allocs[k].bytes, (void *)s, net->alloc.ctx);
-      else (void)hipFree(net->allocs[k].p);
+      else pool_free(net->device, net->allocs[k].p, net->allocs[k].bytes);
     }
     net->allocs.resize(mark.size());
     net->device_bytes = bytes_before;
@@ -842,7 +912,7 @@ double time_delivery(snn_network *net, const std::vector<std::vector<uint32_t>> 
   }
   for (size_t k = mark.size(); k < net->allocs.size(); ++k) {
     if (net->has_alloc) net->alloc.free(net->allocs[k].p, net->allocs[k].bytes, (void *)s, net->alloc.ctx);
-    else (void)hipFree(net->allocs[k].p);
+    else pool_free(net->device, net->allocs[k].p, net->allocs[k].bytes);
   }
   net->allocs.resize(mark.size());
   net->device_bytes = bytes_before;
@@ -1314,6 +1384,28 @@ snn_status snn_run(snn_network *net, uint32_t n_steps) {
     refuse_member(net);
     run(net, n_steps);
   });
+}
+
+snn_status snn_memory_cache_stats(int device, uint64_t *bytes, uint64_t *blocks, uint64_t *hits,
+                                  uint64_t *misses) {
+  return guarded([&] {
+    std::lock_guard<std::mutex> lock(g_pool_mutex);
+    uint64_t b = 0, n = 0;
+    for (const PoolBlock &k : g_pool)
+      if (k.device == device) {
+        b += k.bytes;
+        ++n;
+      }
+    const PoolStats st = g_pool_stats.count(device) ? g_pool_stats[device] : PoolStats{};
+    if (bytes) *bytes = b;
+    if (blocks) *blocks = n;
+    if (hits) *hits = st.hits;
+    if (misses) *misses = st.misses;
+  });
+}
+
+snn_status snn_memory_cache_release(int device) {
+  return guarded([&] { pool_release(device); });
 }
 
 snn_status snn_sync(snn_network *net) {

@@ -360,3 +360,18 @@ class Batch:
     def set_tuning(self, block, degree_div):
         t = L.BatchTuning(block=int(block), degree_div=int(degree_div))
         L.check(self._lib.snn_batch_set_tuning(self._h, C.byref(t)))
+
+
+def memory_cache_stats(device=0):
+    """The library's device-memory cache on `device` (used by objects built with
+    torch_memory=False): kept bytes and blocks, and requests served from the cache
+    (hits) or by hipMalloc (misses)."""
+    lib = L.load()
+    vals = [C.c_uint64() for _ in range(4)]
+    L.check(lib.snn_memory_cache_stats(device, *[C.byref(v) for v in vals]))
+    return dict(zip(("bytes", "blocks", "hits", "misses"), (v.value for v in vals)))
+
+
+def memory_cache_release(device=-1):
+    """Return the cache's kept blocks of `device` (every device if negative) to HIP."""
+    L.check(L.load().snn_memory_cache_release(device))

@@ -276,3 +276,33 @@ def test_fixed_out_degree_to_every_other_neuron():
     assert np.array_equal(rp, o.row_ptr())
     assert np.array_equal(col, o.col())
     _compare_run(spec, 150)
+
+
+def test_memory_cache_reuses_blocks_with_identical_results():
+    """Without torch's allocator, device memory comes from the library's cache: after a
+    network is destroyed its blocks are kept, a rebuild of the same spec is served from
+    them entirely (no hipMalloc), and the run on reused memory is the oracle's."""
+    from paper_1912_07423_amd import memory_cache_release, memory_cache_stats
+    spec = W.brunel_fixed_out(n=3000, k=300, delay_steps=15, steps=200)
+    memory_cache_release()
+    assert memory_cache_stats()["bytes"] == 0
+    a = _net(spec, torch_memory=False, raster_steps=200)
+    a.run(200)
+    first = a.raster_bits(0, 200)
+    held = a.info()["device_bytes"]
+    a.close()
+    st0 = memory_cache_stats()
+    assert st0["bytes"] >= held and st0["blocks"] > 0
+    b = _net(spec, torch_memory=False, raster_steps=200)
+    st1 = memory_cache_stats()
+    assert st1["misses"] == st0["misses"] and st1["hits"] >= st0["hits"] + st0["blocks"]
+    assert st1["bytes"] == 0
+    o = oracle.OracleNet(spec, raster_cap=200)
+    b.run(200)
+    o.run(200)
+    from gpu_compare import compare_net
+    compare_net(b, o, 200)
+    assert np.array_equal(b.raster_bits(0, 200), first)
+    b.close()
+    memory_cache_release()
+    assert memory_cache_stats()["bytes"] == 0
