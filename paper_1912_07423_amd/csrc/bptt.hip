@@ -107,7 +107,8 @@ __device__ __forceinline__ float ordered_gather_sum(float acc, uint64_t e0, uint
 // It does not depend on the recurrent state, so all steps run in parallel (a wavefront
 // per (t, j)).
 __global__ __launch_bounds__(256) void k_input_current(BpttArgs a) {
-  const uint64_t w = (uint64_t)blockIdx.x * 4 + threadIdx.x / kWave;
+  // wave-uniform index (readfirstlane lets the edge lists be read with scalar loads)
+  const uint64_t w = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   if (w >= (uint64_t)a.T * a.H) return;
   const uint32_t t = (uint32_t)(w / a.H), j = (uint32_t)(w % a.H);
   const uint32_t b = lane_id();
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(256) void k_input_current(BpttArgs a) {
 // set, s_out[j][b].
 __global__ __launch_bounds__(256) void k_hidden_step(BpttArgs a, uint32_t t, const float *vprev,
                                                      const float *sprev, float *v_out, float *s_out) {
-  const uint32_t j = blockIdx.x * 4 + threadIdx.x / kWave;
+  const uint32_t j = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   if (j >= a.H) return;
   const uint32_t b = lane_id();
   float acc = a.iin[((size_t)t * a.H + j) * 64 + b];
@@ -226,7 +227,7 @@ __global__ void k_lam_u(BpttArgs a, const float *g_loss) {
 // lam_next = lamV_{t+1} ([H][64], zeros past the end), v_t = V_t, lam_out = lamV_t.
 __global__ __launch_bounds__(256) void k_adjoint_step(BpttArgs a, uint32_t t, const float *v_t,
                                                       const float *lam_next, float *lam_out) {
-  const uint32_t i = blockIdx.x * 4 + threadIdx.x / kWave;
+  const uint32_t i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   if (i >= a.H) return;
   const uint32_t b = lane_id();
   const float *lu = a.lamu + (size_t)t * a.O * 64 + b;
