@@ -46,14 +46,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "synaptic events/sec and % HBM roofline, 1 GPU; wall-time per simulated second"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes of spike delivery: per synaptic event the target id (4 B) and, when
-# weights are stored per synapse, the weight (4 B); per dequeued spike its id and its row
-# pointers (4 + 8 B) and, with one weight per source, that weight (4 B)
+# algorithmic bytes of spike delivery: per synaptic event the target id (2 B from the
+# tiled delivery's 16-bit target copy, 4 B for the atomic delivery) and, when weights are
+# stored per synapse, the weight (4 B); per dequeued spike its id and its row pointers
+# (4 + 8 B) and, with one weight per source, that weight (4 B)
 
 
 def delivery_bytes(info):
-    """(bytes per event, bytes per dequeued spike) of the network's weight layout."""
-    return (4, 16) if info.get("source_weights") else (8, 12)
+    """(bytes per event, bytes per dequeued spike) of the network's delivery layout."""
+    tb = int(info.get("target_bytes", 4))
+    return (tb, 16) if info.get("source_weights") else (tb + 4, 12)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_deliver_tiled_brunel_200k_k5000_d15.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1912_07423_amd", "csrc", "step.hip")
 

@@ -137,7 +137,12 @@ typedef struct {
     float index_ms;         /* device time of the delivery indexes (in-edge index with STDP,
                                tile offsets of the tiled delivery; stream time between two
                                events, host allocation gaps included) */
-    float pad2_;
+    uint32_t tile_offset_bytes; /* bytes per stored tile boundary of the tiled delivery: 2
+                                   (every row below 65,536 synapses) or 4; 0 without tiles */
+    uint32_t target_bytes;  /* bytes per target the delivery reads: 2 for the tiled delivery
+                               (a 16-bit copy of the targets, held beside the 4-byte
+                               array), 4 for the atomic delivery */
+    uint32_t pad3_;
 } snn_info;
 
 /* Host views for reading or writing the dynamic state; NULL members are skipped.

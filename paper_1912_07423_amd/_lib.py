@@ -69,7 +69,8 @@ class Info(C.Structure):
                 ("nnz", C.c_uint64), ("t", C.c_uint64), ("events", C.c_uint64),
                 ("spikes", C.c_uint64), ("touches", C.c_uint64), ("device_bytes", C.c_uint64),
                 ("build_ms", C.c_double), ("gen_rows_ms", C.c_float), ("gen_fill_ms", C.c_float),
-                ("index_ms", C.c_float), ("pad2_", C.c_float)]
+                ("index_ms", C.c_float), ("tile_offset_bytes", C.c_uint32),
+                ("target_bytes", C.c_uint32), ("pad3_", C.c_uint32)]
 
 
 class State(C.Structure):

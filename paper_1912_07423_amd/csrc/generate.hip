@@ -306,10 +306,14 @@ __global__ __launch_bounds__(kGenBlock) void k_fill_in(const uint64_t *row_ptr, 
 }
 
 // ---- boundaries of the target tiles inside every (sorted) row ----
+// Entry p of row i is the offset, from the row's start, of the row's first target
+// >= p * tile_size (entry `tiles` is the row length).  Stored as uint16 when every row is
+// shorter than 65,536 synapses, which halves the bytes a delivery workgroup reads per
+// spike for a given number of tiles.
 __global__ __launch_bounds__(kGenBlock) void k_tile_offsets(const uint64_t *row_ptr,
                                                             const int32_t *col, uint32_t n,
                                                             uint32_t tiles, uint32_t tile_size,
-                                                            uint32_t *tile_off) {
+                                                            void *tile_off, bool off16) {
   const uint32_t wave = blockIdx.x * kGenWavesPerBlock + threadIdx.x / kWave;
   const uint32_t n_waves = gridDim.x * kGenWavesPerBlock;
   for (uint32_t i = wave; i < n; i += n_waves) {
@@ -328,8 +332,38 @@ __global__ __launch_bounds__(kGenBlock) void k_tile_offsets(const uint64_t *row_
         }
         rel = a - lo;
       }
-      tile_off[(uint64_t)i * (tiles + 1) + p] = (uint32_t)rel;
+      const uint64_t at = (uint64_t)i * (tiles + 1) + p;
+      if (off16) static_cast<uint16_t *>(tile_off)[at] = (uint16_t)rel;
+      else static_cast<uint32_t *>(tile_off)[at] = (uint32_t)rel;
     }
+  }
+}
+
+// col16[e] = col[e] mod 2^16 for e < nnz, 0 for the padding up to count: the tiled
+// delivery's 2-byte target stream (a range spans fewer than 65,536 targets, so the low
+// 16 bits identify a target inside it).  Each thread converts 8 targets (two int4 loads,
+// one int4 store).
+__global__ __launch_bounds__(kGenBlock) void k_narrow_targets(const int32_t *col, uint64_t nnz,
+                                                              uint64_t groups, uint16_t *col16) {
+  const uint64_t stride = (uint64_t)gridDim.x * kGenBlock;
+  for (uint64_t g = (uint64_t)blockIdx.x * kGenBlock + threadIdx.x; g < groups; g += stride) {
+    const uint64_t e0 = g * 8;
+    uint32_t v[8];
+    if (e0 + 8 <= nnz) {
+      const int4 x = reinterpret_cast<const int4 *>(col)[2 * g];
+      const int4 y = reinterpret_cast<const int4 *>(col)[2 * g + 1];
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+      v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = e0 + k < nnz ? (uint32_t)col[e0 + k] : 0u;
+    }
+    int4 out;
+    out.x = (int)((v[0] & 0xFFFFu) | (v[1] << 16));
+    out.y = (int)((v[2] & 0xFFFFu) | (v[3] << 16));
+    out.z = (int)((v[4] & 0xFFFFu) | (v[5] << 16));
+    out.w = (int)((v[6] & 0xFFFFu) | (v[7] << 16));
+    reinterpret_cast<int4 *>(col16)[g] = out;
   }
 }
 
@@ -379,6 +413,16 @@ hipError_t launch_fill_rows(const GenArgs &g, uint32_t max_fixed_k, const uint64
   return hipGetLastError();
 }
 
+hipError_t launch_narrow_targets(const int32_t *col, uint64_t nnz, uint64_t count, uint16_t *col16,
+                                 hipStream_t s) {
+  if (count % 8 != 0 || count < nnz) return hipErrorInvalidValue;
+  const uint64_t groups = count / 8;
+  const uint64_t want = (groups + kGenBlock - 1) / kGenBlock;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 8192));
+  k_narrow_targets<<<grid, kGenBlock, 0, s>>>(col, nnz, groups, col16);
+  return hipGetLastError();
+}
+
 size_t scan_scratch_elems(uint32_t n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
 
 hipError_t launch_scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint32_t n,
@@ -411,9 +455,9 @@ hipError_t launch_fill_in_edges(const uint64_t *row_ptr, const int32_t *col,
 }
 
 hipError_t launch_tile_offsets(const uint64_t *row_ptr, const int32_t *col, uint32_t n,
-                               uint32_t tiles, uint32_t tile_size, uint32_t *tile_off,
+                               uint32_t tiles, uint32_t tile_size, void *tile_off, bool off16,
                                hipStream_t s) {
-  k_tile_offsets<<<row_grid(n), kGenBlock, 0, s>>>(row_ptr, col, n, tiles, tile_size, tile_off);
+  k_tile_offsets<<<row_grid(n), kGenBlock, 0, s>>>(row_ptr, col, n, tiles, tile_size, tile_off, off16);
   return hipGetLastError();
 }
 

@@ -326,19 +326,22 @@ void choose_delivery(snn_network *net) {
     net->block = b ? b : 1024;
     // A workgroup accumulates a range of up to kTileGroupMax base tiles in LDS.  The
     // largest base tile is set by the workgroup LDS limit (160 KB on gfx950, less the
-    // kernel's static arrays); the default base tile is kDefaultTile targets (the fastest
-    // of the launch-shape sweep on the 1e9-synapse network, with 1,024-thread workgroups
-    // and one per CU).
+    // kernel's static arrays); the default base tile is kDefaultTile targets, so that a
+    // range holds up to 18,432 targets (the fastest range size of the launch-shape sweep
+    // on the 1e9-synapse network, with 1,024-thread workgroups and one per CU).
     size_t lds_dyn = 0;
     check(snn::prepare_deliver_tiled(net->block, &lds_dyn), "tiled delivery LDS limit");
     const uint32_t tile_cap = (uint32_t)(lds_dyn / 4 / snn::kTileGroupMax);
-    constexpr uint32_t kDefaultTile = 4608;
+    constexpr uint32_t kDefaultTile = 2304;
     const uint32_t min_tiles = (net->n + tile_cap - 1) / tile_cap;
     uint32_t tiles = net->prm.tiles ? net->prm.tiles : (net->n + kDefaultTile - 1) / kDefaultTile;
     tiles = std::max(std::min(tiles, std::max(1u, net->n / 16u)), min_tiles);
     net->tile_size = (net->n + tiles - 1) / tiles;
     net->tiles = (net->n + net->tile_size - 1) / net->tile_size;
     if (net->tile_size > tile_cap) fail(SNN_E_INVALID, "tile too large for LDS");
+    // the delivery reads 16-bit targets, which identify a target only inside a range of
+    // fewer than 65,536 targets
+    if ((uint64_t)net->tile_size * snn::kTileGroupMax > 65536) fail(SNN_E_INVALID, "tile range exceeds 65,536 targets");
     // one 1,024-thread workgroup per CU (the kernel's registers allow one resident)
     net->grid = net->prm.grid ? net->prm.grid : net->cu_count * (net->block == 1024 ? 1u : 2u);
   } else if (net->delivery == SNN_DELIVERY_ATOMIC) {
@@ -356,6 +359,23 @@ hipEvent_t new_event() {
   // marker between two launches costs as little as possible
   check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
   return e;
+}
+
+// Indexes of the tiled delivery: the tile boundaries of every row (uint16 when no row can
+// reach 65,536 synapses, else uint32) and the 16-bit copy of the targets it streams.
+void alloc_tile_offsets(snn_network *net) {
+  if (!net->col16) {
+    const uint64_t count = ((net->nnz + 7) & ~7ull) + 8;
+    net->col16 = dev_array<uint16_t>(net, count);
+    check(snn::launch_narrow_targets(net->col, net->nnz, count, net->col16, net->stream), "16-bit targets");
+  }
+  net->tile_off16 = net->row_len_bound < 65536;
+  const size_t entries = (size_t)net->n * (net->tiles + 1);
+  if (net->tile_off16) net->tile_off = dev_array<uint16_t>(net, entries);
+  else net->tile_off = dev_array<uint32_t>(net, entries);
+  check(snn::launch_tile_offsets(net->row_ptr, net->col, net->n, net->tiles, net->tile_size, net->tile_off,
+                                 net->tile_off16, net->stream),
+        "tile offsets");
 }
 
 void build(snn_network *net) {
@@ -391,6 +411,15 @@ void build(snn_network *net) {
     }
   }
   pop_proj[n_pops] = (uint32_t)gp.size();
+  // longest possible row: a source's fixed out-degrees plus the sizes of the target
+  // ranges of its ER projections
+  net->row_len_bound = 0;
+  for (uint32_t a = 0; a < n_pops; ++a) {
+    uint64_t b = 0;
+    for (uint32_t q = pop_proj[a]; q < pop_proj[a + 1]; ++q)
+      b += gp[q].kind == SNN_PROJ_FIXED_OUT ? gp[q].k : gp[q].size;
+    net->row_len_bound = std::max(net->row_len_bound, b);
+  }
 
   snn::GenProj *d_proj = dev_array<snn::GenProj>(net, std::max<size_t>(gp.size(), 1));
   uint32_t *d_pop_off = dev_array<uint32_t>(net, n_pops + 1);
@@ -484,11 +513,7 @@ void build(snn_network *net) {
   }
 
   choose_delivery(net);
-  if (net->delivery == SNN_DELIVERY_TILED) {
-    net->tile_off = dev_array<uint32_t>(net, (size_t)n * (net->tiles + 1));
-    check(snn::launch_tile_offsets(net->row_ptr, net->col, n, net->tiles, net->tile_size, net->tile_off, s),
-          "tile offsets");
-  }
+  if (net->delivery == SNN_DELIVERY_TILED) alloc_tile_offsets(net);
   check(hipEventRecord(ev[5], s), "hipEventRecord");
 
   // neuron state, FIFO, raster, control block
@@ -596,6 +621,7 @@ snn::DeliverArgs deliver_args(snn_network *net) {
   a.w_src = net->w_src;
   a.q = queue_ref(net);
   a.input = net->input;
+  a.col16 = net->col16;
   a.tile_off = net->tile_off;
   a.ctl = net->ctl;
   a.n = net->n;
@@ -605,6 +631,7 @@ snn::DeliverArgs deliver_args(snn_network *net) {
   a.window_max = net->window;
   a.tiles = net->tiles;
   a.tile_size = net->tile_size;
+  a.off16 = net->tile_off16 ? 1u : 0u;
   a.advance = 1;
   return a;
 }
@@ -808,10 +835,7 @@ void dev_free(snn_network *net, void *p) {
 
 void build_tile_offsets(snn_network *net) {
   if (net->delivery != SNN_DELIVERY_TILED) return;
-  net->tile_off = dev_array<uint32_t>(net, (size_t)net->n * (net->tiles + 1));
-  check(snn::launch_tile_offsets(net->row_ptr, net->col, net->n, net->tiles, net->tile_size, net->tile_off,
-                                 net->stream),
-        "tile offsets");
+  alloc_tile_offsets(net);
   check(hipStreamSynchronize(net->stream), "sync after tile offsets");
 }
 
@@ -831,6 +855,10 @@ void set_delivery(snn_network *net, uint32_t delivery, uint32_t tiles, uint32_t 
   if (net->tile_off) {
     dev_free(net, net->tile_off);
     net->tile_off = nullptr;
+  }
+  if (net->col16 && net->delivery != SNN_DELIVERY_TILED) {
+    dev_free(net, net->col16);
+    net->col16 = nullptr;
   }
   build_tile_offsets(net);
   if (net->graph) {
@@ -945,7 +973,7 @@ snn_delivery_tuning autotune_delivery(snn_network *net, uint32_t reps) {
   std::vector<Cand> cands;
   cands.push_back({SNN_DELIVERY_ATOMIC, 0, 0, 0});
   if (!net->plastic && net->n >= 1024) {
-    for (uint32_t tile : {3072u, 4608u, 6144u})
+    for (uint32_t tile : {1536u, 2304u, 3072u})
       for (uint32_t block : {512u, 1024u})
         for (uint32_t grid : {net->cu_count, 2 * net->cu_count, 3 * net->cu_count})
           cands.push_back({SNN_DELIVERY_TILED, std::max(1u, (net->n + tile - 1) / tile), block, grid});
@@ -1479,6 +1507,8 @@ snn_status snn_get_info(snn_network *net, snn_info *info) {
     r.gen_rows_ms = net->gen_rows_ms;
     r.gen_fill_ms = net->gen_fill_ms;
     r.index_ms = net->index_ms;
+    r.tile_offset_bytes = net->tile_off ? (net->tile_off16 ? 2u : 4u) : 0u;
+    r.target_bytes = net->delivery == SNN_DELIVERY_TILED ? 2u : 4u;
     if (c.t != net->t_host) fail(SNN_E_STATE, "device step counter disagrees with the host");
     *info = r;
   });

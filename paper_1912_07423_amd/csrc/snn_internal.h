@@ -97,10 +97,14 @@ struct DeliverArgs {
                           // Q16 weight of every synapse of source i (no w_q16)
   QueueRef q;
   int32_t *input;
-  const uint32_t *tile_off;  // [n][tiles + 1] relative tile boundaries of each row
+  const uint16_t *col16;  // tiled delivery: low 16 bits of every target, [nnz] padded to
+                          // whole 16-byte groups
+  const void *tile_off;   // [n][tiles + 1] tile boundaries of each row, relative to the
+                          // row's start: uint16 when off16, else uint32
   Ctl *ctl;
   uint32_t n, slots, n_inbuf, delay, window_max;
   uint32_t tiles, tile_size;
+  uint32_t off16;
   uint32_t advance;       // this launch closes the window: advance the step counter
 };
 
@@ -183,7 +187,7 @@ hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t 
                                  hipStream_t s);
 hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t block,
                                 uint32_t grid, hipStream_t s);
-constexpr uint32_t kTileGroupMax = 4;  // base tiles one tiled-delivery workgroup may own
+constexpr uint32_t kTileGroupMax = 8;  // base tiles one tiled-delivery workgroup may own
 hipError_t prepare_deliver_tiled(uint32_t block, size_t *max_dynamic_lds);
 hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_row_lengths(const GenArgs &g, uint32_t *len, uint32_t *plast_rel,
@@ -201,8 +205,10 @@ hipError_t launch_fill_in_edges(const uint64_t *row_ptr, const int32_t *col,
                                 uint32_t n, uint64_t *cursor, int32_t *in_src,
                                 uint32_t *in_edge, hipStream_t s);
 hipError_t launch_tile_offsets(const uint64_t *row_ptr, const int32_t *col, uint32_t n,
-                               uint32_t tiles, uint32_t tile_size, uint32_t *tile_off,
+                               uint32_t tiles, uint32_t tile_size, void *tile_off, bool off16,
                                hipStream_t s);
+hipError_t launch_narrow_targets(const int32_t *col, uint64_t nnz, uint64_t count, uint16_t *col16,
+                                 hipStream_t s);
 hipError_t launch_init_neurons(float *v, int32_t *ref, uint32_t n, uint32_t key0, uint32_t key1,
                                float lo, float span, hipStream_t s);
 
@@ -244,7 +250,10 @@ struct snn_network {
   uint64_t *in_ptr = nullptr;
   int32_t *in_src = nullptr;
   uint32_t *in_edge = nullptr;
-  uint32_t *tile_off = nullptr;
+  void *tile_off = nullptr;
+  uint16_t *col16 = nullptr;   // low 16 bits of every target (tiled delivery)
+  bool tile_off16 = false;    // tile boundaries stored as uint16 (every row < 65,536 synapses)
+  uint64_t row_len_bound = 0; // upper bound on a row's length, from the projections
   float *v = nullptr, *x_pre = nullptr, *x_post = nullptr;
   int32_t *ref = nullptr, *input = nullptr, *queue = nullptr;
   uint32_t *qlen = nullptr;

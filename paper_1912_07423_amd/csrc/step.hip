@@ -10,8 +10,9 @@
 //                    input accumulators in global memory.
 //  k_deliver_tiled   Receive Spikes, one workgroup per (target tile, emission step):
 //                    the workgroup reads the tile's slice of every dequeued spike's
-//                    sorted row, accumulates in LDS with int32 atomics and writes the
-//                    tile's input accumulators with plain stores.
+//                    sorted row from the 16-bit copy of the targets, accumulates in
+//                    LDS with int32 atomics and writes the tile's input accumulators
+//                    with plain stores.
 //  k_stdp_ltd/ltp    Update Synapses: depression over S_{t-d}'s plastic out-edges,
 //                    potentiation over S_t's plastic in-edges (transposed index).
 //
@@ -333,91 +334,125 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
   }
 }
 
-constexpr int kTiledGroups = 4;  // 16-byte groups per lane per batch (16 synapses)
+// 16-byte groups per lane per batch: 4 groups of 8 targets (and, with weights stored per
+// synapse, 2 groups and their 32 bytes of weights, to bound the registers in flight).
+template <bool kSrcW>
+constexpr int tiled_groups() { return kSrcW ? 4 : 2; }
 
-// Sub-rows are streamed as 16-byte aligned groups of 4 synapses (one int4 load of
-// targets, and of weights when they are stored per synapse); the elements of a group
-// outside its sub-row are masked off.  Loads kU groups of the flattened group range,
-// 64 apart, from this lane's group `first`; `o` is the lane's current sub-row
-// (monotone).  With source weights (kSrcW) the weight is the sub-row's, held in LDS.
+// One 16-byte group of the tiled delivery's target stream: 8 consecutive 16-bit
+// targets of the flattened sub-rows, the weights of those 8 synapses (w0: 0-3, w1: 4-7;
+// with source weights w0.x is the sub-row's weight), and the mask of the elements that
+// lie inside the sub-row.
+struct TiledGroup {
+  int4 c, w0, w1;
+  uint32_t mask;
+};
+
+// Sub-rows are streamed as 16-byte aligned groups of 8 synapses of the 16-bit target
+// array; the elements of a group outside its sub-row are masked off.  Loads kU groups of
+// the flattened group range, 64 apart, from this lane's group `first`; `o` is the lane's
+// current sub-row (monotone).
 template <int kU, bool kSrcW>
 __device__ __forceinline__ void tiled_load(const DeliverArgs &a, const uint64_t *s_lo,
                                            const uint32_t *s_len, const uint32_t *s_pre,
                                            const int32_t *s_w, uint32_t first, uint32_t end,
-                                           uint32_t &o, int4 (&cv)[kU], int4 (&wv)[kU],
-                                           uint32_t (&mask)[kU]) {
+                                           uint32_t &o, TiledGroup (&gr)[kU]) {
 #pragma unroll
   for (int u = 0; u < kU; ++u) {
     const uint32_t idx = first + u * kWave;
-    mask[u] = 0;
+    gr[u].mask = 0;
+    gr[u].w0 = make_int4(0, 0, 0, 0);
+    gr[u].w1 = make_int4(0, 0, 0, 0);
     if (idx < end) {
       while (s_pre[o + 1] <= idx) ++o;
       const uint64_t lo = s_lo[o], hi = lo + s_len[o];
-      const uint64_t g = (lo >> 2) + (idx - s_pre[o]);
-      cv[u] = reinterpret_cast<const int4 *>(a.col)[g];
+      const uint64_t g = (lo >> 3) + (idx - s_pre[o]);
+      gr[u].c = reinterpret_cast<const int4 *>(a.col16)[g];
       if constexpr (kSrcW) {
-        const int32_t x = s_w[o];
-        wv[u] = make_int4(x, x, x, x);
+        gr[u].w0.x = s_w[o];
       } else {
-        wv[u] = reinterpret_cast<const int4 *>(a.w_q16)[g];
+        gr[u].w0 = reinterpret_cast<const int4 *>(a.w_q16)[2 * g];
+        gr[u].w1 = reinterpret_cast<const int4 *>(a.w_q16)[2 * g + 1];
       }
-      const uint64_t e0 = g << 2;
+      const uint64_t e0 = g << 3;
       const uint32_t first_q = lo > e0 ? (uint32_t)(lo - e0) : 0u;
-      const uint32_t last_q = hi - e0 < 4 ? (uint32_t)(hi - e0) : 4u;
-      mask[u] = ((1u << last_q) - 1u) & ~((1u << first_q) - 1u);
+      const uint32_t last_q = hi - e0 < 8 ? (uint32_t)(hi - e0) : 8u;
+      gr[u].mask = ((1u << last_q) - 1u) & ~((1u << first_q) - 1u);
     }
   }
 }
 
-constexpr uint32_t kMaxTileGroup = 4;  // base tiles a workgroup may own
+// Adds the masked elements of one group into the range's LDS accumulators.  A range
+// spans fewer than 65,536 targets, so a target t of the range is recovered from its low
+// 16 bits: t - range_lo = (t16 - range_lo) mod 2^16.
+template <bool kSrcW>
+__device__ __forceinline__ void tiled_accumulate(int32_t *acc, const TiledGroup &g, uint32_t range_lo) {
+  const uint32_t words[4] = {(uint32_t)g.c.x, (uint32_t)g.c.y, (uint32_t)g.c.z, (uint32_t)g.c.w};
+  const int32_t w[8] = {g.w0.x, g.w0.y, g.w0.z, g.w0.w, g.w1.x, g.w1.y, g.w1.z, g.w1.w};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (g.mask & (1u << k)) {
+      const uint32_t t16 = (k & 1) ? words[k >> 1] >> 16 : words[k >> 1];
+      atomicAdd(&acc[(t16 - range_lo) & 0xFFFFu], kSrcW ? w[0] : w[k]);
+    }
+  }
+}
 
 // Balanced schedule of one window, derived by every workgroup from the step counts
 // c_w: step w is cut into ceil(P / m_w) target ranges of m_w consecutive base tiles,
-// one workgroup each, with m_w in [1, kMaxTileGroup].  The work of a range is about
+// one workgroup each, with m_w in [1, kTileGroupMax].  The work of a range is about
 // c_w * m_w sub-rows; the schedule takes the smallest bound X on it for which the
-// ranges fit the grid, m_w = clamp(X / c_w, 1, kMaxTileGroup).  The candidate bounds
-// are the products c_w * m (one lane each), so a wave finds X in one pass.
+// ranges fit the grid, m_w = clamp(X / c_w, 1, kTileGroupMax).  The candidate bounds
+// are the products c_w * m, one per lane and pass.
 struct TileSchedule {
   uint32_t m[kWave];          // base tiles per range, per step
   uint32_t first[kWave + 1];  // first workgroup of each step
 };
 
-// Base tiles per range of a step with count c under the work bound x (division-free:
-// m = clamp(floor(x / c), 1, kMaxTileGroup)).
-__device__ __forceinline__ uint32_t group_for(uint32_t x, uint32_t c) {
-  if (c == 0) return kMaxTileGroup;
-  uint32_t m = 1;
-#pragma unroll
-  for (uint32_t k = 2; k <= kMaxTileGroup; ++k) m += (uint64_t)x >= (uint64_t)c * k ? 1u : 0u;
-  return m;
+// Scaled reciprocal of a step count, for group_for (0 for an empty step).  The factor
+// 1 + 2^-40 keeps an exact quotient x / c = m from rounding down to m - 1: for c < 2^32
+// and quotients below kTileGroupMax + 1 the product's floor is then the exact one.
+__device__ __forceinline__ double schedule_inv(uint32_t c) {
+  return c ? (1.0 + 0x1p-40) / (double)c : 0.0;
 }
 
-__device__ void make_schedule(const uint32_t *cnt, uint32_t steps, uint32_t tiles, uint32_t grid,
-                              TileSchedule &sch) {
+// Base tiles per range of a step under the work bound x: clamp(floor(x / c), 1,
+// kTileGroupMax), with inv = schedule_inv(c); an empty step takes maximal ranges.
+// Every workgroup evaluates the same operations on the same counts, so all derive one
+// schedule; any m in [1, kTileGroupMax] still covers every tile.
+__device__ __forceinline__ uint32_t group_for(uint64_t x, double inv) {
+  if (inv == 0.0) return kTileGroupMax;
+  const double q = fmin(fmax((double)x * inv, 1.0), (double)kTileGroupMax);
+  return (uint32_t)q;
+}
+
+// s_inv[w] = schedule_inv(c_w); s_rng[m] = ceil(P / m) for m in [1, kTileGroupMax].
+__device__ void make_schedule(const uint32_t *cnt, const double *s_inv, const uint32_t *s_rng,
+                              uint32_t steps, uint32_t grid, TileSchedule &sch) {
   const uint32_t lane = lane_id();
-  uint32_t ranges[kMaxTileGroup + 1];
-#pragma unroll
-  for (uint32_t m = 1; m <= kMaxTileGroup; ++m) ranges[m] = (tiles + m - 1) / m;
-  // candidate bound from lane = (step, m) pairs; other lanes propose "all ranges maximal"
-  const uint32_t w_c = lane / kMaxTileGroup, m_c = lane % kMaxTileGroup + 1;
-  uint32_t x = 0xFFFFFFFFu;
-  if (w_c < steps) x = cnt[w_c] * m_c;
-  uint32_t need = 0;
-  for (uint32_t w = 0; w < steps; ++w) {
-    const uint32_t g = x == 0xFFFFFFFFu ? kMaxTileGroup : group_for(x, cnt[w]);
-#pragma unroll
-    for (uint32_t m = 1; m <= kMaxTileGroup; ++m) need += g == m ? ranges[m] : 0u;
+  uint64_t best = ~0ull;  // ~0: every step takes maximal ranges
+  const uint32_t cands = steps * kTileGroupMax;
+  for (uint32_t c0 = 0; c0 < cands; c0 += kWave) {
+    const uint32_t id = c0 + lane;
+    const bool live = id < cands;
+    const uint32_t w_c = live ? id / kTileGroupMax : 0u, m_c = id % kTileGroupMax + 1;
+    const uint64_t x = (uint64_t)cnt[w_c] * m_c;
+    uint32_t need = 0;
+    for (uint32_t w = 0; w < steps; ++w) need += s_rng[group_for(x, s_inv[w])];
+    if (live && need <= grid && x < best) best = x;
   }
-  uint32_t best = need <= grid ? x : 0xFFFFFFFFu;
 #pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) best = min(best, (uint32_t)__shfl_xor(best, d, kWave));
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    const uint64_t o = ((uint64_t)(uint32_t)__shfl_xor((int)(best >> 32), d, kWave) << 32) |
+                       (uint32_t)__shfl_xor((int)(uint32_t)best, d, kWave);
+    best = o < best ? o : best;
+  }
   // lane w: the tiles per range and the range count of step w; their prefix over the
   // steps gives each step's first workgroup
   uint32_t g = 0, r = 0;
   if (lane < steps) {
-    g = best == 0xFFFFFFFFu ? kMaxTileGroup : group_for(best, cnt[lane]);
-#pragma unroll
-    for (uint32_t m = 1; m <= kMaxTileGroup; ++m) r += g == m ? ranges[m] : 0u;
+    g = best == ~0ull ? kTileGroupMax : group_for(best, s_inv[lane]);
+    r = s_rng[g];
   }
   const uint32_t incl = wave_inclusive_scan(r);
   sch.m[lane] = g;
@@ -444,13 +479,13 @@ __device__ __forceinline__ uint32_t xcd_unit(uint32_t b, uint32_t grid, uint32_t
 // range's input accumulators.  Spikes are processed in chunks of kBlock: every thread
 // fetches one spike's sub-row bounds (the edges of the spike's sorted row that fall in
 // the range), a block scan lays the sub-rows end to end, and each wave streams a
-// contiguous share of the flattened edge range, 64 x kTiledUnroll elements at a time,
-// with the next batch's loads issued before the current batch's LDS atomics.
+// contiguous share of the flattened 16-byte groups, 64 x tiled_groups() at a time, with
+// the next batch's loads issued before the current batch's LDS atomics.
 template <int kBlock, bool kSrcW>
 __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_t steps) {
   extern __shared__ int32_t acc[];
   constexpr int kWaves = kBlock / kWave;
-  constexpr int kU = kTiledGroups;
+  constexpr int kU = tiled_groups<kSrcW>();
   __shared__ uint64_t s_lo[kBlock];
   __shared__ uint32_t s_len[kBlock];
   __shared__ uint32_t s_pre[kBlock + 1];
@@ -460,6 +495,8 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
   __shared__ uint32_t s_cnt[kWave];
   __shared__ uint32_t s_qpre[kWave][kQueueGroups + 1];
   __shared__ uint32_t s_slot[kWave];
+  __shared__ double s_inv[kWave];
+  __shared__ uint32_t s_rng[kTileGroupMax + 1];
   __shared__ TileSchedule sch;
   const uint64_t t0 = a.ctl->t_deliver;
   close_window(a, t0, steps);
@@ -479,10 +516,12 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
 #pragma unroll
     for (uint32_t g = 0; g <= kQueueGroups; ++g) s_qpre[lane][g] = qp[g];
     s_cnt[lane] = qp[kQueueGroups];
+    s_inv[lane] = schedule_inv(qp[kQueueGroups]);
+    if (lane >= 1 && lane <= kTileGroupMax) s_rng[lane] = (a.tiles + lane - 1) / lane;
   }
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < kMaxTileGroup * a.tile_size; j += kBlock) acc[j] = 0;
-  if (wave == 0) make_schedule(s_cnt, steps, a.tiles, gridDim.x, sch);
+  for (uint32_t j = threadIdx.x; j < kTileGroupMax * a.tile_size; j += kBlock) acc[j] = 0;
+  if (wave == 0) make_schedule(s_cnt, s_inv, s_rng, steps, gridDim.x, sch);
   __syncthreads();
   const uint32_t unit = xcd_unit(blockIdx.x, gridDim.x, sch.first[steps]);
   if (unit >= sch.first[steps]) return;  // more workgroups than ranges this window
@@ -511,11 +550,20 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
     if (threadIdx.x < mm) {
       const int32_t src = queue_entry(a.q, slot, qpre, c0 + threadIdx.x);
       if ((uint32_t)src < a.n) {
-        const uint32_t *to = a.tile_off + (size_t)src * (a.tiles + 1);
-        const uint32_t o0 = to[tile_a], o1 = to[tile_b];
+        const size_t row = (size_t)src * (a.tiles + 1);
+        uint32_t o0, o1;
+        if (a.off16) {
+          const uint16_t *to = static_cast<const uint16_t *>(a.tile_off) + row;
+          o0 = to[tile_a];
+          o1 = to[tile_b];
+        } else {
+          const uint32_t *to = static_cast<const uint32_t *>(a.tile_off) + row;
+          o0 = to[tile_a];
+          o1 = to[tile_b];
+        }
         lo = a.row_ptr[src] + o0;
         len = o1 - o0;
-        groups = len ? (uint32_t)(((lo + len + 3) >> 2) - (lo >> 2)) : 0u;
+        groups = len ? (uint32_t)(((lo + len + 7) >> 3) - (lo >> 3)) : 0u;
         if (kSrcW) ws = a.w_src[src];
       }
     }
@@ -551,25 +599,17 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
         else hi_j = mid;
       }
       uint32_t o = lo_j;
-      int4 cv[kU], wv[kU], cn[kU], wn[kU];
-      uint32_t mk[kU], mn[kU] = {};
-      tiled_load<kU, kSrcW>(a, s_lo, s_len, s_pre, s_w, beg + lane, end, o, cv, wv, mk);
+      TiledGroup cur[kU], nxt[kU];
+      tiled_load<kU, kSrcW>(a, s_lo, s_len, s_pre, s_w, beg + lane, end, o, cur);
       for (uint32_t b0 = beg; b0 < end; b0 += kWave * kU) {
         const uint32_t nb = b0 + kWave * kU;
-        if (nb < end) tiled_load<kU, kSrcW>(a, s_lo, s_len, s_pre, s_w, nb + lane, end, o, cn, wn, mn);
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          if (mk[u] & 1u) atomicAdd(&acc[cv[u].x - (int32_t)tile_lo], wv[u].x);
-          if (mk[u] & 2u) atomicAdd(&acc[cv[u].y - (int32_t)tile_lo], wv[u].y);
-          if (mk[u] & 4u) atomicAdd(&acc[cv[u].z - (int32_t)tile_lo], wv[u].z);
-          if (mk[u] & 8u) atomicAdd(&acc[cv[u].w - (int32_t)tile_lo], wv[u].w);
-        }
+        for (int u = 0; u < kU; ++u) nxt[u].mask = 0;
+        if (nb < end) tiled_load<kU, kSrcW>(a, s_lo, s_len, s_pre, s_w, nb + lane, end, o, nxt);
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          cv[u] = cn[u];
-          wv[u] = wn[u];
-          mk[u] = mn[u];
-        }
+        for (int u = 0; u < kU; ++u) tiled_accumulate<kSrcW>(acc, cur[u], tile_lo);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
       }
     }
     __syncthreads();
@@ -706,9 +746,9 @@ hipError_t prepare_deliver_tiled(uint32_t block, size_t *max_dynamic_lds) {
 hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t block,
                                 uint32_t grid, hipStream_t s) {
   // the schedule always fits when every step uses maximal ranges
-  const uint32_t floor_grid = steps * ((a.tiles + kMaxTileGroup - 1) / kMaxTileGroup);
+  const uint32_t floor_grid = steps * ((a.tiles + kTileGroupMax - 1) / kTileGroupMax);
   if (grid < floor_grid) grid = floor_grid;
-  const size_t lds = (size_t)kMaxTileGroup * a.tile_size * sizeof(int32_t);
+  const size_t lds = (size_t)kTileGroupMax * a.tile_size * sizeof(int32_t);
   const bool src_w = a.w_src != nullptr;
   switch (block) {
     case 256:

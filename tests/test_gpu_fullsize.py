@@ -4,7 +4,7 @@ times: the whole HIP path against the oracle's complete run of the same network.
   * 4,000-neuron CUBA network (ER p = 0.02, no delays): all 10,000 steps.
   * 200,000-neuron Brunel network (fixed out-degree 5,000, 1e9 synapses, 15-step
     delay, Poisson drive): the benchmark's whole run, 300 warm-up + 1,000 timed steps,
-    with the tiled delivery, 44 base tiles, one weight per source, and the device-side
+    with the tiled delivery, 87 base tiles (2-byte boundaries), one weight per source, and the device-side
     schedule, exactly as benchmarked.
   * 100,000-neuron plastic network (ER p = 0.02, 2e8 synapses, STDP on E->E, 10-step
     delay): all 2,000 steps, final FP32 weights of every synapse compared bit for bit.
@@ -44,7 +44,8 @@ def test_brunel_200k_1e9_synapses():
     print(f"[full] brunel_fixed_out n=200000 k=5000: {steps} steps", flush=True)
     rg, inf = compare_run(spec, steps, raster_steps=4096)
     assert inf["nnz"] == 200_000 * 5000
-    assert inf["delivery"] == 2 and inf["tiles"] == 44 and inf["window"] == 15 and inf["source_weights"] == 1
+    assert inf["delivery"] == 2 and inf["tiles"] == 87 and inf["window"] == 15 and inf["source_weights"] == 1
+    assert inf["tile_offset_bytes"] == 2
     print(f"[full] brunel: {int(np.unpackbits(rg.view(np.uint8)).sum())} spikes, "
           f"{inf['events']} events", flush=True)
     assert inf["events"] > 0

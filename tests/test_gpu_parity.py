@@ -99,7 +99,18 @@ def test_tiled_tile_counts():
     spec = W.brunel_fixed_out(n=2500, k=250, delay_steps=15, steps=120)
     for tiles in (1, 3, 17, 39, 120):
         print(f"[tiles] {tiles}", flush=True)
-        _compare_run(spec, 120, delivery="tiled", tiles=tiles)
+        _, inf = _compare_run(spec, 120, delivery="tiled", tiles=tiles)
+        assert inf["tile_offset_bytes"] == 2
+
+
+def test_tiled_wide_tile_offsets():
+    """A 66,000-neuron population as an ER target: a row may then reach 65,536
+    synapses, so the tile boundaries are stored as 4-byte offsets."""
+    spec = W.cuba_lif_4k(n_exc=66_000, n_inh=4_000, p=0.001, steps=100)
+    print("[tiles] 4-byte boundaries, n=70000", flush=True)
+    rg, inf = _compare_run(spec, 100, delivery="tiled", tiles=40)
+    assert inf["tile_offset_bytes"] == 4 and inf["tiles"] == 40
+    assert rg.any()
 
 
 def test_step_by_step_equals_graph_run():
