@@ -305,65 +305,69 @@ __global__ __launch_bounds__(kGenBlock) void k_fill_in(const uint64_t *row_ptr, 
   }
 }
 
-// ---- boundaries of the target tiles inside every (sorted) row ----
-// Entry p of row i is the offset, from the row's start, of the row's first target
-// >= p * tile_size (entry `tiles` is the row length).  Stored as uint16 when every row is
-// shorter than 65,536 synapses, which halves the bytes a delivery workgroup reads per
-// spike for a given number of tiles.
-__global__ __launch_bounds__(kGenBlock) void k_tile_offsets(const uint64_t *row_ptr,
-                                                            const int32_t *col, uint32_t n,
-                                                            uint32_t tiles, uint32_t tile_size,
-                                                            void *tile_off, bool off16) {
-  const uint32_t wave = blockIdx.x * kGenWavesPerBlock + threadIdx.x / kWave;
-  const uint32_t n_waves = gridDim.x * kGenWavesPerBlock;
-  for (uint32_t i = wave; i < n; i += n_waves) {
-    const uint64_t lo = row_ptr[i], hi = row_ptr[i + 1];
-    for (uint32_t p = lane_id(); p <= tiles; p += kWave) {
-      uint64_t rel;
-      if (p == tiles) {
-        rel = hi - lo;
-      } else {
-        const int64_t bound = (int64_t)p * tile_size;
-        uint64_t a = lo, b = hi;  // first e in [lo, hi) with col[e] >= bound
-        while (a < b) {
-          const uint64_t m = (a + b) >> 1;
-          if ((int64_t)col[m] < bound) a = m + 1;
-          else b = m;
-        }
-        rel = a - lo;
-      }
-      const uint64_t at = (uint64_t)i * (tiles + 1) + p;
-      if (off16) static_cast<uint16_t *>(tile_off)[at] = (uint16_t)rel;
-      else static_cast<uint32_t *>(tile_off)[at] = (uint32_t)rel;
-    }
-  }
+// ---- indexes of the tiled delivery: tile boundaries and 16-bit targets ----
+// Tile of target t, floor(t / tile_size): a binary32 estimate from the reciprocal, off by
+// at most one for quotients below 2^22, then corrected exactly in integers.
+__device__ __forceinline__ uint32_t tile_of(uint32_t t, uint32_t tile_size, float inv) {
+  uint32_t q = (uint32_t)((float)t * inv);
+  if ((uint64_t)q * tile_size > t) --q;
+  else if ((uint64_t)(q + 1) * tile_size <= t) ++q;
+  return q;
 }
 
-// col16[e] = col[e] mod 2^16 for e < nnz, 0 for the padding up to count: the tiled
-// delivery's 2-byte target stream (a range spans fewer than 65,536 targets, so the low
-// 16 bits identify a target inside it).  Each thread converts 8 targets (two int4 loads,
-// one int4 store).
-__global__ __launch_bounds__(kGenBlock) void k_narrow_targets(const int32_t *col, uint64_t nnz,
-                                                              uint64_t groups, uint16_t *col16) {
-  const uint64_t stride = (uint64_t)gridDim.x * kGenBlock;
-  for (uint64_t g = (uint64_t)blockIdx.x * kGenBlock + threadIdx.x; g < groups; g += stride) {
-    const uint64_t e0 = g * 8;
-    uint32_t v[8];
-    if (e0 + 8 <= nnz) {
-      const int4 x = reinterpret_cast<const int4 *>(col)[2 * g];
-      const int4 y = reinterpret_cast<const int4 *>(col)[2 * g + 1];
-      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-      v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
-    } else {
+// One wave per (sorted) row, streaming the row's targets once:
+//  * col16[e] = col[e] mod 2^16, the tiled delivery's 2-byte target stream (a range spans
+//    fewer than 65,536 targets, so the low 16 bits identify a target inside it);
+//  * entry p of the row's tile boundaries is the offset, from the row's start, of the
+//    first target >= p * tile_size (entry `tiles` is the row length).  Targets are
+//    sorted, so element e is that boundary for every p in (tile(e - 1), tile(e)]; the
+//    entries past the last element's tile get the row length.  Stored as uint16 when
+//    every row is shorter than 65,536 synapses.
+// The padding of col16 past nnz (up to `count`) is cleared by the first thread.
+constexpr int kIndexUnroll = 4;
+__global__ __launch_bounds__(kGenBlock) void k_tile_index(const uint64_t *row_ptr, const int32_t *col,
+                                                          uint32_t n, uint64_t nnz, uint64_t count,
+                                                          uint32_t tiles, uint32_t tile_size, float inv,
+                                                          uint16_t *col16, void *tile_off, bool off16) {
+  const uint32_t lane = lane_id();
+  const uint32_t wave = blockIdx.x * kGenWavesPerBlock + threadIdx.x / kWave;
+  const uint32_t n_waves = gridDim.x * kGenWavesPerBlock;
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    for (uint64_t e = nnz; e < count; ++e) col16[e] = 0;
+  auto put = [&](uint64_t at, uint32_t rel) {
+    if (off16) static_cast<uint16_t *>(tile_off)[at] = (uint16_t)rel;
+    else static_cast<uint32_t *>(tile_off)[at] = rel;
+  };
+  for (uint32_t i = wave; i < n; i += n_waves) {
+    const uint64_t lo = row_ptr[i], hi = row_ptr[i + 1];
+    const uint64_t out = (uint64_t)i * (tiles + 1);
+    int32_t carry = -1;  // tile of the element before this pass (-1 at the row's start)
+    for (uint64_t base = lo; base < hi; base += kWave * kIndexUnroll) {
+      int32_t t[kIndexUnroll];
+      bool in[kIndexUnroll];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = e0 + k < nnz ? (uint32_t)col[e0 + k] : 0u;
+      for (int j = 0; j < kIndexUnroll; ++j) {
+        const uint64_t e = base + (uint64_t)j * kWave + lane;
+        in[j] = e < hi;
+        t[j] = in[j] ? col[e] : 0;
+      }
+#pragma unroll
+      for (int j = 0; j < kIndexUnroll; ++j) {
+        const uint64_t e = base + (uint64_t)j * kWave + lane;
+        const int32_t tl = in[j] ? (int32_t)tile_of((uint32_t)t[j], tile_size, inv) : (int32_t)tiles;
+        const int32_t up = __shfl_up(tl, 1, kWave);
+        const int32_t prev = lane == 0 ? carry : up;
+        if (in[j]) {
+          col16[e] = (uint16_t)(uint32_t)t[j];
+          for (int32_t p = prev + 1; p <= tl; ++p) put(out + (uint32_t)p, (uint32_t)(e - lo));
+        }
+        carry = __shfl(tl, kWave - 1, kWave);
+      }
     }
-    int4 out;
-    out.x = (int)((v[0] & 0xFFFFu) | (v[1] << 16));
-    out.y = (int)((v[2] & 0xFFFFu) | (v[3] << 16));
-    out.z = (int)((v[4] & 0xFFFFu) | (v[5] << 16));
-    out.w = (int)((v[6] & 0xFFFFu) | (v[7] << 16));
-    reinterpret_cast<int4 *>(col16)[g] = out;
+    // entries past the last element's tile: the row length
+    int32_t last = -1;
+    if (hi > lo) last = (int32_t)tile_of((uint32_t)col[hi - 1], tile_size, inv);
+    for (uint32_t p = (uint32_t)(last + 1) + lane; p <= tiles; p += kWave) put(out + p, (uint32_t)(hi - lo));
   }
 }
 
@@ -413,13 +417,12 @@ hipError_t launch_fill_rows(const GenArgs &g, uint32_t max_fixed_k, const uint64
   return hipGetLastError();
 }
 
-hipError_t launch_narrow_targets(const int32_t *col, uint64_t nnz, uint64_t count, uint16_t *col16,
-                                 hipStream_t s) {
-  if (count % 8 != 0 || count < nnz) return hipErrorInvalidValue;
-  const uint64_t groups = count / 8;
-  const uint64_t want = (groups + kGenBlock - 1) / kGenBlock;
-  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 8192));
-  k_narrow_targets<<<grid, kGenBlock, 0, s>>>(col, nnz, groups, col16);
+hipError_t launch_tile_index(const uint64_t *row_ptr, const int32_t *col, uint32_t n, uint64_t nnz,
+                             uint64_t count, uint32_t tiles, uint32_t tile_size, uint16_t *col16,
+                             void *tile_off, bool off16, hipStream_t s) {
+  if (count < nnz || tile_size == 0 || tiles == 0 || (uint64_t)tiles * tile_size < n) return hipErrorInvalidValue;
+  k_tile_index<<<row_grid(n), kGenBlock, 0, s>>>(row_ptr, col, n, nnz, count, tiles, tile_size,
+                                                 1.0f / (float)tile_size, col16, tile_off, off16);
   return hipGetLastError();
 }
 
@@ -454,12 +457,6 @@ hipError_t launch_fill_in_edges(const uint64_t *row_ptr, const int32_t *col,
   return hipGetLastError();
 }
 
-hipError_t launch_tile_offsets(const uint64_t *row_ptr, const int32_t *col, uint32_t n,
-                               uint32_t tiles, uint32_t tile_size, void *tile_off, bool off16,
-                               hipStream_t s) {
-  k_tile_offsets<<<row_grid(n), kGenBlock, 0, s>>>(row_ptr, col, n, tiles, tile_size, tile_off, off16);
-  return hipGetLastError();
-}
 
 hipError_t launch_init_neurons(float *v, int32_t *ref, uint32_t n, uint32_t key0, uint32_t key1,
                                float lo, float span, hipStream_t s) {

@@ -364,18 +364,15 @@ hipEvent_t new_event() {
 // Indexes of the tiled delivery: the tile boundaries of every row (uint16 when no row can
 // reach 65,536 synapses, else uint32) and the 16-bit copy of the targets it streams.
 void alloc_tile_offsets(snn_network *net) {
-  if (!net->col16) {
-    const uint64_t count = ((net->nnz + 7) & ~7ull) + 8;
-    net->col16 = dev_array<uint16_t>(net, count);
-    check(snn::launch_narrow_targets(net->col, net->nnz, count, net->col16, net->stream), "16-bit targets");
-  }
+  const uint64_t count = ((net->nnz + 7) & ~7ull) + 8;  // whole 16-byte groups, one spare
+  if (!net->col16) net->col16 = dev_array<uint16_t>(net, count);
   net->tile_off16 = net->row_len_bound < 65536;
   const size_t entries = (size_t)net->n * (net->tiles + 1);
   if (net->tile_off16) net->tile_off = dev_array<uint16_t>(net, entries);
   else net->tile_off = dev_array<uint32_t>(net, entries);
-  check(snn::launch_tile_offsets(net->row_ptr, net->col, net->n, net->tiles, net->tile_size, net->tile_off,
-                                 net->tile_off16, net->stream),
-        "tile offsets");
+  check(snn::launch_tile_index(net->row_ptr, net->col, net->n, net->nnz, count, net->tiles, net->tile_size,
+                               net->col16, net->tile_off, net->tile_off16, net->stream),
+        "tile index");
 }
 
 void build(snn_network *net) {

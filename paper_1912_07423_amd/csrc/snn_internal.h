@@ -204,11 +204,9 @@ hipError_t launch_fill_in_edges(const uint64_t *row_ptr, const int32_t *col,
                                 const uint32_t *plast_rel, const uint32_t *plast_len,
                                 uint32_t n, uint64_t *cursor, int32_t *in_src,
                                 uint32_t *in_edge, hipStream_t s);
-hipError_t launch_tile_offsets(const uint64_t *row_ptr, const int32_t *col, uint32_t n,
-                               uint32_t tiles, uint32_t tile_size, void *tile_off, bool off16,
-                               hipStream_t s);
-hipError_t launch_narrow_targets(const int32_t *col, uint64_t nnz, uint64_t count, uint16_t *col16,
-                                 hipStream_t s);
+hipError_t launch_tile_index(const uint64_t *row_ptr, const int32_t *col, uint32_t n, uint64_t nnz,
+                             uint64_t count, uint32_t tiles, uint32_t tile_size, uint16_t *col16,
+                             void *tile_off, bool off16, hipStream_t s);
 hipError_t launch_init_neurons(float *v, int32_t *ref, uint32_t n, uint32_t key0, uint32_t key1,
                                float lo, float span, hipStream_t s);
 
