@@ -402,8 +402,7 @@ __device__ __forceinline__ void tiled_accumulate(int32_t *acc, const TiledGroup 
 // c_w: step w is cut into ceil(P / m_w) target ranges of m_w consecutive base tiles,
 // one workgroup each, with m_w in [1, kTileGroupMax].  The work of a range is about
 // c_w * m_w sub-rows; the schedule takes the smallest bound X on it for which the
-// ranges fit the grid, m_w = clamp(X / c_w, 1, kTileGroupMax).  The candidate bounds
-// are the products c_w * m, one per lane and pass.
+// ranges fit the grid, m_w = clamp(X / c_w, 1, kTileGroupMax).
 struct TileSchedule {
   uint32_t m[kWave];          // base tiles per range, per step
   uint32_t first[kWave + 1];  // first workgroup of each step
@@ -426,33 +425,71 @@ __device__ __forceinline__ uint32_t group_for(uint64_t x, double inv) {
   return (uint32_t)q;
 }
 
-// s_inv[w] = schedule_inv(c_w); s_rng[m] = ceil(P / m) for m in [1, kTileGroupMax].
-__device__ void make_schedule(const uint32_t *cnt, const double *s_inv, const uint32_t *s_rng,
-                              uint32_t steps, uint32_t grid, TileSchedule &sch) {
-  const uint32_t lane = lane_id();
-  uint64_t best = ~0ull;  // ~0: every step takes maximal ranges
+// ceil(P / m) for the range sizes m = 1..8, uniform (scalar registers).
+struct RangeCounts {
+  uint32_t r1, r2, r3, r4, r5, r6, r7, r8;
+};
+static_assert(kTileGroupMax == 8, "RangeCounts holds one count per range size");
+
+__device__ __forceinline__ RangeCounts range_counts(uint32_t tiles) {
+  RangeCounts r;
+  r.r1 = tiles;
+  r.r2 = (tiles + 1) / 2;
+  r.r3 = (tiles + 2) / 3;
+  r.r4 = (tiles + 3) / 4;
+  r.r5 = (tiles + 4) / 5;
+  r.r6 = (tiles + 5) / 6;
+  r.r7 = (tiles + 6) / 7;
+  r.r8 = (tiles + 7) / 8;
+  return r;
+}
+
+// The count for a per-lane m in [1, 8], by a select tree on the bits of m - 1 (VALU only:
+// no table in memory).
+__device__ __forceinline__ uint32_t ranges_of(uint32_t m, const RangeCounts &r) {
+  const uint32_t k = m - 1;
+  const bool b0 = k & 1u, b1 = k & 2u, b2 = k & 4u;
+  const uint32_t t0 = b0 ? r.r2 : r.r1, t1 = b0 ? r.r4 : r.r3;
+  const uint32_t t2 = b0 ? r.r6 : r.r5, t3 = b0 ? r.r8 : r.r7;
+  const uint32_t u0 = b1 ? t1 : t0, u1 = b1 ? t3 : t2;
+  return b2 ? u1 : u0;
+}
+
+// Smallest feasible work bound, searched by the whole workgroup.  Thread t scores the pair
+// (candidate bound x_k = c_w' * m, step w), with w = t mod S (S = steps rounded up to a
+// power of two) and one candidate per group of S lanes: the ranges of step w under x_k.
+// A sum over the S lanes gives need(x_k), the ranges all steps take; the smallest x_k with
+// need(x_k) <= grid is taken by an LDS minimum into *s_best (~0 if none: every step then
+// takes maximal ranges, which the host sizes the grid for).
+template <int kBlock>
+__device__ void schedule_bound(const uint32_t *s_cnt, uint32_t steps, uint32_t tiles, uint32_t grid,
+                               unsigned long long *s_best) {
+  uint32_t S = 1;
+  while (S < steps) S <<= 1;
+  const uint32_t w = threadIdx.x & (S - 1), slot = threadIdx.x / S, per_round = kBlock / S;
+  const RangeCounts rc = range_counts(tiles);
+  const double iw = schedule_inv(w < steps ? s_cnt[w] : 0u);
   const uint32_t cands = steps * kTileGroupMax;
-  for (uint32_t c0 = 0; c0 < cands; c0 += kWave) {
-    const uint32_t id = c0 + lane;
-    const bool live = id < cands;
-    const uint32_t w_c = live ? id / kTileGroupMax : 0u, m_c = id % kTileGroupMax + 1;
-    const uint64_t x = (uint64_t)cnt[w_c] * m_c;
-    uint32_t need = 0;
-    for (uint32_t w = 0; w < steps; ++w) need += s_rng[group_for(x, s_inv[w])];
+  uint64_t best = ~0ull;
+  for (uint32_t k0 = 0; k0 < cands; k0 += per_round) {
+    const uint32_t k = k0 + slot;
+    const bool live = k < cands;
+    const uint64_t x = live ? (uint64_t)s_cnt[k / kTileGroupMax] * (k % kTileGroupMax + 1) : 0ull;
+    uint32_t need = w < steps ? ranges_of(group_for(x, iw), rc) : 0u;
+    for (uint32_t d = S >> 1; d > 0; d >>= 1) need += (uint32_t)__shfl_xor((int)need, (int)d, (int)S);
     if (live && need <= grid && x < best) best = x;
   }
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    const uint64_t o = ((uint64_t)(uint32_t)__shfl_xor((int)(best >> 32), d, kWave) << 32) |
-                       (uint32_t)__shfl_xor((int)(uint32_t)best, d, kWave);
-    best = o < best ? o : best;
-  }
-  // lane w: the tiles per range and the range count of step w; their prefix over the
-  // steps gives each step's first workgroup
+  if (w == 0 && best != ~0ull) atomicMin(s_best, (unsigned long long)best);
+}
+
+// Wave 0: lane w takes the tiles per range and the range count of step w under the bound;
+// their prefix over the steps gives each step's first workgroup.
+__device__ void make_schedule(uint32_t c, uint64_t best, uint32_t tiles, uint32_t steps, TileSchedule &sch) {
+  const uint32_t lane = lane_id();
   uint32_t g = 0, r = 0;
   if (lane < steps) {
-    g = best == ~0ull ? kTileGroupMax : group_for(best, s_inv[lane]);
-    r = s_rng[g];
+    g = best == ~0ull ? kTileGroupMax : group_for(best, schedule_inv(c));
+    r = ranges_of(g, range_counts(tiles));
   }
   const uint32_t incl = wave_inclusive_scan(r);
   sch.m[lane] = g;
@@ -495,8 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
   __shared__ uint32_t s_cnt[kWave];
   __shared__ uint32_t s_qpre[kWave][kQueueGroups + 1];
   __shared__ uint32_t s_slot[kWave];
-  __shared__ double s_inv[kWave];
-  __shared__ uint32_t s_rng[kTileGroupMax + 1];
+  __shared__ unsigned long long s_best;
   __shared__ TileSchedule sch;
   const uint64_t t0 = a.ctl->t_deliver;
   close_window(a, t0, steps);
@@ -516,12 +552,13 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
 #pragma unroll
     for (uint32_t g = 0; g <= kQueueGroups; ++g) s_qpre[lane][g] = qp[g];
     s_cnt[lane] = qp[kQueueGroups];
-    s_inv[lane] = schedule_inv(qp[kQueueGroups]);
-    if (lane >= 1 && lane <= kTileGroupMax) s_rng[lane] = (a.tiles + lane - 1) / lane;
+    if (lane == 0) s_best = ~0ull;
   }
   __syncthreads();
   for (uint32_t j = threadIdx.x; j < kTileGroupMax * a.tile_size; j += kBlock) acc[j] = 0;
-  if (wave == 0) make_schedule(s_cnt, s_inv, s_rng, steps, gridDim.x, sch);
+  schedule_bound<kBlock>(s_cnt, steps, a.tiles, gridDim.x, &s_best);
+  __syncthreads();
+  if (wave == 0) make_schedule(lane < steps ? s_cnt[lane] : 0u, s_best, a.tiles, steps, sch);
   __syncthreads();
   const uint32_t unit = xcd_unit(blockIdx.x, gridDim.x, sch.first[steps]);
   if (unit >= sch.first[steps]) return;  // more workgroups than ranges this window

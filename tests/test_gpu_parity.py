@@ -95,6 +95,16 @@ def test_schedule_variants_identical(delivery, window):
     _compare_run(spec, 200, delivery=delivery, window=window)
 
 
+@pytest.mark.parametrize("delay", [20, 40, 64])
+def test_tiled_long_windows(delay):
+    """Windows of 17 to 64 steps (64 is the longest): the tile schedule's search then
+    scores each candidate bound over 32 or 64 lanes, one per step."""
+    spec = W.brunel_fixed_out(n=3000, k=300, delay_steps=delay, steps=400)
+    print(f"[window] tiled, d = window = {delay}", flush=True)
+    _, inf = _compare_run(spec, 400, delivery="tiled", window=delay)
+    assert inf["window"] == delay and inf["delivery"] == 2
+
+
 def test_tiled_tile_counts():
     spec = W.brunel_fixed_out(n=2500, k=250, delay_steps=15, steps=120)
     for tiles in (1, 3, 17, 39, 120):
