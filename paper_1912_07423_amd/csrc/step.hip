@@ -78,6 +78,9 @@ constexpr int kPrefetch = 16;  // steps of input in flight (4 quads)
 // equal to 2^32 cannot be reached by a 32-bit word) is found from a guide table over
 // the top 12 bits of r, which holds the count at both ends of each bucket, plus a
 // short scan when a threshold falls inside the bucket.
+// The drive and the LIF arithmetic run on every lane without branching on the neuron's
+// state: a refractory neuron discards its drive inside lif_advance, and a lane past n
+// never reports a spike or stores.
 __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t steps) {
   __shared__ __align__(16) uint32_t tbl[kTableCap];
   __shared__ __align__(16) uint16_t guide[kGuideBuckets];
@@ -145,27 +148,24 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
   uint64_t my_spikes = 0;  // bit w: this neuron spiked at step w
   for (uint32_t qq = 0; qq < n_quads; ++qq) {
     Words4 rnd{};
-    if (drive && active)
+    if (drive)
       rnd = philox(i, (uint32_t)(quad0 + qq), (uint32_t)((quad0 + qq) >> 32), kStreamPoisson, a.key0, a.key1);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int32_t w = (int32_t)(4 * qq + u) - (int32_t)off;
       if (w < 0 || w >= (int32_t)steps) continue;  // uniform
-      bool spike = false;
-      if (active) {
-        int32_t k = 0;
-        if (drive && ref <= 0) {  // a refractory neuron discards its drive
-          const uint32_t r = rnd.w[u];
-          const uint32_t gk = guide[r >> (32 - kGuideBits)];
-          k = (int32_t)(gk & 0xFFu);
-          const int32_t k_hi = (int32_t)(gk >> 8);
-          while (k < k_hi && tbl[k] <= r) ++k;
-        }
-        spike = lif_advance(v, ref, acc[u], k, lif);
-        if (a.plastic) {
-          xp = xp * a.beta_plus;
-          xq = xq * a.beta_minus;
-        }
+      int32_t k = 0;
+      if (drive) {
+        const uint32_t r = rnd.w[u];
+        const uint32_t gk = guide[r >> (32 - kGuideBits)];
+        k = (int32_t)(gk & 0xFFu);
+        const int32_t k_hi = (int32_t)(gk >> 8);
+        while (k < k_hi && tbl[k] <= r) ++k;
+      }
+      const bool spike = lif_advance(v, ref, acc[u], k, lif) && active;
+      if (a.plastic) {
+        xp = xp * a.beta_plus;
+        xq = xq * a.beta_minus;
       }
       const uint64_t mask = __ballot(spike);
       if (lane == (uint32_t)w) my_mask = mask;
@@ -204,7 +204,9 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
   }
   __syncthreads();
   for (uint32_t w = 0; w < steps; ++w) {
-    const uint64_t mask = __shfl(my_mask, w, kWave);
+    // step w's ballot from lane w (uniform w: two lane reads, no LDS round trip)
+    const uint64_t mask = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(my_mask >> 32), (int)w) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)my_mask, (int)w);
     if (!mask) continue;
     const uint32_t pos = s_base[wave][w] + lanes_below(mask);
     const uint32_t slot = ring_add(slot0, w, a.slots);
