@@ -47,3 +47,13 @@ def test_traffic_summary_scales_by_the_copy(tmp_path, monkeypatch):
     assert t["kernel_source_sha"] == bench.kernel_source_sha()
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
     assert bench.measured_traffic() == pytest.approx(t["bytes_per_launch"])
+
+
+def test_delivery_byte_model():
+    """Per event: the target the delivery reads (2 B from the tiled delivery's 16-bit copy,
+    4 B for the atomic delivery) plus a 4-byte weight when weights are stored per synapse;
+    per dequeued spike: id + row pointers, plus the source weight in the Table I layout."""
+    assert bench.delivery_bytes({"source_weights": 1, "target_bytes": 2}) == (2, 16)
+    assert bench.delivery_bytes({"source_weights": 0, "target_bytes": 2}) == (6, 12)
+    assert bench.delivery_bytes({"source_weights": 1, "target_bytes": 4}) == (4, 16)
+    assert bench.delivery_bytes({"source_weights": 0, "target_bytes": 4}) == (8, 12)
