@@ -336,10 +336,12 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
   }
 }
 
-// 16-byte groups per lane per batch: 4 groups of 8 targets (and, with weights stored per
-// synapse, 2 groups and their 32 bytes of weights, to bound the registers in flight).
+// 16-byte groups per lane per batch (8 targets each; with weights stored per synapse,
+// also their 32 bytes of weights).  A wave's share of a step is short (about 14 groups
+// per lane on the 1e9-synapse network), so two per batch, with the next two in flight,
+// beat three or four: the last, partly filled batch is shorter.
 template <bool kSrcW>
-constexpr int tiled_groups() { return kSrcW ? 4 : 2; }
+constexpr int tiled_groups() { return 2; }
 
 // One 16-byte group of the tiled delivery's target stream: 8 consecutive 16-bit
 // targets of the flattened sub-rows, the weights of those 8 synapses (w0: 0-3, w1: 4-7;
