@@ -306,10 +306,11 @@ __global__ __launch_bounds__(kGenBlock) void k_fill_in(const uint64_t *row_ptr, 
 }
 
 // ---- indexes of the tiled delivery: tile boundaries and 16-bit targets ----
-// Tile of target t, floor(t / tile_size): a binary32 estimate from the reciprocal, off by
-// at most one for quotients below 2^22, then corrected exactly in integers.
-__device__ __forceinline__ uint32_t tile_of(uint32_t t, uint32_t tile_size, float inv) {
-  uint32_t q = (uint32_t)((float)t * inv);
+// Tile of target t, floor(t / tile_size): a binary64 estimate from the reciprocal (relative
+// error ~2^-52, so within one of the quotient for any 32-bit t), corrected exactly in
+// integers.
+__device__ __forceinline__ uint32_t tile_of(uint32_t t, uint32_t tile_size, double inv) {
+  uint32_t q = (uint32_t)((double)t * inv);
   if ((uint64_t)q * tile_size > t) --q;
   else if ((uint64_t)(q + 1) * tile_size <= t) ++q;
   return q;
@@ -327,7 +328,7 @@ __device__ __forceinline__ uint32_t tile_of(uint32_t t, uint32_t tile_size, floa
 constexpr int kIndexUnroll = 4;
 __global__ __launch_bounds__(kGenBlock) void k_tile_index(const uint64_t *row_ptr, const int32_t *col,
                                                           uint32_t n, uint64_t nnz, uint64_t count,
-                                                          uint32_t tiles, uint32_t tile_size, float inv,
+                                                          uint32_t tiles, uint32_t tile_size, double inv,
                                                           uint16_t *col16, void *tile_off, bool off16) {
   const uint32_t lane = lane_id();
   const uint32_t wave = blockIdx.x * kGenWavesPerBlock + threadIdx.x / kWave;
@@ -422,7 +423,7 @@ hipError_t launch_tile_index(const uint64_t *row_ptr, const int32_t *col, uint32
                              void *tile_off, bool off16, hipStream_t s) {
   if (count < nnz || tile_size == 0 || tiles == 0 || (uint64_t)tiles * tile_size < n) return hipErrorInvalidValue;
   k_tile_index<<<row_grid(n), kGenBlock, 0, s>>>(row_ptr, col, n, nnz, count, tiles, tile_size,
-                                                 1.0f / (float)tile_size, col16, tile_off, off16);
+                                                 1.0 / (double)tile_size, col16, tile_off, off16);
   return hipGetLastError();
 }
 
