@@ -341,7 +341,7 @@ void choose_delivery(snn_network *net) {
     if (net->tile_size > tile_cap) fail(SNN_E_INVALID, "tile too large for LDS");
     // the delivery reads 16-bit targets, which identify a target only inside a range of
     // fewer than 65,536 targets
-    if ((uint64_t)net->tile_size * snn::kTileGroupMax > 65536) fail(SNN_E_INVALID, "tile range exceeds 65,536 targets");
+    if ((uint64_t)net->tile_size * snn::kTileGroupMax >= 65536) fail(SNN_E_INVALID, "tile range reaches 65,536 targets");
     // one 1,024-thread workgroup per CU (the kernel's registers allow one resident)
     net->grid = net->prm.grid ? net->prm.grid : net->cu_count * (net->block == 1024 ? 1u : 2u);
   } else if (net->delivery == SNN_DELIVERY_ATOMIC) {
