@@ -7,17 +7,19 @@ int32 targets, with one Q16 weight per source population as in Table I), J = 0.1
 g = 5, uniform delay 1.5 ms (15 steps), Poisson drive of 1,000 virtual inputs per neuron
 at 20 Hz, dt = 0.1 ms.  Synthetic, generated on the device from a seed.  One "step" is
 one simulation time step of the whole pipeline (update neurons -> FIFO -> receive
-spikes); `--steps` steps are timed after `--warmup` untimed ones.  The default warm-up,
-300 steps (30 ms), runs past the synchronous population burst that the uniform random
-initial potentials cause in the first ~10 ms, so that the timed steps measure the
-network's steady state (the paper's runs simulate 10 s).
+spikes).  Every run first simulates SETTLE_STEPS = 300 steps (30 ms), whatever
+`--warmup` says: the uniform random initial potentials cause a synchronous population
+burst in the first ~10 ms, and the timed steps are meant to measure the network's steady
+state (the paper's runs simulate 10 s).  Then `--warmup` untimed steps, then exactly
+`--steps` timed steps.
 
 Prints one JSON line: synaptic events/s over the timed steps (inputs resident in HBM,
 network built before the clock starts), wall time per simulated second, the delivery
-kernel's achieved HBM bandwidth (algorithmic bytes / mean launch time from HIP events
-on the simulator's stream) against the 8 TB/s peak, its measured HBM traffic when a
-counter summary of the current kernel source exists under profiles/, and the CPU
-oracle's rate on a bounded sample of the same workload.
+kernel's achieved HBM bandwidth (algorithmic bytes / mean launch duration, each timed
+launch stamped with its own begin and end by HIP events on the simulator's stream)
+against the 8 TB/s peak, its measured HBM traffic when a counter summary of the same
+kernel source at the same operating point exists under profiles/, and the CPU oracle's
+rate on a bounded sample of the same workload with the host it ran on.
 
 Other workloads (`--workload`, one JSON line each, not the headline):
   stdp   100,000-neuron plastic network (2e8 synapses, STDP on E->E), 2,000 steps
@@ -57,7 +59,10 @@ def delivery_bytes(info):
     tb = int(info.get("target_bytes", 4))
     return (tb, 16) if info.get("source_weights") else (tb + 4, 12)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_deliver_tiled_brunel_200k_k5000_d15.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1912_07423_amd", "csrc", "step.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1912_07423_amd", "csrc", f)
+                  for f in ("step.hip", "snn_internal.h", "device_math.h")]
+WORKLOAD = "brunel_fixed_out_200k_k5000_d15_poisson20hz"
+SETTLE_STEPS = 300  # past the start-up burst, always simulated before the warm-up
 
 
 def workload_spec():
@@ -67,19 +72,53 @@ def workload_spec():
 
 
 def kernel_source_sha():
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(point):
     """HBM bytes per delivery launch from the committed counter summary, if it was taken
-    of the current kernel source; otherwise None."""
+    of the current kernel source at exactly this operating point (workload, settle,
+    warm-up and timed steps, launch shape, and the timed region's events and spikes:
+    the simulation is deterministic, so equal counts mean the same launches); otherwise
+    None."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha") != kernel_source_sha():
+    if t.get("kernel_source_sha") != kernel_source_sha() or t.get("operating_point") != point:
         return None
     return t.get("bytes_per_launch")
+
+
+def host_info():
+    """CPU model, usable hardware threads and RAM of this host."""
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ram = None
+    try:
+        for ln in open("/proc/meminfo"):
+            if ln.startswith("MemTotal:"):
+                ram = int(ln.split()[1]) * 1024
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(),
+            "ram_gib": round(ram / 2**30, 1) if ram else None}
+
+
+def launches_for(steps, window):
+    """Delivery launches issued by one run(steps) call: windows of `window` steps (graph
+    replays hold whole windows) and a shorter last window."""
+    return -(-steps // window) if steps > 0 else 0
 
 
 def cpu_baseline_child(steps):
@@ -130,8 +169,13 @@ def bench_brunel(args):
     build_s = time.perf_counter() - tb
     info = net.info()
     print(f"[bench] built in {build_s:.2f}s: {info}", file=sys.stderr, flush=True)
+    net.run(SETTLE_STEPS)
     net.run(args.warmup)
     net.sync()
+    W = info["window"]
+    before = launches_for(SETTLE_STEPS, W) + launches_for(args.warmup, W)
+    print(f"[bench] settled {SETTLE_STEPS} + warm-up {args.warmup} steps ({before} delivery launches); "
+          f"timing {args.steps} steps", file=sys.stderr, flush=True)
 
     i0 = net.info()
     net.set_profiling(True)
@@ -149,16 +193,17 @@ def bench_brunel(args):
 
     events = i1["events"] - i0["events"]
     spikes = i1["spikes"] - i0["spikes"]
-    emitted = int(net.raster(args.warmup, args.warmup + args.steps).sum()) if args.steps <= 4096 else None
+    t_begin = SETTLE_STEPS + args.warmup
+    emitted = int(net.raster(t_begin, t_begin + args.steps).sum()) if args.steps <= 4096 else None
     dt_ms = spec["params"]["dt_ms"]
     launches = max(1, prof["deliver_launches"])
     deliver_avg_ms = prof["deliver_ms"] / launches
     b_ev, b_spk = delivery_bytes(info)
     bytes_per_launch = (events * b_ev + spikes * b_spk) / launches
     achieved = bytes_per_launch / (deliver_avg_ms * 1e-3) / 1e9 if deliver_avg_ms > 0 else 0.0
-    print(f"[bench] {args.steps} steps in {wall * 1e3:.2f} ms; {events} events; "
-          f"deliver {deliver_avg_ms * 1e3:.1f} us x {launches}; update "
-          f"{prof['update_ms'] / max(1, prof['update_launches']) * 1e3:.1f} us x "
+    print(f"[bench] {args.steps} steps in {wall * 1e3:.3f} ms; {events} events; "
+          f"deliver {deliver_avg_ms * 1e3:.2f} us x {launches}; update "
+          f"{prof['update_ms'] / max(1, prof['update_launches']) * 1e3:.2f} us x "
           f"{prof['update_launches']}", file=sys.stderr, flush=True)
 
     net.close()
@@ -177,22 +222,28 @@ def bench_brunel(args):
                    "sample": f"the same 200k-neuron / 1e9-synapse network built by the oracle "
                              f"({r['build_s']:.0f} s on all host threads, untimed), first "
                              f"{r['steps']} steps timed ({r['seconds']:.1f} s, {r['events']} "
-                             f"events) on one host thread"}
+                             f"events) on one host thread",
+                   "host": host_info()}
     kernel = "k_deliver_tiled" if info["delivery_name"] == "tiled" else "k_deliver_atomic"
-    traffic = measured_traffic() if kernel == "k_deliver_tiled" else None
+    point = {"workload": WORKLOAD, "settle_steps": SETTLE_STEPS, "warmup": args.warmup,
+             "steps": args.steps, "events": events, "spikes": spikes, "delivery": info["delivery_name"],
+             "tiles": info["tiles"], "window": W, "delivery_launches": prof["deliver_launches"]}
+    traffic = measured_traffic(point) if kernel == "k_deliver_tiled" else None
     line(METRIC, events / wall, "events/s", args.steps, args.warmup, wall * 1e3 / args.steps, "int32",
-         {"workload": "brunel_fixed_out_200k_k5000_d15_poisson20hz",
+         {"workload": WORKLOAD,
           "neurons": info["n"], "synapses": info["nnz"], "delay_steps": info["delay"],
-          "dt_ms": dt_ms, "delivery": info["delivery_name"], "window": info["window"],
+          "dt_ms": dt_ms, "delivery": info["delivery_name"], "window": W,
           "tiles": info["tiles"], "source_weights": bool(info["source_weights"]),
-          "parallelism": "single-gpu"},
+          "settle_steps": SETTLE_STEPS, "parallelism": "single-gpu"},
          wall_s_per_sim_s=wall / (args.steps * dt_ms * 1e-3), events=events,
          spikes_delivered=spikes, spikes_emitted=emitted,
          rate_hz=(emitted / info["n"] / (args.steps * dt_ms * 1e-3)) if emitted is not None else None,
          build_s=build_s,
          kernels={"deliver_ms_mean": deliver_avg_ms, "deliver_launches": prof["deliver_launches"],
                   "update_ms_mean": prof["update_ms"] / max(1, prof["update_launches"]),
-                  "update_launches": prof["update_launches"]},
+                  "update_launches": prof["update_launches"],
+                  "delivery_launches_before_timed": before},
+         operating_point=point,
          roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
                    "bytes_per_launch": bytes_per_launch, "bytes_per_event": b_ev,
@@ -201,13 +252,14 @@ def bench_brunel(args):
 
 
 def bench_stdp(args):
+    warm = max(args.warmup, SETTLE_STEPS)  # past the start-up burst
     import torch
     from paper_1912_07423_amd import Network
     from paper_1912_07423_amd import workloads as W
     spec = W.stdp_er()
     steps = args.steps if args.steps != 1000 else spec["steps"]
     net = Network(spec, raster_steps=4096)
-    net.run(args.warmup)
+    net.run(warm)
     net.sync()
     i0 = net.info()
     net.set_profiling(True)
@@ -234,7 +286,7 @@ def bench_stdp(args):
     achieved = events / (prof["deliver_ms"] * 1e-3) if prof["deliver_ms"] > 0 else 0.0
     saturated = ev_sat / (ms_sat * 1e-3) if ms_sat > 0 else 0.0
     line("STDP network: synaptic events/sec, STDP synapse touches/sec, 1 GPU", events / wall, "events/s",
-         steps, args.warmup, wall * 1e3 / steps, "fp32",
+         steps, warm, wall * 1e3 / steps, "fp32",
          {"workload": "stdp_er_100k_p0.02_d10_poisson10hz", "neurons": i1["n"], "synapses": i1["nnz"],
           "delay_steps": i1["delay"], "delivery": i1["delivery_name"], "parallelism": "single-gpu"},
          touches_per_s=touches / wall, events=events, touches=touches,
@@ -253,6 +305,7 @@ def bench_stdp(args):
 
 
 def bench_sweep(args):
+    warm = max(args.warmup, SETTLE_STEPS)  # past the start-up burst
     import numpy as np
     import torch
     from paper_1912_07423_amd import Batch, Network
@@ -264,7 +317,7 @@ def bench_sweep(args):
     build_s = time.perf_counter() - tb
     tuning = b.autotune(trial_steps=100)
     print(f"[bench] sweep built in {build_s:.1f}s; tuning {tuning}", file=sys.stderr, flush=True)
-    b.run(args.warmup)
+    b.run(warm)
     b.sync()
     ev0 = sum(b.network(k).events for k in range(len(specs)))
     torch.cuda.synchronize()
@@ -282,7 +335,7 @@ def bench_sweep(args):
     seq = 0.0
     for k in sample:
         g = Network(specs[k], raster_steps=16)
-        g.run(args.warmup)
+        g.run(warm)
         g.sync()
         t1 = time.perf_counter()
         g.run(steps)
@@ -291,7 +344,7 @@ def bench_sweep(args):
         g.close()
     seq_all = seq * len(specs) / len(sample)
     line("batched sweep: synaptic events/sec over 512 independent networks, 1 GPU", events / wall,
-         "events/s", steps, args.warmup, wall * 1e3 / steps, "int32",
+         "events/s", steps, warm, wall * 1e3 / steps, "int32",
          {"workload": "sweep_512_cuba_lif_1k-20k_p0.01-0.05", "networks": len(specs), "neurons": neurons,
           "synapses": synapses, "parallelism": "single-gpu"},
          network_steps_per_s=len(specs) * steps / wall, wall_s=wall, build_s=build_s, tuning=tuning,
@@ -328,7 +381,7 @@ def bench_bptt(args):
             plan.forward(x, w_in, w_rec, w_out, y)
 
     def timed(fn, n):
-        for _ in range(max(1, min(10, args.warmup // 5))):  # untimed iterations
+        for _ in range(max(3, min(10, args.warmup))):  # untimed iterations
             fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -385,14 +438,22 @@ def bench_bptt(args):
     plan.close()
 
 
-def summarize_pmc(fetch_dir, write_dir, copy_mib, command, skip):
+def summarize_pmc(fetch_dir, write_dir, lines, copy_mib, command):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) of
-    the same bench command into HBM bytes per tiled-delivery launch, each counter scaled
-    by what it reads for the plain device copy of `copy_mib` MiB in the same run.  The
-    first `skip` delivery dispatches (the untimed warm-up windows) are left out, so the
-    mean covers the launches whose algorithmic bytes the bench line reports."""
+    the same bench command into HBM bytes per tiled-delivery launch of its timed region,
+    each counter scaled by what it reads for the plain device copy of `copy_mib` MiB in
+    the same run.  `lines` are the two runs' JSON lines: they must report the same
+    operating point (the simulation is deterministic), which is recorded with the
+    summary, and they say which delivery dispatches precede the timed ones."""
     import csv
     import glob
+
+    recs = [json.loads(open(f).read().strip().splitlines()[-1]) for f in lines]
+    points = [r["operating_point"] for r in recs]
+    if points[0] != points[1]:
+        raise SystemExit(f"the two runs differ: {points}")
+    skip = recs[0]["kernels"]["delivery_launches_before_timed"]
+    timed = points[0]["delivery_launches"]
 
     def read(d, counter):
         rows = []
@@ -400,25 +461,30 @@ def summarize_pmc(fetch_dir, write_dir, copy_mib, command, skip):
             with open(f) as fh:
                 for r in csv.DictReader(fh):
                     if r.get("Counter_Name") == counter:
-                        rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+                        rows.append((int(r.get("Dispatch_Id", 0) or 0), r["Kernel_Name"], float(r["Counter_Value"])))
         if not rows:
             raise SystemExit(f"no {counter} rows under {d}")
-        return rows
+        rows.sort()
+        return [(k, v) for _, k, v in rows]
 
-    out = {"kernel_source_sha": kernel_source_sha(), "command": command, "copy_mib": copy_mib}
+    out = {"kernel_source_sha": kernel_source_sha(), "operating_point": points[0], "command": command,
+           "copy_mib": copy_mib}
     known = copy_mib * (1 << 20)
     for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = read(d, counter)
         # the three calibration copies are the largest copy dispatches of the run (the
         # runtime's copy kernel also serves the small copies of the simulator's setup)
         copies = sorted((v for k, v in rows if "copy" in k.lower()), reverse=True)[:3]
-        deliver = [v for k, v in rows if "k_deliver_tiled" in k][skip:]
-        if len(copies) < 3 or not deliver:
-            raise SystemExit(f"{counter}: need 3 copy and some k_deliver_tiled dispatches")
+        deliver = [v for k, v in rows if "k_deliver_tiled" in k]
+        if len(copies) < 3 or len(deliver) < skip + timed:
+            raise SystemExit(f"{counter}: need 3 copy and {skip + timed} k_deliver_tiled dispatches, "
+                             f"found {len(copies)} and {len(deliver)}")
+        deliver = deliver[skip:skip + timed]
         copy_kib = copies[1]
         factor = known / (copy_kib * 1024.0)
         out[f"{key}_copy_kib"] = copy_kib
         out[f"{key}_factor"] = factor
+        out[f"{key}_kib_per_dispatch"] = deliver
         out[f"{key}_bytes_per_launch"] = sum(deliver) / len(deliver) * 1024.0 * factor
         out[f"{key}_dispatches"] = len(deliver)
     out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
@@ -429,6 +495,7 @@ def summarize_pmc(fetch_dir, write_dir, copy_mib, command, skip):
 def bench_scaling(args):
     """Eq. 1 size sweep (Sec. IV, the runtime-vs-synapses comparison): both models grown
     with their weights scaled so that the firing regime is kept."""
+    warm = max(args.warmup, SETTLE_STEPS)  # past the start-up burst
     import torch
     from paper_1912_07423_amd import Network
     from paper_1912_07423_amd import workloads as W
@@ -439,7 +506,7 @@ def bench_scaling(args):
         for n in sizes:
             spec = W.vogels_scaled(n) if model == "vogels" else W.brunel_scaled(n)
             net = Network(spec, raster_steps=max(16, steps))
-            net.run(args.warmup)
+            net.run(warm)
             net.sync()
             i0 = net.info()
             torch.cuda.synchronize()
@@ -448,7 +515,7 @@ def bench_scaling(args):
             net.sync()
             wall = time.perf_counter() - t0
             i1 = net.info()
-            spikes = int(net.raster(args.warmup, args.warmup + steps).sum())
+            spikes = int(net.raster(warm, warm + steps).sum())
             dt = spec["params"]["dt_ms"] * 1e-3
             # the delivery kernel's roofline, from a separate profiled pass (HIP events
             # between the launches, which the timed run above does without)
@@ -474,7 +541,7 @@ def bench_scaling(args):
             net.close()
     top = points[-1]
     line("Eq. 1 size sweep: wall time per simulated second and synaptic events/sec vs synapse count, 1 GPU",
-         top["events_per_s"], "events/s", steps, args.warmup, top["wall_s_per_sim_s"] * 0.1, "int32",
+         top["events_per_s"], "events/s", steps, warm, top["wall_s_per_sim_s"] * 0.1, "int32",
          {"workload": "eq1_size_sweep_vogels_4k-128k_brunel_20k-400k", "parallelism": "single-gpu"},
          points=points)
 
@@ -486,6 +553,7 @@ def bench_layout(args):
     the geometry of the paper's aligned 2-D adjacency array), each with one weight per
     source (4 B per synapse) and with a weight per synapse (8 B), through the tiled and
     the atomic delivery.  Reported: each delivery's algorithmic bytes per second."""
+    warm = max(args.warmup, SETTLE_STEPS)  # past the start-up burst
     from paper_1912_07423_amd import Network
     from paper_1912_07423_amd import workloads as W
     steps = min(args.steps, 300)
@@ -497,7 +565,7 @@ def bench_layout(args):
             net = Network(spec, raster_steps=16, synapse_weights=weights)
             for delivery in ("tiled", "atomic"):
                 net.set_delivery(delivery)
-                net.run(args.warmup)
+                net.run(warm)
                 net.sync()
                 i0 = net.info()
                 net.set_profiling(True)
@@ -521,7 +589,7 @@ def bench_layout(args):
             net.close()
     best = max(points, key=lambda p: p["algorithmic_gbs"])
     line("delivery bandwidth by adjacency layout (CSR vs 128-B aligned rows; 4 vs 8 B per synapse), 1 GPU",
-         best["algorithmic_gbs"], "GB/s", steps, args.warmup, None, "int32",
+         best["algorithmic_gbs"], "GB/s", steps, warm, None, "int32",
          {"workload": "layout_ab_brunel_200k_k5000_vs_k5024_d15", "parallelism": "single-gpu"},
          points=points)
 
@@ -580,7 +648,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=15,
+                    help="untimed steps after the fixed 300-step settle period (Brunel workload)")
     ap.add_argument("--cpu-steps", type=int, default=1500,
                     help="steps of the CPU-oracle sample (0 disables it)")
     ap.add_argument("--delivery", default="auto")
@@ -588,15 +657,15 @@ def main():
     ap.add_argument("--workload", default="brunel", choices=["brunel", "stdp", "sweep", "bptt", "scaling", "setup", "layout"])
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run 3 plain device copies of this size first (HBM counter scaling)")
-    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="write the traffic summary of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "FETCH_LINE", "WRITE_LINE"),
+                    help="write the traffic summary of two rocprofv3 --pmc runs (their output "
+                         "directories and the JSON lines they printed) and exit")
     ap.add_argument("--pmc-command", default="", help="the profiled command, recorded in the summary")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.summarize_pmc:
-        # the profiled run's untimed warm-up windows (15-step windows of the headline network)
-        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.copy_calibration_mib,
-                      args.pmc_command, skip=-(-args.warmup // 15))
+        f, w, fl, wl = args.summarize_pmc
+        summarize_pmc(f, w, [fl, wl], args.copy_calibration_mib, args.pmc_command)
         return
     if args.cpu_baseline_child:
         cpu_baseline_child(args.cpu_steps)

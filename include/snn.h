@@ -11,8 +11,8 @@
  *
  * Conventions
  *  - Every call returns snn_status: SNN_OK (0) or a negative error code.  No C++
- *    exception crosses this interface.  snn_last_error() returns a message for the
- *    last failing call on the calling thread (storage owned by the library, valid
+ *    exception crosses this interface.  snn_last_error(net) returns a message for
+ *    the last failing call on the calling thread (storage owned by the library, valid
  *    until the next call on that thread).
  *  - snn_network is opaque; the library owns it and every device buffer it holds.
  *    The caller owns every host array passed in or out.  Host arrays are read or
@@ -181,13 +181,23 @@ snn_status snn_build_network(const snn_params *prm, const snn_population *pops, 
  * receive spikes).  Asynchronous. */
 snn_status snn_step(snn_network *net);
 
-/* Advance n_steps steps; launches are grouped into windows of up to `window` steps
- * and replayed from a captured HIP graph where possible.  Asynchronous. */
+/* Advance n_steps steps: the loop of repeated step() calls that drives a network in
+ * the paper's interface (Sec. III-B, the listing that ends in `while (true)
+ * net.step()`), each step being the Fig. 1 pipeline.  Launches are grouped into windows
+ * of up to `window` steps and replayed from a captured HIP graph where possible.  The
+ * result is identical to n_steps calls of snn_step.  Asynchronous.  SNN_E_STATE for a
+ * batch member; SNN_E_HIP if a launch fails. */
 snn_status snn_run(snn_network *net, uint32_t n_steps);
 
-/* Spikes of steps [t_begin, t_end) as (step, id) pairs sorted by step then id.
- * Returns SNN_E_INVALID if the range is not held by the raster ring, and
- * SNN_E_OVERFLOW with *n_spikes = required count if capacity is too small. */
+/* Download of timestamped spikes (Sec. III-B: the simulators compared there let the
+ * user download the spikes of a run with their time stamps): the spikes of steps
+ * [t_begin, t_end) as (step, id) pairs sorted by step, then by id, written to the
+ * caller's host arrays steps[] and ids[] (capacity entries each).  *n_spikes always
+ * receives the number of spikes in the range.  Synchronises the network's stream.
+ * Errors: SNN_E_INVALID if t_end < t_begin, if the range reaches past the simulated
+ * steps or is no longer held by the raster ring (raster_steps most recent steps), or if
+ * an output array is NULL while the range holds spikes; SNN_E_OVERFLOW if capacity is
+ * below the count (nothing is written; call again with *n_spikes entries). */
 snn_status snn_get_raster(snn_network *net, uint64_t t_begin, uint64_t t_end, uint32_t *steps,
                           uint32_t *ids, uint64_t capacity, uint64_t *n_spikes);
 
@@ -250,7 +260,10 @@ typedef struct {
 snn_status snn_autotune_delivery(snn_network *net, uint32_t reps, snn_delivery_tuning *chosen);
 
 void snn_destroy(snn_network *net);
-const char *snn_last_error(void);
+/* Message of the last failing call on the calling thread (thread-local storage owned by
+ * the library, valid until the next call on that thread).  `net` may be NULL: the
+ * message does not depend on it. */
+const char *snn_last_error(const snn_network *net);
 
 /* ---- Device-memory cache (Sec. IV: allocate only when necessary, with hysteresis) ---
  *

@@ -24,8 +24,15 @@
  *                       brute-force propagation (int64 mat-vec) incl. delays, the
  *                       ping-pong model of Listing 1, FIFO delay invariants, exact
  *                       event counts, closed-form pair STDP and all-pairs STDP sums.
- *   V0 initialisation   parity unpinned beyond range/uniformity statistics (any
- *                       fixed counter-based definition is as correct as another).
+ *   V0 initialisation   pinned: every value in [lo, hi] (binary32 rounding of
+ *                       lo + span u can give hi itself), Kolmogorov-Smirnov test against
+ *                       U(lo, hi), mean and variance within 5 standard errors over
+ *                       1e5 neurons for several seeds and ranges, independence of the
+ *                       network size and of other seeds; planted mistakes (span = hi,
+ *                       the unshifted word) fail it.
+ *   plastic delivery    pinned: FP32 weights at exact Q16 ties (x.5 2^-16 mV, both
+ *                       signs) deliver the round-half-even value; truncation, floor,
+ *                       half-up and half-away each fail it.
  */
 #ifndef SNN_ORACLE_H
 #define SNN_ORACLE_H

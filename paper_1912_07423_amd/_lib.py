@@ -136,7 +136,7 @@ SIGNATURES = {
     "snn_set_delivery": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]),
     "snn_autotune_delivery": (C.c_int32, [C.c_void_p, C.c_uint32, C.POINTER(DeliveryTuning)]),
     "snn_destroy": (None, [C.c_void_p]),
-    "snn_last_error": (C.c_char_p, []),
+    "snn_last_error": (C.c_char_p, [C.c_void_p]),
     "snn_build_batch": (C.c_int32, [C.POINTER(BatchMember), C.c_uint32, C.c_uint32,
                                     C.POINTER(Allocator), C.c_void_p, C.POINTER(C.c_void_p)]),
     "snn_batch_run": (C.c_int32, [C.c_void_p, C.c_uint32]),
@@ -188,4 +188,4 @@ def load():
 
 def check(status):
     if status != SNN_OK:
-        raise SnnError(status, load().snn_last_error().decode(errors="replace"))
+        raise SnnError(status, load().snn_last_error(None).decode(errors="replace"))

@@ -94,7 +94,11 @@ void pool_release(int device) {
   }
 }
 
-void *pool_alloc(int device, size_t bytes) {
+// Serves `bytes` on `device`; *got receives the size of the block handed out (a kept
+// block may be up to twice the request plus 1 MiB), which the caller records and hands
+// back to pool_free, so a reused block keeps its true size.
+void *pool_alloc(int device, size_t bytes, size_t *got) {
+  *got = bytes;
   {
     std::lock_guard<std::mutex> lock(g_pool_mutex);
     size_t best = g_pool.size();
@@ -105,6 +109,7 @@ void *pool_alloc(int device, size_t bytes) {
     }
     if (best != g_pool.size()) {
       void *p = g_pool[best].p;
+      *got = g_pool[best].bytes;
       g_pool.erase(g_pool.begin() + (std::ptrdiff_t)best);
       ++g_pool_stats[device].hits;
       return p;
@@ -120,7 +125,7 @@ void *pool_alloc(int device, size_t bytes) {
   return nullptr;
 }
 
-// Keeps a block for reuse; its size is the rounded size it was allocated with.
+// Keeps a block for reuse; `bytes` is its true size (as pool_alloc reported it).
 void pool_free(int device, void *p, size_t bytes) {
   std::lock_guard<std::mutex> lock(g_pool_mutex);
   g_pool.push_back({device, p, bytes});
@@ -134,8 +139,10 @@ void *dev_alloc(snn_network *net, size_t bytes) {
     p = net->alloc.alloc(bytes, (void *)net->stream, net->alloc.ctx);
     if (!p) fail(SNN_E_OOM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
   } else {
-    p = pool_alloc(net->device, bytes);
+    size_t got = bytes;
+    p = pool_alloc(net->device, bytes, &got);
     if (!p) fail(SNN_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    bytes = got;  // a reused block may be larger than the request: record what is held
   }
   net->allocs.push_back({p, bytes});
   net->device_bytes += bytes;
@@ -658,10 +665,11 @@ snn::StdpArgs stdp_args(snn_network *net) {
 
 uint32_t atomic_grid(const snn_network *net) { return net->cu_count * 8; }
 
-hipError_t launch_delivery(snn_network *net, const snn::DeliverArgs &d, uint32_t steps) {
+hipError_t launch_delivery(snn_network *net, const snn::DeliverArgs &d, uint32_t steps,
+                           const snn::LaunchEvents &ev = {}) {
   if (net->delivery == SNN_DELIVERY_TILED)
-    return snn::launch_deliver_tiled(d, steps, net->block, net->grid, net->stream);
-  return snn::launch_deliver_atomic(d, steps, atomic_grid(net), net->stream);
+    return snn::launch_deliver_tiled(d, steps, net->block, net->grid, net->stream, ev);
+  return snn::launch_deliver_atomic(d, steps, atomic_grid(net), net->stream, ev);
 }
 
 hipEvent_t pooled_event(snn_network *net) {
@@ -671,29 +679,24 @@ hipEvent_t pooled_event(snn_network *net) {
   return e;
 }
 
-// With profiling on, consecutive launches share events: the event after one launch is
-// the event before the next, so a window adds one marker per kernel to the stream.
+// With profiling on, every launch gets its own pair of events, stamped by the dispatch
+// itself with its begin and end (hipExtLaunchKernel): no marker packet is placed between
+// launches, so the durations are the kernels' own and the stream runs as without them.
 template <typename F>
 void timed(snn_network *net, int kind, F &&launch) {
   if (!net->profiling) {
-    check(launch(), "kernel launch");
+    check(launch(snn::LaunchEvents{}), "kernel launch");
     return;
   }
-  hipEvent_t a = net->prof_last;
-  if (!a) {
-    a = pooled_event(net);
-    check(hipEventRecord(a, net->stream), "hipEventRecord");
-  }
-  check(launch(), "kernel launch");
-  hipEvent_t b = pooled_event(net);
-  check(hipEventRecord(b, net->stream), "hipEventRecord");
-  net->prof_pending.push_back(snn_network::ProfRecord{kind, a, b});
-  net->prof_last = b;
+  snn::LaunchEvents ev;
+  ev.start = pooled_event(net);
+  ev.stop = pooled_event(net);
+  check(launch(ev), "kernel launch");
+  net->prof_pending.push_back(snn_network::ProfRecord{kind, ev.start, ev.stop});
 }
 
 void resolve_profile(snn_network *net) {
   auto &v = net->prof_pending;
-  net->prof_last = nullptr;
   if (v.empty()) return;
   check(hipStreamSynchronize(net->stream), "sync");
   std::vector<hipEvent_t> done;
@@ -722,13 +725,13 @@ void resolve_profile(snn_network *net) {
 // One window of `steps` consecutive steps: update -> [STDP] -> delivery.
 void issue_window(snn_network *net, uint32_t steps) {
   const snn::UpdateArgs u = update_args(net);
-  timed(net, 0, [&] { return snn::launch_update(u, steps, net->stream); });
+  timed(net, 0, [&](const snn::LaunchEvents &ev) { return snn::launch_update(u, steps, net->stream, ev); });
   if (net->plastic) {
     const snn::StdpArgs sa = stdp_args(net);
-    timed(net, 2, [&] { return snn::launch_stdp(sa, net->cu_count * 4, net->stream); });
+    timed(net, 2, [&](const snn::LaunchEvents &ev) { return snn::launch_stdp(sa, net->cu_count * 4, net->stream, ev); });
   }
   const snn::DeliverArgs d = deliver_args(net);
-  timed(net, 1, [&] { return launch_delivery(net, d, steps); });
+  timed(net, 1, [&](const snn::LaunchEvents &ev) { return launch_delivery(net, d, steps, ev); });
   net->t_host += steps;
 }
 
@@ -773,7 +776,6 @@ void run(snn_network *net, uint64_t n_steps) {
 }
 
 void sync(snn_network *net) {
-  net->prof_last = nullptr;
   check(hipStreamSynchronize(net->stream), "stream sync");
 }
 
@@ -830,34 +832,62 @@ void dev_free(snn_network *net, void *p) {
     }
 }
 
-void build_tile_offsets(snn_network *net) {
-  if (net->delivery != SNN_DELIVERY_TILED) return;
-  alloc_tile_offsets(net);
-  check(hipStreamSynchronize(net->stream), "sync after tile offsets");
-}
-
 // A new delivery variant / tiling / launch shape, taking effect at the next window (the
 // input ring holds exactly the pending arrivals at every window boundary, whichever
-// variant filled it).
+// variant filled it).  The new configuration is resolved and its tile index built before
+// anything of the old one is released; if any of that fails (an impossible block or
+// tiling, device memory, a launch), every field and buffer of the old configuration is
+// restored, so the network keeps running as before.
 void set_delivery(snn_network *net, uint32_t delivery, uint32_t tiles, uint32_t block, uint32_t grid) {
   if (delivery > SNN_DELIVERY_TILED) fail(SNN_E_INVALID, "unknown delivery variant");
   if (net->plastic && delivery == SNN_DELIVERY_TILED) fail(SNN_E_INVALID, "tiled delivery needs static weights");
   check(hipStreamSynchronize(net->stream), "sync");
-  net->prm.delivery = delivery;
-  net->prm.tiles = tiles;
-  net->prm.block = block;
-  net->prm.grid = grid;
-  net->delivery = net->plastic ? SNN_DELIVERY_ATOMIC : delivery;
-  choose_delivery(net);
-  if (net->tile_off) {
-    dev_free(net, net->tile_off);
-    net->tile_off = nullptr;
+  struct Saved {
+    uint32_t p_delivery, p_tiles, p_block, p_grid, delivery, block, tiles, tile_size, grid;
+    void *tile_off;
+    uint16_t *col16;
+    bool tile_off16;
+  };
+  const Saved old{net->prm.delivery, net->prm.tiles, net->prm.block, net->prm.grid, net->delivery,
+                  net->block,        net->tiles,     net->tile_size, net->grid,     net->tile_off,
+                  net->col16,        net->tile_off16};
+  try {
+    net->prm.delivery = delivery;
+    net->prm.tiles = tiles;
+    net->prm.block = block;
+    net->prm.grid = grid;
+    net->delivery = net->plastic ? SNN_DELIVERY_ATOMIC : delivery;
+    choose_delivery(net);
+    if (net->delivery == SNN_DELIVERY_TILED) {
+      net->tile_off = nullptr;  // a fresh index; the old one stays valid until this succeeds
+      alloc_tile_offsets(net);  // reuses col16 when it exists (it does not depend on the tiling)
+      check(hipStreamSynchronize(net->stream), "sync after tile offsets");
+    } else {
+      net->tile_off = nullptr;
+    }
+  } catch (...) {
+    (void)hipStreamSynchronize(net->stream);  // no index launch may still write a block freed here
+    if (net->tile_off && net->tile_off != old.tile_off) dev_free(net, net->tile_off);
+    if (net->col16 && net->col16 != old.col16) dev_free(net, net->col16);
+    net->prm.delivery = old.p_delivery;
+    net->prm.tiles = old.p_tiles;
+    net->prm.block = old.p_block;
+    net->prm.grid = old.p_grid;
+    net->delivery = old.delivery;
+    net->block = old.block;
+    net->tiles = old.tiles;
+    net->tile_size = old.tile_size;
+    net->grid = old.grid;
+    net->tile_off = old.tile_off;
+    net->col16 = old.col16;
+    net->tile_off16 = old.tile_off16;
+    throw;
   }
+  if (old.tile_off) dev_free(net, old.tile_off);
   if (net->col16 && net->delivery != SNN_DELIVERY_TILED) {
     dev_free(net, net->col16);
     net->col16 = nullptr;
   }
-  build_tile_offsets(net);
   if (net->graph) {
     (void)hipGraphExecDestroy(net->graph);
     net->graph = nullptr;
@@ -911,16 +941,22 @@ double time_delivery(snn_network *net, const std::vector<std::vector<uint32_t>> 
     d.ctl = ctl;
     d.advance = 0;
     check(launch_delivery(net, d, steps), "warm-up delivery");
-    net->prof_last = nullptr;
-    hipEvent_t a = new_event(), b = new_event();
-    check(hipEventRecord(a, s), "event");
-    for (uint32_t r = 0; r < reps; ++r) check(launch_delivery(net, d, steps), "delivery");
-    check(hipEventRecord(b, s), "event");
-    check(hipEventSynchronize(b), "event sync");
+    // each launch stamped with its own begin and end (no marker packets between them)
+    std::vector<snn::LaunchEvents> evs(reps);
+    for (auto &e : evs) {
+      e.start = pooled_event(net);
+      e.stop = pooled_event(net);
+    }
+    for (uint32_t r = 0; r < reps; ++r) check(launch_delivery(net, d, steps, evs[r]), "delivery");
+    check(hipStreamSynchronize(s), "sync");
     float ms = 0.f;
-    check(hipEventElapsedTime(&ms, a, b), "elapsed");
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    for (auto &e : evs) {
+      float one = 0.f;
+      check(hipEventElapsedTime(&one, e.start, e.stop), "elapsed");
+      ms += one;
+      net->event_pool.push_back(e.start);
+      net->event_pool.push_back(e.stop);
+    }
     std::vector<snn::Ctl> c1(1);
     check(hipMemcpy(c1.data(), ctl, sizeof(snn::Ctl), hipMemcpyDeviceToHost), "ctl");
     ms_out = ms / reps;
@@ -1627,7 +1663,6 @@ snn_status snn_set_profiling(snn_network *net, int32_t on) {
   return guarded([&] {
     if (!net) fail(SNN_E_INVALID, "null network");
     net->profiling = on != 0;
-    net->prof_last = nullptr;
   });
 }
 
@@ -1700,7 +1735,7 @@ void snn_destroy(snn_network *net) {
   delete net;
 }
 
-const char *snn_last_error(void) { return g_error.c_str(); }
+const char *snn_last_error(const snn_network *) { return g_error.c_str(); }
 
 snn_status snn_build_batch(const snn_batch_member *nets, uint32_t n_nets, uint32_t raster_steps,
                            const snn_allocator *alloc, void *stream, snn_batch **out) {

@@ -1,5 +1,6 @@
 // snn_internal.h -- library-private types shared by the host runtime and kernels.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -181,15 +182,24 @@ hipError_t bptt_forward(const BpttArgs &a, const float *x, const int32_t *labels
 typedef struct _rocblas_handle *rocblas_handle_t;
 hipError_t bptt_backward(const BpttArgs &a, const float *g_loss, rocblas_handle_t blas, hipStream_t s);
 
+// Optional timing events of one launch.  When set, the kernel is launched with
+// hipExtLaunchKernel, which stamps `start` and `stop` with the dispatch's own begin and
+// end (no marker packet is placed between launches); launches that span two kernels
+// stamp the first one's begin and the last one's end.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool on() const { return start != nullptr || stop != nullptr; }
+};
+
 // kernel launchers (step.hip / generate.hip)
-hipError_t launch_update(const UpdateArgs &a, uint32_t steps, hipStream_t s);
+hipError_t launch_update(const UpdateArgs &a, uint32_t steps, hipStream_t s, const LaunchEvents &ev = {});
 hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t grid,
-                                 hipStream_t s);
+                                 hipStream_t s, const LaunchEvents &ev = {});
 hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t block,
-                                uint32_t grid, hipStream_t s);
+                                uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});
 constexpr uint32_t kTileGroupMax = 8;  // base tiles one tiled-delivery workgroup may own
 hipError_t prepare_deliver_tiled(uint32_t block, size_t *max_dynamic_lds);
-hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});
 hipError_t launch_row_lengths(const GenArgs &g, uint32_t *len, uint32_t *plast_rel,
                               uint32_t *plast_len, hipStream_t s);
 hipError_t launch_fill_rows(const GenArgs &g, uint32_t max_fixed_k, const uint64_t *row_ptr,
@@ -290,5 +300,4 @@ struct snn_network {
   snn_profile prof{};
   std::vector<ProfRecord> prof_pending;
   std::vector<hipEvent_t> event_pool;
-  hipEvent_t prof_last = nullptr;  // last event recorded, if nothing was enqueued since
 };

@@ -738,16 +738,24 @@ __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltp(StdpArgs a) {
 
 }  // namespace
 
-hipError_t launch_update(const UpdateArgs &a, uint32_t steps, hipStream_t s) {
+// One launch, through hipExtLaunchKernel when timing events are requested.
+template <typename... KArgs, typename... Args>
+void launch_kernel(void (*kernel)(KArgs...), uint32_t grid, uint32_t block, size_t lds, hipStream_t s,
+                   hipEvent_t start, hipEvent_t stop, Args... args) {
+  if (start || stop) hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), (uint32_t)lds, s, start, stop, 0u, args...);
+  else kernel<<<grid, block, lds, s>>>(args...);
+}
+
+hipError_t launch_update(const UpdateArgs &a, uint32_t steps, hipStream_t s, const LaunchEvents &ev) {
   const uint32_t grid = (a.n + kUpdateBlock - 1) / kUpdateBlock;
-  k_update<<<grid, kUpdateBlock, 0, s>>>(a, steps);
+  launch_kernel(k_update, grid, kUpdateBlock, 0, s, ev.start, ev.stop, a, steps);
   return hipGetLastError();
 }
 
-hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t grid, hipStream_t s) {
-  if (a.w_f32) k_deliver_atomic<kWeightF32><<<grid, kAtomicBlock, 0, s>>>(a, steps);
-  else if (a.w_src) k_deliver_atomic<kWeightSrc><<<grid, kAtomicBlock, 0, s>>>(a, steps);
-  else k_deliver_atomic<kWeightQ16><<<grid, kAtomicBlock, 0, s>>>(a, steps);
+hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t grid, hipStream_t s,
+                                 const LaunchEvents &ev) {
+  auto k = a.w_f32 ? k_deliver_atomic<kWeightF32> : a.w_src ? k_deliver_atomic<kWeightSrc> : k_deliver_atomic<kWeightQ16>;
+  launch_kernel(k, grid, kAtomicBlock, 0, s, ev.start, ev.stop, a, steps);
   return hipGetLastError();
 }
 
@@ -785,7 +793,7 @@ hipError_t prepare_deliver_tiled(uint32_t block, size_t *max_dynamic_lds) {
 }
 
 hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t block,
-                                uint32_t grid, hipStream_t s) {
+                                uint32_t grid, hipStream_t s, const LaunchEvents &ev) {
   // the schedule always fits when every step uses maximal ranges
   const uint32_t floor_grid = steps * ((a.tiles + kTileGroupMax - 1) / kTileGroupMax);
   if (grid < floor_grid) grid = floor_grid;
@@ -793,24 +801,24 @@ hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t b
   const bool src_w = a.w_src != nullptr;
   switch (block) {
     case 256:
-      if (src_w) k_deliver_tiled<256, true><<<grid, 256, lds, s>>>(a, steps);
-      else k_deliver_tiled<256, false><<<grid, 256, lds, s>>>(a, steps);
+      launch_kernel(src_w ? k_deliver_tiled<256, true> : k_deliver_tiled<256, false>, grid, 256, lds, s,
+                    ev.start, ev.stop, a, steps);
       break;
     case 512:
-      if (src_w) k_deliver_tiled<512, true><<<grid, 512, lds, s>>>(a, steps);
-      else k_deliver_tiled<512, false><<<grid, 512, lds, s>>>(a, steps);
+      launch_kernel(src_w ? k_deliver_tiled<512, true> : k_deliver_tiled<512, false>, grid, 512, lds, s,
+                    ev.start, ev.stop, a, steps);
       break;
     default:
-      if (src_w) k_deliver_tiled<1024, true><<<grid, 1024, lds, s>>>(a, steps);
-      else k_deliver_tiled<1024, false><<<grid, 1024, lds, s>>>(a, steps);
+      launch_kernel(src_w ? k_deliver_tiled<1024, true> : k_deliver_tiled<1024, false>, grid, 1024, lds, s,
+                    ev.start, ev.stop, a, steps);
       break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s) {
-  k_stdp_ltd<<<grid, kStdpBlock, 0, s>>>(a);
-  k_stdp_ltp<<<grid, kStdpBlock, 0, s>>>(a);
+hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev) {
+  launch_kernel(k_stdp_ltd, grid, kStdpBlock, 0, s, ev.start, nullptr, a);
+  launch_kernel(k_stdp_ltp, grid, kStdpBlock, 0, s, nullptr, ev.stop, a);
   return hipGetLastError();
 }
 

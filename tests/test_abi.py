@@ -65,14 +65,15 @@ def test_struct_layouts_match_header():
 
 
 def test_last_error_is_a_string():
-    assert isinstance(L.load().snn_last_error(), bytes)
+    assert isinstance(L.load().snn_last_error(None), bytes)
 
 
 def test_null_arguments_rejected_without_gpu():
     lib = L.load()
     h = C.c_void_p()
     assert lib.snn_build_network(None, None, 0, None, 0, None, None, C.byref(h)) == L.SNN_E_INVALID
-    assert b"null" in lib.snn_last_error()
+    assert b"null" in lib.snn_last_error(None)
+    assert b"null" in lib.snn_last_error(h)  # the message is per thread, not per network
     assert lib.snn_run(None, 1) == L.SNN_E_INVALID
     assert lib.snn_get_info(None, None) == L.SNN_E_INVALID
     lib.snn_destroy(None)

@@ -28,25 +28,64 @@ def _csv(path, counter, rows):
             w.writerow({"Dispatch_Id": i, "Kernel_Name": k, "Counter_Name": counter, "Counter_Value": v})
 
 
+def _bench_line(path, point, before):
+    with open(path, "w") as f:
+        f.write("[bench] noise\n")
+        f.write(json.dumps({"operating_point": point, "kernels": {"delivery_launches_before_timed": before}}) + "\n")
+
+
 def test_traffic_summary_scales_by_the_copy(tmp_path, monkeypatch):
     out = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
     copy = "void at::native::direct_copy_kernel_cuda(...)"
-    # the copy of 1 MiB reads 1024 KiB and the counter says 512: factor 2
+    d = "snn::k_deliver_tiled<512>"
+    # the copy of 1 MiB reads 1024 KiB and the counter says 512: factor 2.  One delivery
+    # dispatch precedes the timed region, two are timed, one follows (not counted)
     _csv(str(tmp_path / "f" / "x" / "run_counter_collection.csv"), "FETCH_SIZE",
-         [(copy, 512.0), (copy, 512.0), (copy, 512.0), (copy, 3.0), ("snn::k_deliver_tiled<512>", 100.0),
-          ("snn::k_deliver_tiled<512>", 300.0), ("snn::k_update", 7.0)])
+         [(copy, 512.0), (copy, 512.0), (copy, 512.0), (copy, 3.0), (d, 999.0), (d, 100.0),
+          (d, 300.0), ("snn::k_update", 7.0), (d, 777.0)])
     _csv(str(tmp_path / "w" / "run_counter_collection.csv"), "WRITE_SIZE",
-         [(copy, 1024.0), (copy, 1024.0), (copy, 1024.0), (copy, 0.0), ("snn::k_deliver_tiled<512>", 10.0)])
-    bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), 1, "cmd", skip=0)
+         [(copy, 1024.0), (copy, 1024.0), (copy, 1024.0), (copy, 0.0), (d, 55.0), (d, 10.0), (d, 10.0),
+          (d, 66.0)])
+    point = {"workload": bench.WORKLOAD, "settle_steps": 300, "warmup": 5, "steps": 20, "events": 123,
+             "spikes": 4, "delivery": "tiled", "tiles": 87, "window": 15, "delivery_launches": 2}
+    _bench_line(str(tmp_path / "a.json"), point, 1)
+    _bench_line(str(tmp_path / "b.json"), point, 1)
+    bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"),
+                        [str(tmp_path / "a.json"), str(tmp_path / "b.json")], 1, "cmd")
     t = json.load(open(out))
     assert t["fetch_factor"] == pytest.approx(2.0) and t["write_factor"] == pytest.approx(1.0)
     assert t["fetch_bytes_per_launch"] == pytest.approx(200.0 * 1024 * 2)
     assert t["write_bytes_per_launch"] == pytest.approx(10.0 * 1024)
     assert t["bytes_per_launch"] == pytest.approx(200.0 * 1024 * 2 + 10.0 * 1024)
     assert t["kernel_source_sha"] == bench.kernel_source_sha()
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
-    assert bench.measured_traffic() == pytest.approx(t["bytes_per_launch"])
+    assert bench.measured_traffic(point) == pytest.approx(t["bytes_per_launch"])
+    # any other operating point gets no traffic figure
+    for k, v in (("warmup", 6), ("events", 124), ("steps", 1000), ("tiles", 88)):
+        assert bench.measured_traffic({**point, k: v}) is None
+    # nor does another kernel source
+    monkeypatch.setattr(bench, "kernel_source_sha", lambda: "0" * 16)
+    assert bench.measured_traffic(point) is None
+
+
+def test_traffic_summary_refuses_runs_at_different_points(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    point = {"workload": bench.WORKLOAD, "steps": 20, "events": 1}
+    _bench_line(str(tmp_path / "a.json"), point, 1)
+    _bench_line(str(tmp_path / "b.json"), {**point, "events": 2}, 1)
+    with pytest.raises(SystemExit):
+        bench.summarize_pmc(str(tmp_path), str(tmp_path), [str(tmp_path / "a.json"), str(tmp_path / "b.json")],
+                            1, "cmd")
+
+
+def test_launch_count_of_a_run():
+    assert bench.launches_for(300, 15) == 20 and bench.launches_for(5, 15) == 1
+    assert bench.launches_for(0, 15) == 0 and bench.launches_for(20, 15) == 2
+
+
+def test_host_info_fields():
+    h = bench.host_info()
+    assert h["nproc"] >= 1 and set(h) == {"cpu_model", "nproc", "cpu_count", "ram_gib"}
 
 
 def test_delivery_byte_model():
