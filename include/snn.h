@@ -367,7 +367,9 @@ typedef struct {
     uint32_t checkpoint;   /* steps per checkpoint segment, 1..32 */
     float beta, beta_out, theta, slope;
     uint32_t smooth;       /* 0: spiking forward, surrogate backward; 1: smooth forward */
-    uint32_t pad_;
+    uint32_t eager;        /* 0: replay the per-step kernels of each pass from a HIP graph
+                              captured at the plan's first call; 1: launch them one by one
+                              (same kernels, same results) */
 } snn_bptt_desc;
 
 /* A plan for one network structure: host CSR arrays (rows = presynaptic neuron, targets

@@ -104,7 +104,7 @@ class BpttDesc(C.Structure):
     _fields_ = [("batch", C.c_uint32), ("steps", C.c_uint32), ("n_in", C.c_uint32),
                 ("n_hidden", C.c_uint32), ("n_out", C.c_uint32), ("checkpoint", C.c_uint32),
                 ("beta", C.c_float), ("beta_out", C.c_float), ("theta", C.c_float),
-                ("slope", C.c_float), ("smooth", C.c_uint32), ("pad_", C.c_uint32)]
+                ("slope", C.c_float), ("smooth", C.c_uint32), ("eager", C.c_uint32)]
 
 
 # every symbol declared in include/snn.h, with its ctypes signature

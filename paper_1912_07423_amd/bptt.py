@@ -26,10 +26,13 @@ def _csr(mask):
 
 
 class RecurrentLIF:
-    """Plan (structure + workspace) of the recurrent LIF network on one GPU."""
+    """Plan (structure + workspace) of the recurrent LIF network on one GPU.  The per-step
+    kernels of each pass are replayed from HIP graphs captured at the first call, or
+    launched one by one with eager=True (same kernels, same results)."""
 
     def __init__(self, in_mask, rec_mask, n_out, batch, steps, checkpoint=25, tau_ms=20.0,
-                 tau_out_ms=20.0, dt_ms=1.0, theta=1.0, slope=25.0, smooth=False, device=0):
+                 tau_out_ms=20.0, dt_ms=1.0, theta=1.0, slope=25.0, smooth=False, eager=False,
+                 device=0):
         import torch
         self._lib = L.load()
         self._h = None
@@ -44,7 +47,7 @@ class RecurrentLIF:
         d = L.BpttDesc(batch=self.batch, steps=self.steps, n_in=self.n_in, n_hidden=self.n_hidden,
                        n_out=self.n_out, checkpoint=int(checkpoint),
                        beta=math.exp(-dt_ms / tau_ms), beta_out=math.exp(-dt_ms / tau_out_ms),
-                       theta=theta, slope=slope, smooth=1 if smooth else 0)
+                       theta=theta, slope=slope, smooth=1 if smooth else 0, eager=1 if eager else 0)
         self.desc = d
         stream = torch.cuda.current_stream(self.device)
 

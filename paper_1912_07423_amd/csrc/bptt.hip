@@ -9,13 +9,12 @@
 //   vck   [T/K][H][64]       membrane potential before each checkpoint segment
 //   vseg  [K][H][64]         membranes of one segment, recomputed in the backward pass
 //   lamu  [T][O][64]         readout adjoint
-//   lamv  [K][H][64]         membrane adjoint of one segment (+ carry [H][64])
+//   lamv  [T][H][64]         membrane adjoint of every step (+ zeros [H][64] for step T)
+//   xbits [C][T], sbits [H][T]  64-bit batch masks of the binary input and hidden spikes
 // Weights stay in the caller's CSR order (rows = presynaptic neuron, sorted targets);
 // the forward current is a gather over the transposed index (per target, sources in
 // ascending order, input projection first), the adjoint's dL/ds a gather over the
 // forward rows, and every weight gradient has exactly one owner.
-#include <rocblas/rocblas.h>
-
 #include <algorithm>
 
 #include "device_math.h"
@@ -102,6 +101,35 @@ __device__ __forceinline__ float ordered_gather_sum(float acc, uint64_t e0, uint
   return acc;
 }
 
+// The same ordered sum for the per-step kernels, where one wavefront per neuron is all
+// the parallelism a step has and each memory round trip is on the critical path: the
+// edges are taken kWide at a time, their sources and weights read by the lanes (two
+// edges per lane), and all kWide presynaptic values requested before the first term is
+// added.  The terms are added one at a time in edge order, exactly as above.
+constexpr int kWide = 128;
+__device__ __forceinline__ float ordered_gather_wide(float acc, uint64_t e0, uint64_t e1, const int32_t *src,
+                                                     const float *w, const float *val, uint32_t b) {
+  for (uint64_t e = e0; e < e1; e += kWide) {
+    const uint32_t n = (uint32_t)min((uint64_t)kWide, e1 - e);  // wave-uniform
+    const int32_t s0 = b < n ? src[e + b] : 0, s1 = b + 64 < n ? src[e + 64 + b] : 0;
+    const float w0 = b < n ? w[e + b] : 0.0f, w1 = b + 64 < n ? w[e + 64 + b] : 0.0f;
+    float xv[kWide];
+#pragma unroll
+    for (int k = 0; k < kWide; ++k) {
+      const int32_t sk = __builtin_amdgcn_readlane(k < 64 ? s0 : s1, k & 63);
+      xv[k] = (uint32_t)k < n ? val[(size_t)sk * 64 + b] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kWide; ++k) {
+      if ((uint32_t)k < n) {
+        const float wk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(k < 64 ? w0 : w1), k & 63));
+        acc = acc + wk * xv[k];
+      }
+    }
+  }
+  return acc;
+}
+
 // Input-projection current of every step: iin[t][j][b] = sum over j's input in-edges,
 // sources ascending, from 0 -- the first part of the hidden current in its defined order.
 // It does not depend on the recurrent state, so all steps run in parallel (a wavefront
@@ -126,7 +154,7 @@ __global__ __launch_bounds__(256) void k_hidden_step(BpttArgs a, uint32_t t, con
   if (j >= a.H) return;
   const uint32_t b = lane_id();
   float acc = a.iin[((size_t)t * a.H + j) * 64 + b];
-  if (sprev) acc = ordered_gather_sum(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t, sprev, b);
+  if (sprev) acc = ordered_gather_wide(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t, sprev, b);
   const float vp = vprev ? vprev[(size_t)j * 64 + b] : 0.0f;
   const float sp = sprev ? sprev[(size_t)j * 64 + b] : 0.0f;
   float v = a.beta * vp;
@@ -224,7 +252,7 @@ __global__ void k_lam_u(BpttArgs a, const float *g_loss) {
 }
 
 // Membrane adjoint of step t: one wavefront per hidden neuron i, lane = batch.
-// lam_next = lamV_{t+1} ([H][64], zeros past the end), v_t = V_t, lam_out = lamV_t.
+// lam_next = lamV_{t+1} ([H][64], zeros for step T), v_t = V_t, lam_out = lamV_t.
 __global__ __launch_bounds__(256) void k_adjoint_step(BpttArgs a, uint32_t t, const float *v_t,
                                                       const float *lam_next, float *lam_out) {
   const uint32_t i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
@@ -233,42 +261,114 @@ __global__ __launch_bounds__(256) void k_adjoint_step(BpttArgs a, uint32_t t, co
   const float *lu = a.lamu + (size_t)t * a.O * 64 + b;
   float ds = 0.0f;
   for (uint32_t o = 0; o < a.O; ++o) ds = ds + a.w_out[(size_t)i * a.O + o] * lu[(size_t)o * 64];
-  ds = ordered_gather_sum(ds, a.rec_ptr[i], a.rec_ptr[i + 1], a.rec_col, a.w_rec, lam_next, b);
+  ds = ordered_gather_wide(ds, a.rec_ptr[i], a.rec_ptr[i + 1], a.rec_col, a.w_rec, lam_next, b);
   const float ln = lam_next[(size_t)i * 64 + b];
   if (!a.detach_reset) ds = ds - a.theta * ln;
   const float z = v_t[(size_t)i * 64 + b] - a.theta;
   lam_out[(size_t)i * 64 + b] = a.beta * ln + surrogate(z, a.slope, a.smooth != 0) * ds;
 }
 
-// Gradients of the sparse weights are masked dense contractions over (t, b):
-//   dW_in[c][j]  = sum_{t,b} x_t[c][b] lamV_t[j][b]
-//   dW_rec[i][j] = sum_{t,b} s_{t-1}[i][b] lamV_t[j][b]
-// Each checkpoint segment lays its trajectories out as [row][(t, b)] matrices and adds
-// its contribution with one FP32 GEMM per projection (rocBLAS, accumulating over the
-// segments); the entries on the masks are then gathered into the CSR-ordered gradients.
-//
-// seg[r][k * 64 + b] = src[t0 + k - shift][r][b] (zero before step 0), k < len, for a
-// [T][rows][64] trajectory; row stride kcols.
-__global__ void k_seg_rows(const float *src, float *seg, uint32_t rows, uint32_t t0, uint32_t len,
-                           uint32_t kcols, uint32_t shift) {
-  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (uint64_t)rows * len * 64) return;
-  const uint32_t b = (uint32_t)(idx & 63u);
-  const uint64_t rk = idx >> 6;
-  const uint32_t k = (uint32_t)(rk % len), r = (uint32_t)(rk / len);
-  const int64_t t = (int64_t)t0 + k - shift;
-  seg[(size_t)r * kcols + (size_t)k * 64 + b] = t >= 0 ? src[((size_t)t * rows + r) * 64 + b] : 0.0f;
+// Batch masks of a [T][rows][64] trajectory: bits[r][t] bit b = (val[t][r][b] != 0) for
+// b < B; flag receives 1 if any of those values is neither 0 nor 1 (the masks then do
+// not represent the values and the gradients take the general path).  A wavefront per
+// (t, r).
+__global__ __launch_bounds__(256) void k_bits(const float *val, uint32_t rows, uint32_t T, uint32_t B,
+                                              uint64_t *bits, uint32_t *flag) {
+  const uint64_t w = (uint64_t)blockIdx.x * 4 + threadIdx.x / kWave;
+  if (w >= (uint64_t)T * rows) return;
+  const uint32_t t = (uint32_t)(w / rows), r = (uint32_t)(w % rows), b = lane_id();
+  const float x = val[w * 64 + b];
+  const bool on = b < B && x != 0.0f;
+  const uint64_t m = __ballot(on);
+  const uint64_t bad = __ballot(on && x != 1.0f);
+  if (b == 0) {
+    bits[(size_t)r * T + t] = m;
+    if (bad) atomicOr(flag, 1u);
+  }
 }
 
-// g[edge] = dense[src][j] for every in-edge (src -> j) of the transposed index; a
-// wavefront per target j.
-__global__ __launch_bounds__(256) void k_mask_gather(const uint64_t *t_ptr, const int32_t *t_src,
-                                                     const uint32_t *t_edge, const float *dense, uint32_t cols,
-                                                     uint32_t n_targets, float *g) {
-  const uint32_t j = blockIdx.x * 4 + threadIdx.x / kWave;
-  if (j >= n_targets) return;
-  for (uint64_t e = t_ptr[j] + lane_id(); e < t_ptr[j + 1]; e += kWave)
-    g[t_edge[e]] = dense[(size_t)t_src[e] * cols + j];
+constexpr int kGradBlock = 256;
+constexpr uint32_t kGradChunk = 128;  // steps of lamV staged in LDS at a time (32 KB)
+constexpr int kMaskAhead = 8;         // mask words in flight per lane
+
+// Gradients of the sparse weights, one owner per synapse: the adjoint of the current
+// I_t = W_in^T x_t + W_rec^T s_{t-1} gives
+//   g_in[c -> j]  = sum_t sum_b x_t[c][b] lamV_t[j][b]
+//   g_rec[i -> j] = sum_t sum_b s_{t-1}[i][b] lamV_t[j][b].
+// One workgroup per target j stages lamV_t[j][.] in LDS, kGradChunk steps at a time; each
+// lane owns one in-edge of j (input projection first, then recurrent, each in ascending
+// source order), kGradBlock edges per pass.  With binary presynaptic values (the masks'
+// flag clear) the lane walks the set bits of its source's batch mask of every step and
+// adds the matching lamV entries in ascending b, summing each step before adding it to
+// the edge's total; otherwise it multiplies the stored values in.  The mask words of the
+// next kMaskAhead steps are loaded while the current ones are used.
+__global__ __launch_bounds__(kGradBlock) void k_grad_edges(BpttArgs a, const uint64_t *xbits,
+                                                           const uint64_t *sbits, const uint32_t *flags) {
+  extern __shared__ float lam_s[];  // [kGradChunk][64]
+  const uint32_t j = blockIdx.x;
+  const uint64_t in0 = a.in_t_ptr[j], rec0 = a.rec_t_ptr[j];
+  const uint32_t n_in = (uint32_t)(a.in_t_ptr[j + 1] - in0), n_rec = (uint32_t)(a.rec_t_ptr[j + 1] - rec0);
+  const uint32_t deg = n_in + n_rec, T = a.T;
+  const bool x_bits = flags[0] == 0, s_bits = !a.smooth && flags[1] == 0;
+  for (uint32_t base = 0; base < deg; base += kGradBlock) {
+    const uint32_t k = base + threadIdx.x;
+    const bool live = k < deg, is_in = k < n_in;
+    uint32_t src = 0, edge = 0;
+    if (live) {
+      src = (uint32_t)(is_in ? a.in_t_src[in0 + k] : a.rec_t_src[rec0 + (k - n_in)]);
+      edge = is_in ? a.in_t_edge[in0 + k] : a.rec_t_edge[rec0 + (k - n_in)];
+    }
+    const bool use_bits = is_in ? x_bits : s_bits;
+    // the lane's mask row: the input's step t, or the hidden neuron's step t - 1
+    const uint64_t *row = is_in ? xbits + (size_t)src * T : sbits + (size_t)src * T;
+    const uint32_t lag = is_in ? 0u : 1u;
+    auto mask_at = [&](uint32_t t) -> uint64_t {
+      return (live && use_bits && t >= lag && t - lag < T) ? row[t - lag] : 0ull;
+    };
+    float total = 0.0f;
+    for (uint32_t tc = 0; tc < T; tc += kGradChunk) {
+      const uint32_t len = min(kGradChunk, T - tc);
+      __syncthreads();  // the previous chunk has been read by every lane
+      for (uint32_t x = threadIdx.x; x < len * 64; x += kGradBlock)
+        lam_s[x] = a.lamv[((size_t)(tc + x / 64) * a.H + j) * 64 + (x & 63u)];
+      __syncthreads();
+      if (!live) continue;
+      if (use_bits) {
+        uint64_t cur[kMaskAhead], nxt[kMaskAhead];
+#pragma unroll
+        for (int q = 0; q < kMaskAhead; ++q) cur[q] = mask_at(tc + q);
+        for (uint32_t u0 = 0; u0 < len; u0 += kMaskAhead) {
+#pragma unroll
+          for (int q = 0; q < kMaskAhead; ++q) nxt[q] = u0 + kMaskAhead + q < len ? mask_at(tc + u0 + kMaskAhead + q) : 0ull;
+#pragma unroll
+          for (int q = 0; q < kMaskAhead; ++q) {
+            if (u0 + q >= len) break;
+            uint64_t m = cur[q];
+            const float *lt = lam_s + (size_t)(u0 + q) * 64;
+            float part = 0.0f;
+            while (m) {
+              part += lt[__builtin_ctzll(m)];
+              m &= m - 1;
+            }
+            total += part;
+          }
+#pragma unroll
+          for (int q = 0; q < kMaskAhead; ++q) cur[q] = nxt[q];
+        }
+      } else {
+        for (uint32_t u = 0; u < len; ++u) {
+          const uint32_t t = tc + u;
+          if (t < lag) continue;
+          const float *val = is_in ? a.xt + ((size_t)t * a.C + src) * 64 : a.s + ((size_t)(t - 1) * a.H + src) * 64;
+          const float *lt = lam_s + (size_t)u * 64;
+          float part = 0.0f;
+          for (uint32_t b = 0; b < a.B; ++b) part += val[b] * lt[b];
+          total += part;
+        }
+      }
+    }
+    if (live) (is_in ? a.g_w_in : a.g_w_rec)[edge] = total;
+  }
 }
 
 // Gradient of the dense readout weights over the whole sequence: one wavefront per
@@ -309,81 +409,94 @@ static void gather_weights(const BpttArgs &a, hipStream_t s) {
                        a.w_rec_t, a.nnz_rec);
 }
 
-hipError_t bptt_forward(const BpttArgs &a, const float *x, const int32_t *labels, float *loss,
-                        hipStream_t s) {
+// The forward and backward passes each run as three parts.  The prologue and epilogue
+// read or write the caller's arrays (inputs, weights, labels, loss, gradients); the body
+// in between touches only the plan's own buffers (its weight copies included), so the
+// runtime can capture it once per plan in a HIP graph and replay it on every call.
+
+hipError_t bptt_forward_prologue(const BpttArgs &a, const float *x, hipStream_t s) {
   gather_weights(a, s);
   hipLaunchKernelGGL(k_transpose_x, dim3(blocks_for((uint64_t)a.T * a.C * 64, 256)), dim3(256), 0, s, x,
                      a.xt, a.B, a.T, a.C);
-  hipLaunchKernelGGL(k_input_current, dim3(blocks_for((uint64_t)a.T * a.H, 4)), dim3(256), 0, s, a);
-  const dim3 grid(blocks_for(a.H, 4));
+  const hipError_t e = hipMemcpyAsync(a.w_out_c, a.w_out, (size_t)a.H * a.O * 4, hipMemcpyDeviceToDevice, s);
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+// g: the plan's arguments with w_out = w_out_c
+hipError_t bptt_forward_body(const BpttArgs &g, hipStream_t s) {
+  hipLaunchKernelGGL(k_input_current, dim3(blocks_for((uint64_t)g.T * g.H, 4)), dim3(256), 0, s, g);
+  const dim3 grid(blocks_for(g.H, 4));
   float *vprev = nullptr;
-  for (uint32_t t = 0; t < a.T; ++t) {
+  for (uint32_t t = 0; t < g.T; ++t) {
     // V of the step before each checkpoint segment is kept; the others rotate
-    float *v_out = (t % a.K == a.K - 1 || t == a.T - 1) ? a.vck + (size_t)(t / a.K) * a.H * 64
-                                                          : a.vtmp + (size_t)(t & 1u) * a.H * 64;
-    const float *sprev = t ? a.s + (size_t)(t - 1) * a.H * 64 : nullptr;
-    hipLaunchKernelGGL(k_hidden_step, grid, dim3(256), 0, s, a, t, vprev, sprev, v_out,
-                       a.s + (size_t)t * a.H * 64);
+    float *v_out = (t % g.K == g.K - 1 || t == g.T - 1) ? g.vck + (size_t)(t / g.K) * g.H * 64
+                                                          : g.vtmp + (size_t)(t & 1u) * g.H * 64;
+    const float *sprev = t ? g.s + (size_t)(t - 1) * g.H * 64 : nullptr;
+    hipLaunchKernelGGL(k_hidden_step, grid, dim3(256), 0, s, g, t, vprev, sprev, v_out,
+                       g.s + (size_t)t * g.H * 64);
     vprev = v_out;
   }
-  hipLaunchKernelGGL(k_readout_drive, dim3(blocks_for((uint64_t)a.T * a.O * 64, 256)), dim3(256), 0, s, a,
-                     a.ro);
-  hipLaunchKernelGGL(k_readout_scan, dim3(a.O), dim3(64), 0, s, a, a.ro);
+  hipLaunchKernelGGL(k_readout_drive, dim3(blocks_for((uint64_t)g.T * g.O * 64, 256)), dim3(256), 0, s, g,
+                     g.ro);
+  hipLaunchKernelGGL(k_readout_scan, dim3(g.O), dim3(64), 0, s, g, g.ro);
+  return hipGetLastError();
+}
+
+hipError_t bptt_forward_epilogue(const BpttArgs &a, const int32_t *labels, float *loss, hipStream_t s) {
   hipLaunchKernelGGL(k_loss, dim3(1), dim3(64), 0, s, a, labels, loss);
   return hipGetLastError();
 }
 
-hipError_t bptt_backward(const BpttArgs &a, const float *g_loss, rocblas_handle blas, hipStream_t s) {
-  if (rocblas_set_stream(blas, s) != rocblas_status_success) return hipErrorUnknown;
+hipError_t bptt_backward_prologue(const BpttArgs &a, const float *g_loss, hipStream_t s) {
   gather_weights(a, s);
-  hipLaunchKernelGGL(k_fill, dim3(blocks_for((uint64_t)a.H * 64, 256)), dim3(256), 0, s, a.lam_carry,
-                     (uint64_t)a.H * 64, 0.0f);
+  hipError_t e = hipMemcpyAsync(a.w_out_c, a.w_out, (size_t)a.H * a.O * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && a.nnz_rec)
+    e = hipMemcpyAsync(a.w_rec_c, a.w_rec, (size_t)a.nnz_rec * 4, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_lam_u, dim3(a.O), dim3(64), 0, s, a, g_loss);
-  hipLaunchKernelGGL(k_grad_out, dim3(blocks_for((uint64_t)a.H * a.O, 4)), dim3(256), 0, s, a);
-  const dim3 grid(blocks_for(a.H, 4));
-  const uint32_t n_seg = (a.T + a.K - 1) / a.K;
-  for (int32_t g = (int32_t)n_seg - 1; g >= 0; --g) {
-    const uint32_t t0 = (uint32_t)g * a.K, len = std::min(a.K, a.T - t0);
+  return hipGetLastError();
+}
+
+// g: the plan's arguments with w_out = w_out_c and w_rec = w_rec_c
+hipError_t bptt_backward_body(const BpttArgs &g, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for((uint64_t)g.H * 64, 256)), dim3(256), 0, s, g.lam_carry,
+                     (uint64_t)g.H * 64, 0.0f);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, reinterpret_cast<float *>(g.flags), (uint64_t)2, 0.0f);
+  // batch masks of the binary trajectories, for the sparse-weight gradients
+  hipLaunchKernelGGL(k_bits, dim3(blocks_for((uint64_t)g.T * g.C, 4)), dim3(256), 0, s, g.xt, g.C, g.T, g.B,
+                     g.xbits, g.flags);
+  hipLaunchKernelGGL(k_bits, dim3(blocks_for((uint64_t)g.T * g.H, 4)), dim3(256), 0, s, g.s, g.H, g.T, g.B,
+                     g.sbits, g.flags + 1);
+  const dim3 grid(blocks_for(g.H, 4));
+  const uint32_t n_seg = (g.T + g.K - 1) / g.K;
+  for (int32_t seg = (int32_t)n_seg - 1; seg >= 0; --seg) {
+    const uint32_t t0 = (uint32_t)seg * g.K, len = std::min(g.K, g.T - t0);
     // recompute the segment's membranes from the checkpoint before it and the stored
     // spikes (the same kernel and operations as the forward pass)
-    const float *vprev = g ? a.vck + (size_t)(g - 1) * a.H * 64 : nullptr;
+    const float *vprev = seg ? g.vck + (size_t)(seg - 1) * g.H * 64 : nullptr;
     for (uint32_t k = 0; k < len; ++k) {
       const uint32_t t = t0 + k;
-      float *v_out = a.vseg + (size_t)k * a.H * 64;
-      const float *sprev = t ? a.s + (size_t)(t - 1) * a.H * 64 : nullptr;
-      hipLaunchKernelGGL(k_hidden_step, grid, dim3(256), 0, s, a, t, vprev, sprev, v_out, (float *)nullptr);
+      float *v_out = g.vseg + (size_t)k * g.H * 64;
+      const float *sprev = t ? g.s + (size_t)(t - 1) * g.H * 64 : nullptr;
+      hipLaunchKernelGGL(k_hidden_step, grid, dim3(256), 0, s, g, t, vprev, sprev, v_out, (float *)nullptr);
       vprev = v_out;
     }
     for (int32_t k = (int32_t)len - 1; k >= 0; --k) {
-      const float *lam_next = k + 1 < (int32_t)len ? a.lamv + (size_t)(k + 1) * a.H * 64 : a.lam_carry;
-      hipLaunchKernelGGL(k_adjoint_step, grid, dim3(256), 0, s, a, t0 + (uint32_t)k,
-                         a.vseg + (size_t)k * a.H * 64, lam_next, a.lamv + (size_t)k * a.H * 64);
+      const uint32_t t = t0 + (uint32_t)k;
+      const float *lam_next = t + 1 < g.T ? g.lamv + (size_t)(t + 1) * g.H * 64 : g.lam_carry;
+      hipLaunchKernelGGL(k_adjoint_step, grid, dim3(256), 0, s, g, t, g.vseg + (size_t)k * g.H * 64, lam_next,
+                         g.lamv + (size_t)t * g.H * 64);
     }
-    // this segment's share of the sparse-weight gradients (two GEMMs over k = (t, b))
-    const uint32_t kcols = a.K * 64, kk = len * 64;
-    hipLaunchKernelGGL(k_seg_rows, dim3(blocks_for((uint64_t)a.H * len * 64, 256)), dim3(256), 0, s, a.lamv,
-                       a.lseg, a.H, 0u, len, kcols, 0u);
-    hipLaunchKernelGGL(k_seg_rows, dim3(blocks_for((uint64_t)a.C * len * 64, 256)), dim3(256), 0, s, a.xt,
-                       a.xseg, a.C, t0, len, kcols, 0u);
-    hipLaunchKernelGGL(k_seg_rows, dim3(blocks_for((uint64_t)a.H * len * 64, 256)), dim3(256), 0, s, a.s,
-                       a.sseg, a.H, t0, len, kcols, 1u);
-    const float one = 1.0f, beta = (uint32_t)g == n_seg - 1 ? 0.0f : 1.0f;
-    rocblas_status bs = rocblas_sgemm(blas, rocblas_operation_transpose, rocblas_operation_none, (int)a.H,
-                                      (int)a.C, (int)kk, &one, a.lseg, (int)kcols, a.xseg, (int)kcols, &beta,
-                                      a.dw_in, (int)a.H);
-    if (bs == rocblas_status_success)
-      bs = rocblas_sgemm(blas, rocblas_operation_transpose, rocblas_operation_none, (int)a.H, (int)a.H,
-                         (int)kk, &one, a.lseg, (int)kcols, a.sseg, (int)kcols, &beta, a.dw_rec, (int)a.H);
-    if (bs != rocblas_status_success) return hipErrorUnknown;
-    // lamV of the segment's first step is the next (earlier) segment's lamV_{t+1}
-    (void)hipMemcpyAsync(a.lam_carry, a.lamv, (size_t)a.H * 64 * 4, hipMemcpyDeviceToDevice, s);
   }
-  if (a.nnz_in)
-    hipLaunchKernelGGL(k_mask_gather, grid, dim3(256), 0, s, a.in_t_ptr, a.in_t_src, a.in_t_edge, a.dw_in, a.H,
-                       a.H, a.g_w_in);
-  if (a.nnz_rec)
-    hipLaunchKernelGGL(k_mask_gather, grid, dim3(256), 0, s, a.rec_t_ptr, a.rec_t_src, a.rec_t_edge, a.dw_rec,
-                       a.H, a.H, a.g_w_rec);
+  return hipGetLastError();
+}
+
+// the gradients, written to the caller's arrays
+hipError_t bptt_backward_epilogue(const BpttArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_out, dim3(blocks_for((uint64_t)a.H * a.O, 4)), dim3(256), 0, s, a);
+  if (a.nnz_in + a.nnz_rec)
+    hipLaunchKernelGGL(k_grad_edges, dim3(a.H), dim3(kGradBlock), (size_t)std::min(kGradChunk, a.T) * 64 * 4, s, a,
+                       a.xbits, a.sbits, a.flags);
   return hipGetLastError();
 }
 

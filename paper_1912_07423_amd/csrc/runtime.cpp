@@ -2,7 +2,6 @@
 // constants, device allocation, on-device network construction, the window schedule
 // of the step pipeline, HIP graph replay, profiling and state/raster readback.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -1279,7 +1278,7 @@ struct snn_bptt {
   snn_network pool;          // holds the plan's allocations and default stream
   snn::BpttArgs args{};
   uint64_t forwards = 0;     // forward passes run (the backward uses the latest)
-  rocblas_handle blas = nullptr;  // the GEMMs of the sparse-weight gradients
+  hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;  // captured bodies of the two passes
 };
 
 namespace {
@@ -1366,14 +1365,13 @@ void build_bptt(snn_bptt *p, const uint64_t *in_ptr, const int32_t *in_col, cons
   a.rec_ptr = upload(pool, std::vector<uint64_t>(rec_ptr, rec_ptr + d.n_hidden + 1));
   a.rec_col = upload(pool, std::vector<int32_t>(rec_col, rec_col + nnz_rec));
   const size_t HB = (size_t)a.H * 64, n_seg = (a.T + a.K - 1) / a.K;
-  a.xseg = dev_array<float>(pool, (size_t)a.C * a.K * 64);
-  a.sseg = dev_array<float>(pool, (size_t)a.H * a.K * 64);
-  a.lseg = dev_array<float>(pool, (size_t)a.H * a.K * 64);
-  a.dw_in = dev_array<float>(pool, (size_t)a.C * a.H);
-  a.dw_rec = dev_array<float>(pool, (size_t)a.H * a.H);
-  if (rocblas_create_handle(&p->blas) != rocblas_status_success) fail(SNN_E_HIP, "rocblas_create_handle failed");
+  a.xbits = dev_array<uint64_t>(pool, (size_t)a.C * a.T);
+  a.sbits = dev_array<uint64_t>(pool, (size_t)a.H * a.T);
+  a.flags = dev_array<uint32_t>(pool, 2);
   a.w_in_t = dev_array<float>(pool, std::max<uint64_t>(1, nnz_in));
   a.w_rec_t = dev_array<float>(pool, std::max<uint64_t>(1, nnz_rec));
+  a.w_rec_c = dev_array<float>(pool, std::max<uint64_t>(1, nnz_rec));
+  a.w_out_c = dev_array<float>(pool, (size_t)a.H * a.O);
   a.xt = dev_array<float>(pool, (size_t)a.T * a.C * 64);
   a.iin = dev_array<float>(pool, (size_t)a.T * HB);
   a.s = dev_array<float>(pool, (size_t)a.T * HB);
@@ -1382,12 +1380,42 @@ void build_bptt(snn_bptt *p, const uint64_t *in_ptr, const int32_t *in_col, cons
   a.vseg = dev_array<float>(pool, (size_t)a.K * HB);
   a.ro = dev_array<float>(pool, (size_t)a.T * a.O * 64);
   a.lamu = dev_array<float>(pool, (size_t)a.T * a.O * 64);
-  a.lamv = dev_array<float>(pool, (size_t)a.K * HB);
+  a.lamv = dev_array<float>(pool, (size_t)a.T * HB);
   a.lam_carry = dev_array<float>(pool, HB);
   a.m = dev_array<float>(pool, (size_t)a.B * a.O);
   a.dm = dev_array<float>(pool, (size_t)a.B * a.O);
   a.tmax = dev_array<int32_t>(pool, (size_t)a.B * a.O);
   check(hipStreamSynchronize(pool->stream), "sync after plan");
+}
+
+// Runs a pass's body: from its HIP graph (captured on the first call, on the call's
+// stream), or launched kernel by kernel when the plan is eager.
+template <typename F>
+void bptt_body(snn_bptt *p, hipGraphExec_t &exec, hipStream_t s, F &&body) {
+  if (p->desc.eager) {
+    check(body(s), "bptt launch");
+    return;
+  }
+  if (!exec) {
+    hipGraph_t g = nullptr;
+    check(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "begin capture");
+    const hipError_t e = body(s);
+    const hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      check(e != hipSuccess ? e : e2, "bptt capture");
+    }
+    const hipError_t e3 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    check(e3, "bptt graph instantiate");
+  }
+  check(hipGraphLaunch(exec, s), "bptt graph launch");
+}
+
+void bptt_release_graphs(snn_bptt *p) {
+  if (p->g_fwd) (void)hipGraphExecDestroy(p->g_fwd);
+  if (p->g_bwd) (void)hipGraphExecDestroy(p->g_bwd);
+  p->g_fwd = p->g_bwd = nullptr;
 }
 
 }  // namespace
@@ -1842,7 +1870,6 @@ snn_status snn_bptt_create(const snn_bptt_desc *desc, const uint64_t *in_row_ptr
       }
       build_bptt(p, in_row_ptr, in_col, rec_row_ptr, rec_col);
     } catch (...) {
-      if (p->blas) (void)rocblas_destroy_handle(p->blas);
       release(&p->pool);
       delete p;
       throw;
@@ -1861,7 +1888,11 @@ snn_status snn_bptt_forward(snn_bptt *p, const float *x, const float *w_in, cons
     a.w_rec = w_rec;
     a.w_out = w_out;
     hipStream_t s = stream ? (hipStream_t)stream : p->pool.stream;
-    check(snn::bptt_forward(a, x, labels, loss, s), "bptt forward");
+    check(snn::bptt_forward_prologue(a, x, s), "bptt forward");
+    snn::BpttArgs g = p->args;  // the body reads the plan's buffers only
+    g.w_out = g.w_out_c;
+    bptt_body(p, p->g_fwd, s, [&](hipStream_t st) { return snn::bptt_forward_body(g, st); });
+    check(snn::bptt_forward_epilogue(a, labels, loss, s), "bptt forward");
     p->forwards++;
   });
 }
@@ -1882,7 +1913,12 @@ snn_status snn_bptt_backward(snn_bptt *p, const float *w_in, const float *w_rec,
     a.g_w_rec = g_w_rec;
     a.g_w_out = g_w_out;
     hipStream_t s = stream ? (hipStream_t)stream : p->pool.stream;
-    check(snn::bptt_backward(a, g_loss, p->blas, s), "bptt backward");
+    check(snn::bptt_backward_prologue(a, g_loss, s), "bptt backward");
+    snn::BpttArgs g = p->args;
+    g.w_out = g.w_out_c;
+    g.w_rec = g.w_rec_c;
+    bptt_body(p, p->g_bwd, s, [&](hipStream_t st) { return snn::bptt_backward_body(g, st); });
+    check(snn::bptt_backward_epilogue(a, s), "bptt backward");
   });
 }
 
@@ -1905,7 +1941,7 @@ snn_status snn_bptt_get_trace(snn_bptt *p, float *spikes, float *v_checkpoints, 
 void snn_bptt_destroy(snn_bptt *p) {
   if (!p) return;
   if (p->pool.stream) (void)hipStreamSynchronize(p->pool.stream);
-  if (p->blas) (void)rocblas_destroy_handle(p->blas);
+  bptt_release_graphs(p);
   release(&p->pool);
   delete p;
 }

@@ -171,16 +171,23 @@ struct BpttArgs {
   const float *w_in, *w_rec, *w_out;  // caller's weights: CSR order, CSR order, [H][O]
   float *g_w_in, *g_w_rec, *g_w_out;
   float *w_in_t, *w_rec_t;     // weights gathered into transposed (per-target) order
+  float *w_out_c, *w_rec_c;    // the plan's copies of w_out and of w_rec in CSR order
   float *iin;                  // [T][H][64] input-projection current of every step
-  float *xseg, *sseg, *lseg;   // one segment as [row][(t, b)] matrices (row stride K * 64)
-  float *dw_in, *dw_rec;       // dense gradient accumulators [C][H], [H][H]
+  uint64_t *xbits, *sbits;     // batch masks of the input and hidden spikes: [C][T], [H][T]
+  uint32_t *flags;             // [2]: a value of x / s is neither 0 nor 1 (masks not used)
   float *xt, *s, *vck, *vtmp, *vseg, *ro, *lamu, *lamv, *lam_carry, *m, *dm;
   int32_t *tmax;
 };
-hipError_t bptt_forward(const BpttArgs &a, const float *x, const int32_t *labels, float *loss,
-                        hipStream_t s);
-typedef struct _rocblas_handle *rocblas_handle_t;
-hipError_t bptt_backward(const BpttArgs &a, const float *g_loss, rocblas_handle_t blas, hipStream_t s);
+// Forward and backward passes in three parts each: prologue and epilogue touch the
+// caller's arrays, the body only the plan's buffers (capturable once per plan).  The body
+// takes the plan's arguments with w_out (and, backward, w_rec) pointing at the plan's
+// copies w_out_c / w_rec_c, which the prologue fills.
+hipError_t bptt_forward_prologue(const BpttArgs &a, const float *x, hipStream_t s);
+hipError_t bptt_forward_body(const BpttArgs &g, hipStream_t s);
+hipError_t bptt_forward_epilogue(const BpttArgs &a, const int32_t *labels, float *loss, hipStream_t s);
+hipError_t bptt_backward_prologue(const BpttArgs &a, const float *g_loss, hipStream_t s);
+hipError_t bptt_backward_body(const BpttArgs &g, hipStream_t s);
+hipError_t bptt_backward_epilogue(const BpttArgs &a, hipStream_t s);
 
 // Optional timing events of one launch.  When set, the kernel is launched with
 // hipExtLaunchKernel, which stamps `start` and `stop` with the dispatch's own begin and

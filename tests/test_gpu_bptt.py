@@ -4,10 +4,10 @@ through the C ABI and the torch.autograd.Function) against the oracle:
   * forward: the oracle's float32 forward sums every current in the kernel's order, so
     spikes, membrane checkpoints, readout maxima and their steps must be bit-identical;
     the loss (float32 on the GPU, float64 in the oracle) within 1e-5 relative;
-  * backward: the oracle's float64 adjoint on the same trajectory; every gradient within
-    1e-4 of the largest gradient entry of its matrix (the 1e-4 relative bar), for the
-    spiking mode and the smooth mode (whose oracle adjoint is pinned to finite
-    differences), on ragged checkpoint segments and a batch below one wavefront;
+  * backward: the oracle's float64 adjoint on the same trajectory; every gradient entry
+    within 1e-4 relative, with an absolute floor of 1e-6 of the largest entry of its
+    matrix, for the spiking mode and the smooth mode (whose oracle adjoint is pinned to
+    finite differences), on ragged checkpoint segments and a batch below one wavefront;
   * autograd: loss.backward() through the Function equals the plan's backward, scaled
     by the incoming gradient;
   * the full recurrent workload (64 x 250 steps, 700 inputs, 1,024 hidden, 20 readouts).
@@ -22,19 +22,22 @@ from paper_1912_07423_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+RTOL = 1e-4    # elementwise relative bar of the gradients
+FLOOR = 1e-6   # absolute floor, as a fraction of the matrix's largest entry
+
 
 @pytest.fixture(scope="module", autouse=True)
 def _gpu(gpu_available):
     return gpu_available
 
 
-def _run(d, checkpoint, smooth=False, g_scale=None):
+def _run(d, checkpoint, smooth=False, g_scale=None, eager=False):
     import torch
     from paper_1912_07423_amd.bptt import RecurrentLIF
     B, T, C = d["x"].shape
     H, O = d["w_out"].shape
     plan = RecurrentLIF(d["mask_in"], d["mask_rec"], O, B, T, checkpoint=checkpoint,
-                        dt_ms=d["dt_ms"], smooth=smooth)
+                        dt_ms=d["dt_ms"], smooth=smooth, eager=eager)
     v_in, v_rec = plan.csr_values(d["w_in"], d["w_rec"])
     dev = plan.device
     x = torch.tensor(d["x"], device=dev)
@@ -78,9 +81,15 @@ def _compare(d, checkpoint, smooth=False):
         if scale == 0:            # e.g. recurrent weights of a one-step sequence
             assert not np.any(got), name
             continue
-        err = np.abs(got - ref).max()
-        print(f"[bptt] d{name}: max |err| / max |ref| = {err / scale:.2e}", flush=True)
-        assert err <= 1e-4 * scale, (name, err, scale)
+        # elementwise: |got - ref| <= 1e-4 |ref| + a floor of 1e-6 of the matrix's largest
+        # entry (float32 sums of up to B T terms cancel in the smallest entries)
+        err = np.abs(got - ref)
+        bound = RTOL * np.abs(ref) + FLOOR * scale
+        worst = np.unravel_index(np.argmax(err / bound), err.shape)
+        rel = err / np.maximum(np.abs(ref), FLOOR * scale)
+        print(f"[bptt] d{name}: max elementwise |err| / (|ref| or the floor) = {rel.max():.2e}, "
+              f"max |err| / max |ref| = {err.max() / scale:.2e}", flush=True)
+        assert np.all(err <= bound), (name, worst, got[worst], ref[worst])
     return plan, fw
 
 
@@ -110,8 +119,42 @@ def test_autograd_scales_with_incoming_gradient():
     _, _, g1 = _run(d, 10)
     _, _, g3 = _run(d, 10, g_scale=3.0)
     for a, b in zip(g1, g3):
-        # the incoming 3 enters at dL/dmax, so the roundings differ from 3 x (gradient)
-        assert np.abs(b - 3.0 * a).max() <= 1e-5 * np.abs(3.0 * a).max()
+        # the incoming 3 enters at dL/dmax, so the roundings differ from 3 x (gradient):
+        # elementwise 1e-5 relative with the floor of the oracle comparison
+        ref = 3.0 * a
+        assert np.all(np.abs(b - ref) <= 1e-5 * np.abs(ref) + FLOOR * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("smooth", [False, True])
+def test_graph_replays_equal_eager_launches(smooth):
+    """The passes' bodies replayed from their HIP graphs give bit-identical losses and
+    gradients to the same kernels launched one by one, on every replay, with other
+    eager work (weight updates, a second plan, host reads) between the replays."""
+    import torch
+    from paper_1912_07423_amd.bptt import RecurrentLIF
+    d = _small(seed=12)
+    B, T, C = d["x"].shape
+    H, O = d["w_out"].shape
+    plans = {e: RecurrentLIF(d["mask_in"], d["mask_rec"], O, B, T, checkpoint=9, dt_ms=d["dt_ms"],
+                             smooth=smooth, eager=e) for e in (True, False)}
+    v_in, v_rec = plans[True].csr_values(d["w_in"], d["w_rec"])
+    dev = plans[True].device
+    x = torch.tensor(d["x"], device=dev)
+    y = torch.tensor(d["labels"].astype(np.int32), device=dev)
+    w0 = [torch.tensor(v_in, device=dev), torch.tensor(v_rec, device=dev), torch.tensor(d["w_out"], device=dev)]
+    for rep in range(4):
+        out = {}
+        for e, plan in plans.items():
+            ws = [w.clone().requires_grad_(True) for w in w0]
+            loss = plan.loss(x, *ws, y)
+            loss.backward()
+            torch.cuda.synchronize()
+            out[e] = [loss.detach().cpu().numpy()] + [w.grad.cpu().numpy() for w in ws]
+        for a, b in zip(out[True], out[False]):
+            assert np.array_equal(np.asarray(a).view(np.uint32), np.asarray(b).view(np.uint32)), f"replay {rep}"
+        # eager work between replays: a small weight change, read back on the host
+        w0 = [w + 1e-3 * torch.sin(w * (rep + 1)) for w in w0]
+        assert np.isfinite(w0[0].cpu().numpy()).all()
 
 
 def test_full_recurrent_workload():
