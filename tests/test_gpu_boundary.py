@@ -99,13 +99,13 @@ def test_spike_download_rejects_ranges_outside_the_ring():
     for t0, t1 in ((150, 140),      # t_end < t_begin
                    (190, 201),      # past the simulated steps
                    (100, 150),      # no longer held by the 64-step ring
-                   (136, 200)):     # one step too old
+                   (135, 200)):     # one step too old: the ring holds [136, 200)
         st, _ = _get_raster(g, t0, t1, len(buf), buf, buf.copy())
         assert st == L.SNN_E_INVALID, (t0, t1)
-    st, n = _get_raster(g, 137, 200, len(buf), buf, buf.copy())
+    st, n = _get_raster(g, 136, 200, len(buf), buf, buf.copy())   # the oldest step held
     assert st == L.SNN_OK
     if n:
-        st, _ = _get_raster(g, 137, 200, len(buf), None, None)
+        st, _ = _get_raster(g, 136, 200, len(buf), None, None)
         assert st == L.SNN_E_INVALID, "NULL outputs while the range holds spikes"
     st, n = _get_raster(g, 137, 137, 0, None, None)
     assert st == L.SNN_OK and n == 0
