@@ -6,12 +6,13 @@ exc./inh.), fixed out-degree 5,000 with uniform random targets (1e9 synapses sto
 int32 targets, with one Q16 weight per source population as in Table I), J = 0.1 mV,
 g = 5, uniform delay 1.5 ms (15 steps), Poisson drive of 1,000 virtual inputs per neuron
 at 20 Hz, dt = 0.1 ms.  Synthetic, generated on the device from a seed.  One "step" is
-one simulation time step of the whole pipeline (update neurons -> FIFO -> receive
-spikes).  Every run first simulates SETTLE_STEPS = 300 steps (30 ms), whatever
-`--warmup` says: the uniform random initial potentials cause a synchronous population
-burst in the first ~10 ms, and the timed steps are meant to measure the network's steady
-state (the paper's runs simulate 10 s).  Then `--warmup` untimed steps, then exactly
-`--steps` timed steps.
+one run of the workload as configured: 1,000 simulation time steps (0.1 s simulated) of
+the whole pipeline (update neurons -> FIFO -> receive spikes), continuing the same
+network.  Every run first simulates SETTLE_STEPS = 300 simulation steps (30 ms): the
+uniform random initial potentials cause a synchronous population burst in the first
+~10 ms, and the timed steps are meant to measure the network's steady state (the
+paper's runs simulate 10 s).  Then `--warmup` untimed bench steps, then exactly
+`--steps` timed bench steps (defaults 1 and 5).
 
 Prints one JSON line: synaptic events/s over the timed steps (inputs resident in HBM,
 network built before the clock starts), wall time per simulated second, the delivery
@@ -63,6 +64,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1912_07423_amd", "csrc", f)
                   for f in ("step.hip", "snn_internal.h", "device_math.h")]
 WORKLOAD = "brunel_fixed_out_200k_k5000_d15_poisson20hz"
 SETTLE_STEPS = 300  # past the start-up burst, always simulated before the warm-up
+SIM_STEPS = 1000    # simulation steps per bench step: one run of the workload as configured
 
 
 def workload_spec():
@@ -169,21 +171,25 @@ def bench_brunel(args):
     build_s = time.perf_counter() - tb
     info = net.info()
     print(f"[bench] built in {build_s:.2f}s: {info}", file=sys.stderr, flush=True)
+    K, Wb = args.steps, args.warmup
+    sim_steps = K * SIM_STEPS
+    # every launch is stamped with its own begin and end (profiling); the warm-up runs the
+    # same way, so the timed run reuses its events
+    net.set_profiling(True)
     net.run(SETTLE_STEPS)
-    net.run(args.warmup)
+    net.run(Wb * SIM_STEPS)
     net.sync()
     W = info["window"]
-    before = launches_for(SETTLE_STEPS, W) + launches_for(args.warmup, W)
-    print(f"[bench] settled {SETTLE_STEPS} + warm-up {args.warmup} steps ({before} delivery launches); "
-          f"timing {args.steps} steps", file=sys.stderr, flush=True)
+    before = launches_for(SETTLE_STEPS, W) + launches_for(Wb * SIM_STEPS, W)
+    print(f"[bench] settled {SETTLE_STEPS} + warm-up {Wb} x {SIM_STEPS} steps ({before} delivery launches); "
+          f"timing {K} x {SIM_STEPS} steps", file=sys.stderr, flush=True)
 
-    i0 = net.info()
-    net.set_profiling(True)
     net.reset_profile()
+    i0 = net.info()
     torch.cuda.synchronize()
     net.sync()
     t0 = time.perf_counter()
-    net.run(args.steps)
+    net.run(sim_steps)
     net.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -193,15 +199,13 @@ def bench_brunel(args):
 
     events = i1["events"] - i0["events"]
     spikes = i1["spikes"] - i0["spikes"]
-    t_begin = SETTLE_STEPS + args.warmup
-    emitted = int(net.raster(t_begin, t_begin + args.steps).sum()) if args.steps <= 4096 else None
     dt_ms = spec["params"]["dt_ms"]
     launches = max(1, prof["deliver_launches"])
     deliver_avg_ms = prof["deliver_ms"] / launches
     b_ev, b_spk = delivery_bytes(info)
     bytes_per_launch = (events * b_ev + spikes * b_spk) / launches
     achieved = bytes_per_launch / (deliver_avg_ms * 1e-3) / 1e9 if deliver_avg_ms > 0 else 0.0
-    print(f"[bench] {args.steps} steps in {wall * 1e3:.3f} ms; {events} events; "
+    print(f"[bench] {sim_steps} steps in {wall * 1e3:.3f} ms; {events} events; "
           f"deliver {deliver_avg_ms * 1e3:.2f} us x {launches}; update "
           f"{prof['update_ms'] / max(1, prof['update_launches']) * 1e3:.2f} us x "
           f"{prof['update_launches']}", file=sys.stderr, flush=True)
@@ -225,19 +229,23 @@ def bench_brunel(args):
                              f"events) on one host thread",
                    "host": host_info()}
     kernel = "k_deliver_tiled" if info["delivery_name"] == "tiled" else "k_deliver_atomic"
-    point = {"workload": WORKLOAD, "settle_steps": SETTLE_STEPS, "warmup": args.warmup,
-             "steps": args.steps, "events": events, "spikes": spikes, "delivery": info["delivery_name"],
-             "tiles": info["tiles"], "window": W, "delivery_launches": prof["deliver_launches"]}
+    point = {"workload": WORKLOAD, "settle_steps": SETTLE_STEPS, "warmup": Wb,
+             "steps": K, "sim_steps_per_step": SIM_STEPS, "events": events, "spikes": spikes,
+             "delivery": info["delivery_name"], "tiles": info["tiles"], "window": W,
+             "delivery_launches": prof["deliver_launches"]}
     traffic = measured_traffic(point) if kernel == "k_deliver_tiled" else None
-    line(METRIC, events / wall, "events/s", args.steps, args.warmup, wall * 1e3 / args.steps, "int32",
+    sim_s = sim_steps * dt_ms * 1e-3
+    line(METRIC, events / wall, "events/s", K, Wb, wall * 1e3 / K, "int32",
          {"workload": WORKLOAD,
           "neurons": info["n"], "synapses": info["nnz"], "delay_steps": info["delay"],
-          "dt_ms": dt_ms, "delivery": info["delivery_name"], "window": W,
+          "dt_ms": dt_ms, "sim_steps_per_step": SIM_STEPS,
+          "step": "one run of the workload as configured: 1,000 simulation steps (0.1 s "
+                  "simulated), continuing the same network",
+          "delivery": info["delivery_name"], "window": W,
           "tiles": info["tiles"], "source_weights": bool(info["source_weights"]),
           "settle_steps": SETTLE_STEPS, "parallelism": "single-gpu"},
-         wall_s_per_sim_s=wall / (args.steps * dt_ms * 1e-3), events=events,
-         spikes_delivered=spikes, spikes_emitted=emitted,
-         rate_hz=(emitted / info["n"] / (args.steps * dt_ms * 1e-3)) if emitted is not None else None,
+         wall_s_per_sim_s=wall / sim_s, us_per_sim_step=wall * 1e6 / sim_steps, events=events,
+         spikes_delivered=spikes, rate_hz=spikes / info["n"] / sim_s,
          build_s=build_s,
          kernels={"deliver_ms_mean": deliver_avg_ms, "deliver_launches": prof["deliver_launches"],
                   "update_ms_mean": prof["update_ms"] / max(1, prof["update_launches"]),
@@ -257,20 +265,19 @@ def bench_stdp(args):
     from paper_1912_07423_amd import Network
     from paper_1912_07423_amd import workloads as W
     spec = W.stdp_er()
-    steps = args.steps if args.steps != 1000 else spec["steps"]
-    net = Network(spec, raster_steps=4096)
+    steps = args.steps or spec["steps"]
+    net = Network(spec, raster_steps=4096, plasticity=args.plasticity)
     net.run(warm)
     net.sync()
-    i0 = net.info()
+    i0 = net.info()   # with lazy plasticity this brings every row current
     net.set_profiling(True)
     net.reset_profile()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     net.run(steps)
-    net.sync()
+    i1 = net.info()   # the timed region ends with every row current (weights, touches)
     wall = time.perf_counter() - t0
     prof = net.profile()
-    i1 = net.info()
     events, touches = i1["events"] - i0["events"], i1["touches"] - i0["touches"]
     spikes = i1["spikes"] - i0["spikes"]
     dmean = prof["deliver_ms"] / max(1, prof["deliver_launches"])
@@ -288,7 +295,8 @@ def bench_stdp(args):
     line("STDP network: synaptic events/sec, STDP synapse touches/sec, 1 GPU", events / wall, "events/s",
          steps, warm, wall * 1e3 / steps, "fp32",
          {"workload": "stdp_er_100k_p0.02_d10_poisson10hz", "neurons": i1["n"], "synapses": i1["nnz"],
-          "delay_steps": i1["delay"], "delivery": i1["delivery_name"], "parallelism": "single-gpu"},
+          "delay_steps": i1["delay"], "delivery": i1["delivery_name"], "plasticity": args.plasticity,
+          "parallelism": "single-gpu"},
          touches_per_s=touches / wall, events=events, touches=touches,
          kernels={"deliver_ms_mean": dmean, "stdp_ms_mean": smean,
                   "update_ms_mean": prof["update_ms"] / max(1, prof["update_launches"]),
@@ -311,7 +319,7 @@ def bench_sweep(args):
     from paper_1912_07423_amd import Batch, Network
     from paper_1912_07423_amd import workloads as W
     specs = W.sweep()
-    steps = args.steps if args.steps != 1000 else specs[0]["steps"]
+    steps = args.steps or specs[0]["steps"]
     tb = time.perf_counter()
     b = Batch(specs, raster_steps=max(16, min(steps, 5000)))
     build_s = time.perf_counter() - tb
@@ -370,7 +378,7 @@ def bench_bptt(args):
     w_in = torch.tensor(v_in, device=dev, requires_grad=True)
     w_rec = torch.tensor(v_rec, device=dev, requires_grad=True)
     w_out = torch.tensor(d["w_out"], device=dev, requires_grad=True)
-    iters = max(1, args.steps if args.steps != 1000 else 20)
+    iters = max(1, args.steps)
 
     def fwd_bwd():
         w_in.grad = w_rec.grad = w_out.grad = None
@@ -647,9 +655,14 @@ def bench_setup(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=15,
-                    help="untimed steps after the fixed 300-step settle period (Brunel workload)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (Brunel workload: bench steps of 1,000 simulation steps, "
+                         "default 5; other workloads: their own unit and default)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps after the fixed 300-step settle period (Brunel: bench "
+                         "steps, default 1)")
+    ap.add_argument("--plasticity", default="eager", choices=["eager", "lazy"],
+                    help="STDP form of the plastic workload")
     ap.add_argument("--cpu-steps", type=int, default=1500,
                     help="steps of the CPU-oracle sample (0 disables it)")
     ap.add_argument("--delivery", default="auto")
@@ -676,6 +689,14 @@ def main():
               "supported: multi-GPU execution is not implemented (its sharding design is "
               "documented only)", file=sys.stderr, flush=True)
         sys.exit(2)
+    # per-workload defaults of (timed steps, warm-up steps); 0 timed steps means the
+    # workload's own length
+    defaults = {"brunel": (5, 1), "stdp": (0, 0), "sweep": (0, 0), "bptt": (20, 10),
+                "scaling": (1000, 15), "setup": (1000, 15), "layout": (1000, 15)}[args.workload]
+    if args.steps is None:
+        args.steps = defaults[0]
+    if args.warmup is None:
+        args.warmup = defaults[1]
     if args.copy_calibration_mib > 0:
         copy_calibration(args.copy_calibration_mib)
     {"brunel": bench_brunel, "stdp": bench_stdp, "sweep": bench_sweep, "bptt": bench_bptt,

@@ -51,6 +51,18 @@ typedef int32_t snn_status;
 #define SNN_DELIVERY_ATOMIC 1u /* wavefront(s) per spike, int32 atomics in global memory */
 #define SNN_DELIVERY_TILED 2u  /* per (target tile, step) workgroup, int32 atomics in LDS */
 
+/* Update Synapses with STDP (Sec. III-A.1).  Both forms give the same weights, traces
+ * and spikes at every step. */
+#define SNN_PLASTICITY_EAGER 0u /* each step: depression over the arriving spikes' rows,
+                                   potentiation over the spiking neurons' in-edges */
+#define SNN_PLASTICITY_LAZY 1u  /* the paper's lazy variation: a row's potentiation events
+                                   wait in a per-neuron spike history (64 steps) and are
+                                   applied in registers when the row transmits or its
+                                   oldest pending step is about to leave the history
+                                   ("expiring neurons", a queue produced by Update
+                                   Neurons); per-neuron ages record what is pending.
+                                   Needs delay_steps <= 64. */
+
 typedef struct {
     uint32_t size;       /* neurons in the population (>= 1) */
     uint32_t excitatory; /* informational */
@@ -97,7 +109,7 @@ typedef struct {
                                  has the same weight, store only the 4-byte target per
                                  synapse and one weight per source (Table I layout);
                                  1: a Q16 weight per synapse as well (8 bytes per synapse) */
-    uint32_t pad_;
+    uint32_t plasticity;   /* SNN_PLASTICITY_*: how STDP weights are kept current */
 } snn_params;
 
 /* Optional device-memory provider (e.g. a framework's caching allocator).  alloc
@@ -142,7 +154,7 @@ typedef struct {
     uint32_t target_bytes;  /* bytes per target the delivery reads: 2 for the tiled delivery
                                (a 16-bit copy of the targets, held beside the 4-byte
                                array), 4 for the atomic delivery */
-    uint32_t pad3_;
+    uint32_t plasticity;    /* SNN_PLASTICITY_* of a plastic network */
 } snn_info;
 
 /* Host views for reading or writing the dynamic state; NULL members are skipped.

@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "SNN_OK", -1: "SNN_E_INVALID", -2: "SNN_E_OOM", -3: "SNN_E_HI
 
 PROJ_KIND = {"er": 0, "fixed": 1}
 DELIVERY = {"auto": 0, "atomic": 1, "tiled": 2}
+PLASTICITY = {"eager": 0, "lazy": 1}
 DELIVERY_NAME = {1: "atomic", 2: "tiled"}
 
 
@@ -43,7 +44,7 @@ PARAM_FIELDS = [
     ("a_plus", C.c_double), ("a_minus", C.c_double), ("w_max_mV", C.c_double),
     ("seed", C.c_uint64), ("raster_steps", C.c_uint32), ("window", C.c_uint32),
     ("delivery", C.c_uint32), ("tiles", C.c_uint32), ("block", C.c_uint32),
-    ("grid", C.c_uint32), ("synapse_weights", C.c_uint32), ("pad_", C.c_uint32),
+    ("grid", C.c_uint32), ("synapse_weights", C.c_uint32), ("plasticity", C.c_uint32),
 ]
 
 
@@ -70,7 +71,7 @@ class Info(C.Structure):
                 ("spikes", C.c_uint64), ("touches", C.c_uint64), ("device_bytes", C.c_uint64),
                 ("build_ms", C.c_double), ("gen_rows_ms", C.c_float), ("gen_fill_ms", C.c_float),
                 ("index_ms", C.c_float), ("tile_offset_bytes", C.c_uint32),
-                ("target_bytes", C.c_uint32), ("pad3_", C.c_uint32)]
+                ("target_bytes", C.c_uint32), ("plasticity", C.c_uint32)]
 
 
 class State(C.Structure):

@@ -222,6 +222,7 @@ void validate_and_derive(snn_network *net) {
   if (!(p.dt_ms > 0.0)) fail(SNN_E_INVALID, "dt_ms must be > 0");
   if (p.delay_steps < 1) fail(SNN_E_INVALID, "delay_steps must be >= 1");
   if (p.synapse_weights > 1) fail(SNN_E_INVALID, "synapse_weights must be 0 (auto) or 1 (per synapse)");
+  if (p.plasticity > SNN_PLASTICITY_LAZY) fail(SNN_E_INVALID, "plasticity must be SNN_PLASTICITY_EAGER or _LAZY");
   if (!(p.tau_m_ms > 0.0)) fail(SNN_E_INVALID, "tau_m_ms must be > 0");
   if (!(p.t_ref_ms >= 0.0)) fail(SNN_E_INVALID, "t_ref_ms must be >= 0");
   if (net->pops.empty()) fail(SNN_E_INVALID, "no populations");
@@ -270,6 +271,9 @@ void validate_and_derive(snn_network *net) {
     }
   }
   net->plastic = plastic;
+  net->lazy = plastic && p.plasticity == SNN_PLASTICITY_LAZY;
+  if (net->lazy && p.delay_steps > snn::kLazyHistory)
+    fail(SNN_E_INVALID, "lazy plasticity needs delay_steps <= " + std::to_string(snn::kLazyHistory));
   net->delay = p.delay_steps;
   net->alpha = (float)std::exp(-p.dt_ms / p.tau_m_ms);
   net->v_inf = (float)(p.v_rest_mV + p.v_bg_mV);
@@ -543,6 +547,24 @@ void build(snn_network *net) {
         "clear queues");
   check(hipMemsetAsync(net->raster, 0, (size_t)net->raster_cap * net->words * 8, s), "clear raster");
   check(hipMemsetAsync(net->ctl, 0, sizeof(snn::Ctl), s), "clear control");
+  if (net->lazy) {
+    // Rows start with nothing pending and ages spread over the history, so that as many
+    // rows expire at every step: row i's first pending step is -(i mod 64), before which
+    // no event exists (empty histories, zero traces).
+    net->hist = dev_array<uint64_t>(net, n);
+    net->age = dev_array<uint32_t>(net, n);
+    net->x_age = dev_array<float>(net, n);
+    net->exq = dev_array<int32_t>(net, 2 * (size_t)net->queue_stride);
+    net->exq_len = dev_array<uint32_t>(net, 2 * (size_t)snn::kQueueGroups * snn::kQlenStride);
+    check(hipMemsetAsync(net->hist, 0, (size_t)n * 8, s), "clear spike history");
+    check(hipMemsetAsync(net->x_age, 0, (size_t)n * 4, s), "clear traces at age");
+    check(hipMemsetAsync(net->exq_len, 0, 2 * (size_t)snn::kQueueGroups * snn::kQlenStride * 4, s),
+          "clear expiring rows");
+    std::vector<uint32_t> age0(n);
+    for (uint32_t i = 0; i < n; ++i) age0[i] = 0u - (i % snn::kLazyHistory);
+    check(hipMemcpyAsync(net->age, age0.data(), (size_t)n * 4, hipMemcpyHostToDevice, s), "row ages");
+    check(hipStreamSynchronize(s), "sync");
+  }
   // the drive table as the kernels search it: thresholds below 2^32 as 32-bit words, and
   // a guide table giving #{j : tbl[j] <= r} at both ends of each bucket of r's top bits
   {
@@ -581,6 +603,17 @@ snn::QueueRef queue_ref(snn_network *net) {
   return snn::QueueRef{net->queue, net->qlen, net->queue_stride, net->group_cap};
 }
 
+snn::LazyRef lazy_ref(snn_network *net) {
+  snn::LazyRef r{};
+  r.hist = net->hist;
+  r.age = net->age;
+  r.x_age = net->x_age;
+  r.plast_len = net->plast_len;
+  r.exq = snn::QueueRef{net->exq, net->exq_len, net->queue_stride, net->group_cap};
+  r.delay = net->delay;
+  return r;
+}
+
 snn::UpdateArgs update_args(snn_network *net) {
   snn::UpdateArgs a{};
   a.v = net->v;
@@ -612,6 +645,7 @@ snn::UpdateArgs update_args(snn_network *net) {
   // the tiled delivery overwrites every accumulator it owns; the atomic one adds
   a.zero_input = net->delivery == SNN_DELIVERY_ATOMIC ? 1u : 0u;
   a.plastic = net->plastic ? 1u : 0u;
+  if (net->lazy) a.lazy = lazy_ref(net);
   return a;
 }
 
@@ -662,7 +696,37 @@ snn::StdpArgs stdp_args(snn_network *net) {
   return a;
 }
 
+snn::LazyArgs lazy_args(snn_network *net) {
+  snn::LazyArgs a{};
+  a.row_ptr = net->row_ptr;
+  a.col = net->col;
+  a.w_f32 = net->w_f32;
+  a.plast_rel = net->plast_rel;
+  a.x_pre = net->x_pre;
+  a.x_post = net->x_post;
+  a.q = queue_ref(net);
+  a.input = net->input;
+  a.lazy = lazy_ref(net);
+  a.ctl = net->ctl;
+  a.n = net->n;
+  a.slots = net->slots;
+  a.delay = net->delay;
+  a.a_plus = net->a_plus;
+  a.w_max = net->w_max;
+  a.beta_plus = net->beta_plus;
+  return a;
+}
+
 uint32_t atomic_grid(const snn_network *net) { return net->cu_count * 8; }
+uint32_t lazy_grid(const snn_network *net) { return net->cu_count * 4; }
+
+// Lazy plasticity: brings every plastic row current at the step boundary (weights and
+// the touch count then equal the eager form's), without changing what the simulation
+// computes next.  Ordered on the network's stream.
+void lazy_flush(snn_network *net) {
+  if (!net->lazy) return;
+  check(snn::launch_lazy_flush(lazy_args(net), net->t_host, lazy_grid(net), net->stream), "lazy flush");
+}
 
 hipError_t launch_delivery(snn_network *net, const snn::DeliverArgs &d, uint32_t steps,
                            const snn::LaunchEvents &ev = {}) {
@@ -725,6 +789,16 @@ void resolve_profile(snn_network *net) {
 void issue_window(snn_network *net, uint32_t steps) {
   const snn::UpdateArgs u = update_args(net);
   timed(net, 0, [&](const snn::LaunchEvents &ev) { return snn::launch_update(u, steps, net->stream, ev); });
+  if (net->lazy) {
+    // depression over the arriving rows, then one launch for the transmitting rows
+    // (pending potentiation, delivery) and the expiring rows
+    const snn::StdpArgs sa = stdp_args(net);
+    timed(net, 2, [&](const snn::LaunchEvents &ev) { return snn::launch_stdp_ltd(sa, net->cu_count * 4, net->stream, ev); });
+    const snn::LazyArgs la = lazy_args(net);
+    timed(net, 1, [&](const snn::LaunchEvents &ev) { return snn::launch_lazy(la, lazy_grid(net), net->stream, ev); });
+    net->t_host += steps;
+    return;
+  }
   if (net->plastic) {
     const snn::StdpArgs sa = stdp_args(net);
     timed(net, 2, [&](const snn::LaunchEvents &ev) { return snn::launch_stdp(sa, net->cu_count * 4, net->stream, ev); });
@@ -779,11 +853,11 @@ void sync(snn_network *net) {
 }
 
 struct CtlTotals {
-  uint64_t t, events, spikes, touches;
+  uint64_t t, events, spikes, touches, lazy_overrun;
 };
 
 CtlTotals sum_ctl(const snn::Ctl &c) {
-  CtlTotals r{c.t, 0, 0, 0};
+  CtlTotals r{c.t, 0, 0, 0, c.lazy_overrun};
   for (uint32_t p = 0; p < snn::kCounterParts; ++p) {
     r.events += c.events[p * snn::kLineU64];
     r.spikes += c.spikes[p * snn::kLineU64];
@@ -819,6 +893,7 @@ void copy_raster_rows(snn_network *net, uint64_t t0, uint64_t t1, uint64_t *out)
 
 
 
+
 // ---- delivery reconfiguration, timing and autotuning --------------------------------
 void dev_free(snn_network *net, void *p) {
   for (size_t k = 0; k < net->allocs.size(); ++k)
@@ -838,6 +913,7 @@ void dev_free(snn_network *net, void *p) {
 // tiling, device memory, a launch), every field and buffer of the old configuration is
 // restored, so the network keeps running as before.
 void set_delivery(snn_network *net, uint32_t delivery, uint32_t tiles, uint32_t block, uint32_t grid) {
+  if (net->lazy) fail(SNN_E_STATE, "lazy plasticity delivers inside its own kernel; there is no variant to choose");
   if (delivery > SNN_DELIVERY_TILED) fail(SNN_E_INVALID, "unknown delivery variant");
   if (net->plastic && delivery == SNN_DELIVERY_TILED) fail(SNN_E_INVALID, "tiled delivery needs static weights");
   check(hipStreamSynchronize(net->stream), "sync");
@@ -982,6 +1058,7 @@ double time_delivery(snn_network *net, const std::vector<std::vector<uint32_t>> 
 // Times every candidate delivery configuration on the spikes of the latest window (read
 // from the raster ring) and keeps the fastest.
 snn_delivery_tuning autotune_delivery(snn_network *net, uint32_t reps) {
+  if (net->lazy) fail(SNN_E_STATE, "lazy plasticity delivers inside its own kernel; there is no variant to tune");
   const uint32_t W = net->window;
   if (net->t_host < W) fail(SNN_E_STATE, "run at least one window before autotuning the delivery");
   if (net->raster_cap < W) fail(SNN_E_STATE, "the raster ring holds less than one window");
@@ -1542,7 +1619,9 @@ snn_status snn_get_raster(snn_network *net, uint64_t t_begin, uint64_t t_end, ui
 snn_status snn_get_info(snn_network *net, snn_info *info) {
   return guarded([&] {
     if (!net || !info) fail(SNN_E_INVALID, "null argument");
+    lazy_flush(net);  // pending potentiation counted as touches
     const CtlTotals c = read_ctl(net);
+    if (c.lazy_overrun) fail(SNN_E_STATE, "lazy plasticity: a row had more pending steps than the spike history holds");
     snn_info r{};
     r.n = net->n;
     r.delay = net->delay;
@@ -1570,6 +1649,7 @@ snn_status snn_get_info(snn_network *net, snn_info *info) {
     r.index_ms = net->index_ms;
     r.tile_offset_bytes = net->tile_off ? (net->tile_off16 ? 2u : 4u) : 0u;
     r.target_bytes = net->delivery == SNN_DELIVERY_TILED ? 2u : 4u;
+    r.plasticity = net->lazy ? SNN_PLASTICITY_LAZY : SNN_PLASTICITY_EAGER;
     if (c.t != net->t_host) fail(SNN_E_STATE, "device step counter disagrees with the host");
     *info = r;
   });
@@ -1578,6 +1658,7 @@ snn_status snn_get_info(snn_network *net, snn_info *info) {
 snn_status snn_get_state(snn_network *net, const snn_state *st) {
   return guarded([&] {
     if (!net || !st) fail(SNN_E_INVALID, "null argument");
+    lazy_flush(net);  // weights as the eager form holds them
     hipStream_t s = net->stream;
     const size_t n = net->n;
     auto d2h = [&](void *dst, const void *src, size_t bytes) {
@@ -1604,6 +1685,9 @@ snn_status snn_get_state(snn_network *net, const snn_state *st) {
 snn_status snn_set_state(snn_network *net, const snn_state *st) {
   return guarded([&] {
     if (!net || !st) fail(SNN_E_INVALID, "null argument");
+    // lazy plasticity: pending potentiation is applied with the traces it was due under;
+    // the rows' traces at age are rebuilt from the new x_pre afterwards
+    lazy_flush(net);
     hipStream_t s = net->stream;
     const size_t n = net->n;
     auto h2d = [&](void *dst, const void *src, size_t bytes) {
@@ -1623,6 +1707,7 @@ snn_status snn_set_state(snn_network *net, const snn_state *st) {
       if (!net->plastic) fail(SNN_E_INVALID, "w_f32 given to a static network");
       h2d(net->w_f32, st->w_f32, net->nnz * 4);
     }
+    lazy_flush(net);
     sync(net);
   });
 }
@@ -1646,6 +1731,7 @@ snn_status snn_get_row(snn_network *net, uint32_t i, int32_t *col, int32_t *w_q1
     }
     if (w_f32) {
       if (!net->w_f32) fail(SNN_E_INVALID, "network has Q16 weights");
+      lazy_flush(net);
       check(hipMemcpyAsync(w_f32, net->w_f32 + rp[0], *len * 4, hipMemcpyDeviceToHost, net->stream), "row");
     }
     sync(net);
@@ -1673,6 +1759,7 @@ snn_status snn_get_synapses(snn_network *net, uint64_t *row_ptr, int32_t *col, i
     }
     if (w_f32) {
       if (!net->w_f32) fail(SNN_E_INVALID, "network has Q16 weights");
+      lazy_flush(net);
       check(hipMemcpyAsync(w_f32, net->w_f32, net->nnz * 4, hipMemcpyDeviceToHost, s), "copy");
     }
     sync(net);

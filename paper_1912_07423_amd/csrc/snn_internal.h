@@ -31,7 +31,8 @@ constexpr uint32_t kGuideBuckets = 1u << kGuideBits;
 struct Ctl {
   uint64_t t;
   uint64_t t_deliver;
-  uint64_t pad[kLineU64 - 2];
+  uint64_t lazy_overrun;  // rows found with more pending steps than the history holds
+  uint64_t pad[kLineU64 - 3];
   uint64_t events[kCounterParts * kLineU64];   // part p at [p * kLineU64]
   uint64_t spikes[kCounterParts * kLineU64];
   uint64_t touches[kCounterParts * kLineU64];
@@ -72,6 +73,21 @@ struct GenArgs {
   uint32_t key0, key1;
 };
 
+// Lazy plasticity (Sec. III-A.1, Table I "bitmasks", "ages", "expirations").  Row i's
+// potentiation events of the steps [age_i, t] are pending: they wait in the targets'
+// spike histories and are applied when the row transmits or, at the latest, when the
+// oldest pending step is about to leave the kLazyHistory-step history.
+constexpr uint32_t kLazyHistory = 64;  // steps of spike history per neuron (one uint64)
+struct LazyRef {
+  uint64_t *hist;         // [n] bit k: the neuron spiked at step t - k (t the last update)
+  uint32_t *age;          // [n] first pending step of the row, mod 2^32
+  float *x_age;           // [n] the row's presynaptic trace at its age step
+  const uint32_t *plast_len;  // [n] plastic synapses of each row (0: no age kept)
+  QueueRef exq;           // 2 slots: the expiring rows of step t in slot t mod 2, laid out
+                          // as a spike queue (kQueueGroups sub-queues)
+  uint32_t delay;
+};
+
 struct UpdateArgs {
   float *v;
   int32_t *ref;
@@ -87,6 +103,9 @@ struct UpdateArgs {
   float alpha, v_inf, v_th, v_reset, beta_plus, beta_minus;
   int32_t ref_steps, w_ext_q16;
   uint32_t zero_input, plastic;
+  // lazy plasticity (one step per launch): spike history, ages and the expiring-row
+  // queue, all null otherwise
+  LazyRef lazy;
 };
 
 struct DeliverArgs {
@@ -107,6 +126,23 @@ struct DeliverArgs {
   uint32_t tiles, tile_size;
   uint32_t off16;
   uint32_t advance;       // this launch closes the window: advance the step counter
+};
+
+// The lazy plasticity kernel of one step t: rows of S_{t-d+1} transmit (pending
+// potentiation applied, then delivered with the current weights), expiring rows are
+// brought current, and the postsynaptic traces of S_t are incremented.
+struct LazyArgs {
+  const uint64_t *row_ptr;
+  const int32_t *col;
+  float *w_f32;
+  const uint32_t *plast_rel;
+  float *x_pre, *x_post;
+  QueueRef q;
+  int32_t *input;
+  LazyRef lazy;
+  Ctl *ctl;
+  uint32_t n, slots, delay;
+  float a_plus, w_max, beta_plus;
 };
 
 struct StdpArgs {
@@ -207,6 +243,11 @@ hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t b
 constexpr uint32_t kTileGroupMax = 8;  // base tiles one tiled-delivery workgroup may own
 hipError_t prepare_deliver_tiled(uint32_t block, size_t *max_dynamic_lds);
 hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});
+hipError_t launch_stdp_ltd(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});
+hipError_t launch_lazy(const LazyArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});
+// Brings every plastic row current at step boundary t (pending potentiation applied,
+// age t, trace at age rebuilt from x_pre and the arrivals of step t).
+hipError_t launch_lazy_flush(const LazyArgs &a, uint64_t t, uint32_t grid, hipStream_t s);
 hipError_t launch_row_lengths(const GenArgs &g, uint32_t *len, uint32_t *plast_rel,
                               uint32_t *plast_len, hipStream_t s);
 hipError_t launch_fill_rows(const GenArgs &g, uint32_t max_fixed_k, const uint64_t *row_ptr,
@@ -246,6 +287,7 @@ struct snn_network {
   uint32_t delivery = SNN_DELIVERY_ATOMIC, tiles = 1, tile_size = 1, block = 512, grid = 512;
   uint32_t raster_cap = 1024, words = 1;
   bool plastic = false;
+  bool lazy = false;  // plastic, with SNN_PLASTICITY_LAZY
   uint64_t nnz = 0, nnz_alloc = 0;
 
   // derived constants
@@ -277,6 +319,12 @@ struct snn_network {
   uint32_t *d_table32 = nullptr;
   uint16_t *d_guide = nullptr;
   snn::Ctl *ctl = nullptr;
+  // lazy plasticity: per-neuron spike history, row ages and traces at age, expiring rows
+  uint64_t *hist = nullptr;
+  uint32_t *age = nullptr;
+  float *x_age = nullptr;
+  int32_t *exq = nullptr;
+  uint32_t *exq_len = nullptr;
 
   // bookkeeping
   struct Alloc {

@@ -85,6 +85,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
   __shared__ __align__(16) uint32_t tbl[kTableCap];
   __shared__ __align__(16) uint16_t guide[kGuideBuckets];
   __shared__ uint32_t s_base[kUpdateWaves][kWave];
+  __shared__ uint32_t s_exp[kUpdateWaves];  // lazy plasticity: expiring rows per wave, then base
   static_assert(kTableCap / 4 <= kUpdateBlock && kGuideBuckets / 8 == 2 * kUpdateBlock,
                 "one 16-byte table load per lane, two guide loads");
 
@@ -126,12 +127,20 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
   }
   float v = 0.f, xp = 0.f, xq = 0.f;
   int32_t ref = 0;
+  const bool lazy = a.lazy.hist != nullptr;  // one step per launch
+  uint64_t hist = 0;
+  uint32_t age = 0, plen = 0;
   if (active) {
     v = a.v[i];
     ref = a.ref[i];
     if (a.plastic) {
       xp = a.x_pre[i];
       xq = a.x_post[i];
+    }
+    if (lazy) {
+      hist = a.lazy.hist[i];
+      age = a.lazy.age[i];
+      plen = a.lazy.plast_len[i];
     }
   }
   int32_t acc[kPrefetch];
@@ -185,12 +194,36 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
       a.x_post[i] = xq;
     }
   }
+  // Lazy plasticity: the spike history gains this step's bit; a plastic row whose pending
+  // steps [age, t0] fill the whole history expires now, unless it transmits now (its
+  // spike of step t0 - d + 1, history bit d - 1), which brings it current anyway.
+  bool expiring = false;
+  uint64_t emask = 0;
+  if (lazy) {
+    hist = (hist << 1) | (my_spikes & 1u);
+    const uint32_t pending = (uint32_t)t0 - age + 1u;
+    const bool transmits = (hist >> (a.lazy.delay - 1u)) & 1u;
+    expiring = active && plen > 0 && pending >= kLazyHistory && !transmits;
+    if (active) a.lazy.hist[i] = hist;
+    emask = __ballot(expiring);
+    if (lane == 0) s_exp[wave] = (uint32_t)__popcll(emask);
+  }
   // raster rows and queue reservations of the whole window, one lane per step
   if (lane < steps) {
     if (word < a.words) a.raster[(size_t)ring_add(ras0, lane, a.raster_cap) * a.words + word] = my_mask;
     s_base[wave][lane] = (uint32_t)__popcll(my_mask);
   }
   __syncthreads();
+  if (lazy && threadIdx.x == kUpdateBlock - 1) {  // not one of the step threads below
+    uint32_t total = 0;
+    for (int v2 = 0; v2 < kUpdateWaves; ++v2) {
+      const uint32_t c = s_exp[v2];
+      s_exp[v2] = total;
+      total += c;
+    }
+    const uint32_t base = total ? atomicAdd(qcount(a.lazy.exq, (uint32_t)(t0 & 1u), group), total) : 0u;
+    for (int v2 = 0; v2 < kUpdateWaves; ++v2) s_exp[v2] += base;
+  }
   if (threadIdx.x < steps) {
     const uint32_t w = threadIdx.x;
     uint32_t total = 0;
@@ -212,6 +245,11 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
     const uint32_t slot = ring_add(slot0, w, a.slots);
     if (((my_spikes >> w) & 1u) && pos < a.q.group_cap)
       a.q.ids[(size_t)slot * a.q.stride + group * a.q.group_cap + pos] = (int32_t)i;
+  }
+  if (expiring) {
+    const uint32_t pos = s_exp[wave] + lanes_below(emask);
+    if (pos < a.lazy.exq.group_cap)
+      a.lazy.exq.ids[(size_t)(t0 & 1u) * a.lazy.exq.stride + group * a.lazy.exq.group_cap + pos] = (int32_t)i;
   }
 }
 
@@ -736,6 +774,176 @@ __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltp(StdpArgs a) {
   if (lane == 0) add_part(a.ctl->touches, gwave, touched);
 }
 
+// ---- lazy plasticity (Sec. III-A.1, "lazy variation of plasticity") ------------------
+// A plastic row keeps an age (its first pending step) and its presynaptic trace at that
+// step.  Its depression events are applied eagerly (k_stdp_ltd: they come once per
+// arrival, over the row's contiguous plastic prefix); its potentiation events, one per
+// postsynaptic spike of each target, wait until the row transmits or its oldest pending
+// step would leave the targets' 64-step spike histories.  Then one workgroup replays
+// them in registers, oldest first, with the same binary32 operations as the eager form.
+constexpr int kLazyBlock = 256;
+constexpr int kLazyUnroll = 4;  // synapses per thread in flight
+
+struct LazyCounts {
+  uint64_t events = 0, spikes = 0, touches = 0;
+};
+
+// Row i, pending steps [t_end - L + 1, t_end] (L <= kLazyHistory; the targets' histories
+// end at step t_end).  The row's presynaptic trace over those steps is the iterated
+// product X(age + m) = X(age) * beta^m, one rounding per step, as the neuron update
+// computes it; no arrival lies inside a pending window (an arrival follows the row's own
+// transmission, which brings the row current).  With `transmit`, every synapse of the row
+// is then delivered with its current weight.  Called by the whole workgroup; s_traj holds
+// kLazyHistory floats.
+__device__ void lazy_row(const LazyArgs &a, int32_t i, uint32_t L, bool transmit, float *s_traj,
+                         LazyCounts &cnt) {
+  const uint64_t rs = a.row_ptr[i], re = a.row_ptr[i + 1];
+  const uint32_t plen = a.lazy.plast_len[i];
+  const uint64_t plo = rs + (plen ? a.plast_rel[i] : 0u), phi = plo + plen;
+  if (plen && L) {
+    if (threadIdx.x < kWave) {
+      float x = a.lazy.x_age[i];
+      for (uint32_t q = 1; q < L; ++q)
+        if (threadIdx.x >= q) x = x * a.beta_plus;
+      if (threadIdx.x < L) s_traj[threadIdx.x] = x;
+    }
+    __syncthreads();
+  }
+  const uint64_t win = L >= 64 ? ~0ull : ((1ull << L) - 1ull);
+  const uint64_t lo = transmit ? rs : plo, hi = transmit ? re : phi;
+  for (uint64_t e0 = lo; e0 < hi; e0 += (uint64_t)kLazyBlock * kLazyUnroll) {
+    int32_t j[kLazyUnroll];
+    uint64_t bits[kLazyUnroll];
+    float w[kLazyUnroll];
+#pragma unroll
+    for (int u = 0; u < kLazyUnroll; ++u) {
+      const uint64_t e = e0 + threadIdx.x + (uint64_t)u * kLazyBlock;
+      j[u] = e < hi ? a.col[e] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kLazyUnroll; ++u) {
+      const uint64_t e = e0 + threadIdx.x + (uint64_t)u * kLazyBlock;
+      const bool plastic = e >= plo && e < phi && L;
+      bits[u] = plastic && j[u] >= 0 ? a.lazy.hist[j[u]] & win : 0ull;
+      w[u] = (j[u] >= 0 && (transmit || bits[u])) ? a.w_f32[e] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < kLazyUnroll; ++u) {
+      const uint64_t e = e0 + threadIdx.x + (uint64_t)u * kLazyBlock;
+      uint64_t b = bits[u];
+      if (b) {
+        cnt.touches += (uint64_t)__popcll(b);
+        float wv = w[u];
+        while (b) {  // oldest pending postsynaptic spike first: highest bit
+          const uint32_t k = 63u - (uint32_t)__builtin_clzll(b);
+          b &= ~(1ull << k);
+          const float dw = a.a_plus * s_traj[L - 1u - k];
+          float x = wv + dw;
+          if (x > a.w_max) x = a.w_max;
+          wv = x;
+        }
+        w[u] = wv;
+        a.w_f32[e] = wv;
+      }
+      if (transmit && j[u] >= 0)
+        __hip_atomic_fetch_add(a.input + j[u], __float2int_rn(w[u] * 65536.0f), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (transmit && threadIdx.x == 0) {
+    cnt.events += re - rs;
+    ++cnt.spikes;
+  }
+}
+
+// The row's new age t_next and its presynaptic trace there: x_pre (the trace of step
+// t_next - 1) decayed once, plus one if the row's spike arrives at t_next.
+__device__ __forceinline__ void lazy_rebase(const LazyArgs &a, int32_t i, uint64_t t_next, bool arrives) {
+  const float xb = a.x_pre[i] * a.beta_plus;
+  a.lazy.x_age[i] = arrives ? xb + 1.0f : xb;
+  a.lazy.age[i] = (uint32_t)t_next;
+}
+
+__device__ __forceinline__ void lazy_commit(const LazyArgs &a, const LazyCounts &c) {
+  const uint32_t part = blockIdx.x * (kLazyBlock / kWave) + threadIdx.x / kWave;
+  const uint64_t ev = wave_sum(c.events), sp = wave_sum(c.spikes), to = wave_sum(c.touches);
+  if (lane_id() == 0) {
+    add_part(a.ctl->events, part, ev);
+    add_part(a.ctl->spikes, part, sp);
+    add_part(a.ctl->touches, part, to);
+  }
+}
+
+// Step t (after the update and the depression pass): one workgroup per transmitting row
+// (S_{t-d+1}) or expiring row; closes the step.
+__global__ __launch_bounds__(kLazyBlock) void k_lazy(LazyArgs a) {
+  __shared__ float s_traj[kLazyHistory];
+  const uint64_t t = a.ctl->t_deliver;
+  const uint32_t cur = (uint32_t)(t % a.slots);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // next step's spike and expiring-row counters start empty; no workgroup of this
+    // launch reads them, and the next update sees the writes after the kernel boundary
+    const uint32_t next = (uint32_t)((t + 1) % a.slots);
+    for (uint32_t g = 0; g < kQueueGroups; ++g) {
+      *qcount(a.q, next, g) = 0u;
+      *qcount(a.lazy.exq, (uint32_t)((t + 1) & 1u), g) = 0u;
+    }
+    a.ctl->t = t + 1;
+  }
+  uint32_t txp[kQueueGroups + 1] = {}, exp[kQueueGroups + 1], pst[kQueueGroups + 1];
+  const bool has_tx = t + 1 >= a.delay;
+  const uint32_t tx_slot = has_tx ? (uint32_t)((t + 1 - a.delay) % a.slots) : 0u;
+  if (has_tx) queue_prefix(a.q, tx_slot, txp);
+  queue_prefix(a.lazy.exq, (uint32_t)(t & 1u), exp);
+  queue_prefix(a.q, cur, pst);
+  // postsynaptic traces of S_t (the depression pass of this step has read them)
+  for (uint32_t f = blockIdx.x * kLazyBlock + threadIdx.x; f < pst[kQueueGroups]; f += gridDim.x * kLazyBlock) {
+    const int32_t j = queue_entry(a.q, cur, pst, f);
+    if ((uint32_t)j < a.n) a.x_post[j] = a.x_post[j] + 1.0f;
+  }
+  const uint32_t n_tx = txp[kQueueGroups], n_items = n_tx + exp[kQueueGroups];
+  LazyCounts c;
+  for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const bool tx = item < n_tx;
+    const int32_t i = tx ? queue_entry(a.q, tx_slot, txp, item)
+                         : queue_entry(a.lazy.exq, (uint32_t)(t & 1u), exp, item - n_tx);
+    if ((uint32_t)i >= a.n) continue;
+    const bool plastic = a.lazy.plast_len[i] > 0;
+    uint32_t L = plastic ? (uint32_t)t - a.lazy.age[i] + 1u : 0u;  // pending steps [age, t]
+    if (L > kLazyHistory) {
+      if (threadIdx.x == 0) atomicAdd((unsigned long long *)&a.ctl->lazy_overrun, 1ull);
+      L = kLazyHistory;
+    }
+    lazy_row(a, i, L, tx, s_traj, c);
+    __syncthreads();  // every thread is done with s_traj and with the row's age
+    if (plastic && threadIdx.x == 0) lazy_rebase(a, i, t + 1, tx);
+  }
+  lazy_commit(a, c);
+}
+
+// Every plastic row brought current at the step boundary t (after step t - 1): pending
+// steps [age, t - 1] applied, age t, trace rebuilt (the row's spike of step t - d arrives
+// at t: history bit d - 1 after the update of step t - 1).
+__global__ __launch_bounds__(kLazyBlock) void k_lazy_flush(LazyArgs a, uint64_t t) {
+  __shared__ float s_traj[kLazyHistory];
+  LazyCounts c;
+  for (uint32_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+    if (a.lazy.plast_len[i] == 0) continue;
+    uint32_t L = (uint32_t)t - a.lazy.age[i];  // pending steps [age, t - 1]
+    if (L > kLazyHistory) {
+      if (threadIdx.x == 0) atomicAdd((unsigned long long *)&a.ctl->lazy_overrun, 1ull);
+      L = kLazyHistory;
+    }
+    if (L) lazy_row(a, (int32_t)i, L, false, s_traj, c);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const bool arrives = t >= a.delay && ((a.lazy.hist[i] >> (a.delay - 1u)) & 1u);
+      lazy_rebase(a, (int32_t)i, t, arrives);
+    }
+  }
+  lazy_commit(a, c);
+}
+
 }  // namespace
 
 // One launch, through hipExtLaunchKernel when timing events are requested.
@@ -819,6 +1027,21 @@ hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t b
 hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev) {
   launch_kernel(k_stdp_ltd, grid, kStdpBlock, 0, s, ev.start, nullptr, a);
   launch_kernel(k_stdp_ltp, grid, kStdpBlock, 0, s, nullptr, ev.stop, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stdp_ltd(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev) {
+  launch_kernel(k_stdp_ltd, grid, kStdpBlock, 0, s, ev.start, ev.stop, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lazy(const LazyArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev) {
+  launch_kernel(k_lazy, grid, kLazyBlock, 0, s, ev.start, ev.stop, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lazy_flush(const LazyArgs &a, uint64_t t, uint32_t grid, hipStream_t s) {
+  k_lazy_flush<<<grid, kLazyBlock, 0, s>>>(a, t);
   return hipGetLastError();
 }
 

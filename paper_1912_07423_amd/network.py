@@ -48,8 +48,9 @@ def _structs(spec, **extra):
     prm = spec["params"]
     fields = {k: prm[k] for k, _ in L.PARAM_FIELDS
               if k not in ("raster_steps", "window", "delivery", "tiles", "block", "grid",
-                           "synapse_weights", "pad_")}
-    base = dict(raster_steps=0, window=0, delivery=0, tiles=0, block=0, grid=0, synapse_weights=0)
+                           "synapse_weights", "plasticity")}
+    base = dict(raster_steps=0, window=0, delivery=0, tiles=0, block=0, grid=0, synapse_weights=0,
+                plasticity=0)
     base.update(extra)
     p = L.Params(**fields, **base)
     pops = (L.Population * len(spec["pops"]))(
@@ -71,19 +72,21 @@ class Network:
     tiles (target base tiles of the tiled delivery; 0 = auto), block (its workgroup
     size: 256 | 512 | 1024; 0 = auto), grid (its workgroups; 0 = auto), synapse_weights
     ("auto": one weight per source population where the projections allow it, else
-    per synapse; "per_synapse": always a weight per synapse), torch_memory (allocate
-    through torch's caching allocator and run on torch's current stream).
+    per synapse; "per_synapse": always a weight per synapse), plasticity ("eager" |
+    "lazy": how STDP weights are kept current; identical results), torch_memory
+    (allocate through torch's caching allocator and run on torch's current stream).
     """
 
     def __init__(self, spec, raster_steps=1024, window=0, delivery="auto", tiles=0, block=0,
-                 grid=0, synapse_weights="auto", torch_memory=True, device=0):
+                 grid=0, synapse_weights="auto", plasticity="eager", torch_memory=True, device=0):
         lib = L.load()
         self._lib = lib
         self._h = None
         p, pops, projs, n_projs = _structs(spec, raster_steps=raster_steps, window=window,
                                            delivery=L.DELIVERY[delivery], tiles=tiles,
                                            block=block, grid=grid,
-                                           synapse_weights={"auto": 0, "per_synapse": 1}[synapse_weights])
+                                           synapse_weights={"auto": 0, "per_synapse": 1}[synapse_weights],
+                                           plasticity=L.PLASTICITY[plasticity])
         self._keep = None
         stream_handle = None
         alloc_ptr = None

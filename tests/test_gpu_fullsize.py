@@ -3,8 +3,8 @@ times: the whole HIP path against the oracle's complete run of the same network.
 
   * 4,000-neuron CUBA network (ER p = 0.02, no delays): all 10,000 steps.
   * 200,000-neuron Brunel network (fixed out-degree 5,000, 1e9 synapses, 15-step
-    delay, Poisson drive): the benchmark's whole run, 300 warm-up + 1,000 timed steps,
-    with the tiled delivery, 87 base tiles (2-byte boundaries), one weight per source, and the device-side
+    delay, Poisson drive): the benchmark's 300-step settle period, its warm-up bench step
+    and one timed bench step (1,000 simulation steps each), with the tiled delivery, 87 base tiles (2-byte boundaries), one weight per source, and the device-side
     schedule, exactly as benchmarked.
   * 100,000-neuron plastic network (ER p = 0.02, 2e8 synapses, STDP on E->E, 10-step
     delay): all 2,000 steps, final FP32 weights of every synapse compared bit for bit.
@@ -19,7 +19,7 @@ import pytest
 
 import oracle
 from paper_1912_07423_amd import workloads as W
-from gpu_compare import compare_run, net
+from gpu_compare import compare_net, compare_run, net
 
 pytestmark = pytest.mark.gpu
 
@@ -40,7 +40,7 @@ def test_cuba_4k_all_10000_steps():
 
 def test_brunel_200k_1e9_synapses():
     spec = W.brunel_fixed_out()
-    steps = 1300
+    steps = 300 + 2 * 1000
     print(f"[full] brunel_fixed_out n=200000 k=5000: {steps} steps", flush=True)
     rg, inf = compare_run(spec, steps, raster_steps=4096)
     assert inf["nnz"] == 200_000 * 5000
@@ -66,13 +66,23 @@ def test_brunel_200k_sampled_rows_match_generator():
         assert len(col) == 5000 and int(i) not in set(col.tolist())
 
 
-def test_stdp_100k_all_2000_steps():
+def test_stdp_100k_all_2000_steps_eager_and_lazy():
+    """Both forms of Update Synapses on the 2e8-synapse plastic network against one run
+    of the oracle: raster, V, traces, every weight and the touch count after 2,000 steps."""
     spec = W.stdp_er()
-    print(f"[full] stdp_er n=100000 p=0.02: {spec['steps']} steps", flush=True)
-    rg, inf = compare_run(spec, spec["steps"])
-    assert inf["plastic"] and inf["touches"] > 0
-    print(f"[full] stdp: {int(np.unpackbits(rg.view(np.uint8)).sum())} spikes, "
-          f"{inf['events']} events, {inf['touches']} touches", flush=True)
+    T = spec["steps"]
+    print(f"[full] stdp_er n=100000 p=0.02: {T} steps, oracle", flush=True)
+    o = oracle.OracleNet(spec, raster_cap=T)
+    o.run(T)
+    for mode in ("eager", "lazy"):
+        print(f"[full] stdp {mode}", flush=True)
+        g = net(spec, raster_steps=T, plasticity=mode)
+        g.run(T)
+        rg, inf = compare_net(g, o, T)
+        assert inf["plastic"] and inf["touches"] > 0 and inf["plasticity"] == (mode == "lazy")
+        print(f"[full] stdp {mode}: {int(np.unpackbits(rg.view(np.uint8)).sum())} spikes, "
+              f"{inf['events']} events, {inf['touches']} touches", flush=True)
+        g.close()
 
 
 def _ids(row_words, n):
