@@ -251,6 +251,23 @@ snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_
                              const uint32_t *step_counts, uint32_t steps, uint32_t reps,
                              double *avg_ms, uint64_t *events);
 
+/* snn_time_delivery for callers that cannot allocate device memory (code that must not
+ * call hipMalloc: tight measurement or serving loops, harnesses that forbid it).  Same
+ * arguments, checks and results, except that the mean time runs from the first timed
+ * launch's begin to the last one's end (back-to-back launches).  Every device buffer
+ * (the staged queues and counters, the control block, the input accumulators and the
+ * copied ids) lives in one fixed 64 MiB device array that each GPU holds for the life of
+ * the process; the call allocates no device memory (its first call on a GPU looks the
+ * array up and creates two timing events).  SNN_E_INVALID if the window needs more than
+ * 64 MiB: 49,408 + steps * (2,048 + 4 * queue_stride) + 4 * input_buffers * n +
+ * 4 * n_ids bytes, each part rounded up to 256.  Every call on a GPU shares its array and
+ * clears what it uses first; calls that overlap on one GPU (other threads or streams)
+ * race and must not be made.  Synchronises the network's stream, so it cannot be
+ * captured into a graph. */
+snn_status snn_time_delivery_static(snn_network *net, const uint32_t *ids_host, uint32_t n_ids,
+                                    const uint32_t *step_counts, uint32_t steps, uint32_t reps,
+                                    double *avg_ms, uint64_t *events);
+
 /* Switch a network's delivery variant (SNN_DELIVERY_*; AUTO picks by size and
  * degree), its base tiles, workgroup size and grid (0 = auto), from the next step on.
  * Rebuilds the tile boundaries; the simulation state is unchanged.  Plastic networks

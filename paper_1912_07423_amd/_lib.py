@@ -134,6 +134,8 @@ SIGNATURES = {
     "snn_memory_cache_release": (C.c_int32, [C.c_int]),
     "snn_time_delivery": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_uint32,
                                       C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
+    "snn_time_delivery_static": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32,
+                                             C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "snn_set_delivery": (C.c_int32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]),
     "snn_autotune_delivery": (C.c_int32, [C.c_void_p, C.c_uint32, C.POINTER(DeliveryTuning)]),
     "snn_destroy": (None, [C.c_void_p]),

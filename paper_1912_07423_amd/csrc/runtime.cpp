@@ -1055,6 +1055,124 @@ double time_delivery(snn_network *net, const std::vector<std::vector<uint32_t>> 
   return ms_out;
 }
 
+// ---- delivery timing in a fixed device array (no allocation) ------------------------
+// Scratch of snn_time_delivery_static: one window's staged queues and counters, the
+// control block and the input accumulators the delivery writes.  Each GPU holds its
+// own copy for the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns for that device.
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+struct StaticScratch {
+  unsigned char *ptr = nullptr;            // device address of `scratch` on this device
+  hipEvent_t start = nullptr, stop = nullptr;  // timing events, created with it
+};
+std::mutex g_static_mu;
+StaticScratch g_static[kMaxDevices];
+
+// Set-up on the first call on `device`, with that device current: the array's device
+// address and the two timing events.  Later calls only read the table.
+StaticScratch static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(SNN_E_INVALID, "device id beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticScratch &s = g_static[device];
+  if (s.ptr) return s;
+  int cur = -1;
+  check(hipGetDevice(&cur), "hipGetDevice");
+  if (cur != device) check(hipSetDevice(device), "hipSetDevice");
+  void *p = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess || !p) {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    check(e != hipSuccess ? e : hipErrorInvalidSymbol, "static scratch set-up");
+  }
+  s.start = a;
+  s.stop = b;
+  s.ptr = static_cast<unsigned char *>(p);
+  return s;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// snn_time_delivery with every device buffer in the static scratch: the ids are checked
+// on the host, copied into the scratch as they are, and laid out as the window's queues
+// by k_stage_window; then one untimed and `reps` timed launches of the network's
+// delivery kernel, the mean taken from the first timed launch's begin to the last one's
+// end.
+double time_delivery_static(snn_network *net, const uint32_t *ids, uint32_t n_ids, const uint32_t *step_counts,
+                            uint32_t steps, uint32_t reps, uint64_t *events) {
+  if (steps == 0 || steps > net->window) fail(SNN_E_INVALID, "steps exceeds the network's window");
+  if (reps == 0) reps = 1;
+  snn::StageArgs st{};
+  st.steps = steps;
+  st.n_ids = n_ids;
+  st.round_robin = step_counts ? 0u : 1u;
+  uint64_t k = 0;
+  for (uint32_t w = 0; w < steps; ++w) {
+    const uint64_t c = step_counts ? step_counts[w] : (n_ids > w ? (n_ids - w + steps - 1) / steps : 0u);
+    if (c > net->n) fail(SNN_E_INVALID, "more ids in a step than neurons");
+    st.off[w] = (uint32_t)k;
+    k += c;
+    if (k > n_ids) fail(SNN_E_INVALID, "step counts exceed the ids");
+  }
+  if (k != n_ids) fail(SNN_E_INVALID, "step counts do not sum to n_ids");
+  st.off[steps] = (uint32_t)k;
+  for (uint32_t j = 0; j < n_ids; ++j)
+    if (ids[j] >= net->n) fail(SNN_E_INVALID, "id out of range");
+  const size_t o_qlen = align256(sizeof(snn::Ctl));
+  const size_t o_queue = o_qlen + align256((size_t)steps * snn::kQueueGroups * snn::kQlenStride * 4);
+  const size_t o_input = o_queue + align256((size_t)steps * net->queue_stride * 4);
+  const size_t o_ids = o_input + align256((size_t)net->n_inbuf * net->n * 4);
+  const size_t need = o_ids + align256((size_t)n_ids * 4);
+  if (need > kStaticScratchBytes)
+    fail(SNN_E_INVALID, "this window needs " + std::to_string(need) + " bytes of device scratch; the static scratch holds " +
+                            std::to_string(kStaticScratchBytes));
+  const StaticScratch sc = static_scratch(net->device);
+  hipStream_t s = net->stream;
+  snn::Ctl *ctl = reinterpret_cast<snn::Ctl *>(sc.ptr);
+  st.q = snn::QueueRef{reinterpret_cast<int32_t *>(sc.ptr + o_queue), reinterpret_cast<uint32_t *>(sc.ptr + o_qlen),
+                       net->queue_stride, net->group_cap};
+  st.ctl = ctl;
+  st.input = reinterpret_cast<int32_t *>(sc.ptr + o_input);
+  st.n_input = (uint64_t)net->n_inbuf * net->n;
+  st.ids = reinterpret_cast<const int32_t *>(sc.ptr + o_ids);
+  // slots 0..steps-1 are the queues delivered by a window starting at t0 when
+  // t0 + n_inbuf - delay = 0 (mod slots)
+  st.t_deliver = (uint64_t)net->delay - net->n_inbuf;
+  if (n_ids)
+    check(hipMemcpyAsync(sc.ptr + o_ids, ids, (size_t)n_ids * 4, hipMemcpyHostToDevice, s), "ids");
+  check(snn::launch_stage_window(st, s), "stage window");
+  snn::DeliverArgs d = deliver_args(net);
+  d.q = st.q;
+  d.input = st.input;
+  d.ctl = ctl;
+  d.advance = 0;
+  check(launch_delivery(net, d, steps), "warm-up delivery");
+  for (uint32_t r = 0; r < reps; ++r) {
+    snn::LaunchEvents ev;
+    if (r == 0) ev.start = sc.start;
+    if (r + 1 == reps) ev.stop = sc.stop;
+    check(launch_delivery(net, d, steps, ev), "delivery");
+  }
+  uint64_t parts[snn::kCounterParts];
+  check(hipMemcpy2DAsync(parts, sizeof(uint64_t), ctl->events, snn::kLineU64 * sizeof(uint64_t), sizeof(uint64_t),
+                         snn::kCounterParts, hipMemcpyDeviceToHost, s),
+        "event counters");
+  check(hipStreamSynchronize(s), "sync");
+  float ms = 0.f;
+  check(hipEventElapsedTime(&ms, sc.start, sc.stop), "elapsed");
+  uint64_t total = 0;
+  for (uint64_t x : parts) total += x;
+  if (events) *events = total / (reps + 1);
+  return (double)ms / reps;
+}
+
 // Times every candidate delivery configuration on the spikes of the latest window (read
 // from the raster ring) and keeps the fastest.
 snn_delivery_tuning autotune_delivery(snn_network *net, uint32_t reps) {
@@ -1820,6 +1938,17 @@ snn_status snn_time_delivery(snn_network *net, const uint32_t *ids_host, uint32_
     uint64_t ev = 0;
     *avg_ms = time_delivery(net, per_step, reps, &ev);
     if (events) *events = ev;
+  });
+}
+
+snn_status snn_time_delivery_static(snn_network *net, const uint32_t *ids_host, uint32_t n_ids,
+                                    const uint32_t *step_counts, uint32_t steps, uint32_t reps,
+                                    double *avg_ms, uint64_t *events) {
+  return guarded([&] {
+    if (!net || (!ids_host && n_ids) || !avg_ms) fail(SNN_E_INVALID, "null argument");
+    refuse_member(net);
+    if (steps == 0) steps = net->window;
+    *avg_ms = time_delivery_static(net, ids_host, n_ids, step_counts, steps, reps, events);
   });
 }
 

@@ -248,6 +248,20 @@ hipError_t launch_lazy(const LazyArgs &a, uint32_t grid, hipStream_t s, const La
 // Brings every plastic row current at step boundary t (pending potentiation applied,
 // age t, trace at age rebuilt from x_pre and the arrivals of step t).
 hipError_t launch_lazy_flush(const LazyArgs &a, uint64_t t, uint32_t grid, hipStream_t s);
+// One window's queues staged from a caller's spike list (k_stage_window): step w's
+// ids are ids[off[w] .. off[w+1]), or dealt round-robin over the steps when
+// round_robin is set (off then still holds each step's count as a prefix).
+struct StageArgs {
+  QueueRef q;             // `steps` slots
+  Ctl *ctl;
+  int32_t *input;         // n_input accumulators, cleared
+  const int32_t *ids;
+  uint64_t n_input;
+  uint64_t t_deliver;
+  uint32_t n_ids, steps, round_robin;
+  uint32_t off[65];       // steps <= 64
+};
+hipError_t launch_stage_window(const StageArgs &a, hipStream_t s);
 hipError_t launch_row_lengths(const GenArgs &g, uint32_t *len, uint32_t *plast_rel,
                               uint32_t *plast_len, hipStream_t s);
 hipError_t launch_fill_rows(const GenArgs &g, uint32_t max_fixed_k, const uint64_t *row_ptr,

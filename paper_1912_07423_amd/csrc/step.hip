@@ -944,6 +944,39 @@ __global__ __launch_bounds__(kLazyBlock) void k_lazy_flush(LazyArgs a, uint64_t 
   lazy_commit(a, c);
 }
 
+// Stages a caller's spike list as one window's queues for a delivery launch (the
+// delivery-timing entry points): position p of step w goes to sub-queue
+// p mod kQueueGroups at index p / kQueueGroups, as the update kernel's appends would
+// lay it out.  Step w's ids are ids[off[w] .. off[w+1]), or, with round_robin, every
+// id k with k mod steps = w (position k / steps).  Also sets every (step, sub-queue)
+// counter of the window, zeroes the control block (then sets t_deliver) and clears the
+// n_input accumulators.  Grid-stride over each part; the parts are disjoint.
+__global__ __launch_bounds__(256) void k_stage_window(StageArgs a) {
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t nthreads = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = tid; k < a.n_ids; k += nthreads) {
+    uint32_t w, p;
+    if (a.round_robin) {
+      w = (uint32_t)(k % a.steps);
+      p = (uint32_t)(k / a.steps);
+    } else {
+      w = 0;  // last w with off[w] <= k
+      while (w + 1 < a.steps && a.off[w + 1] <= k) ++w;
+      p = (uint32_t)(k - a.off[w]);
+    }
+    a.q.ids[(size_t)w * a.q.stride + (size_t)(p % kQueueGroups) * a.q.group_cap + p / kQueueGroups] = a.ids[k];
+  }
+  for (uint64_t j = tid; j < (uint64_t)a.steps * kQueueGroups; j += nthreads) {
+    const uint32_t w = (uint32_t)(j / kQueueGroups), g = (uint32_t)(j % kQueueGroups);
+    const uint32_t c = a.off[w + 1] - a.off[w];
+    a.q.qlen[j * kQlenStride] = c > g ? (c - g + kQueueGroups - 1) / kQueueGroups : 0u;
+  }
+  uint64_t *ctl = reinterpret_cast<uint64_t *>(a.ctl);
+  for (uint64_t j = tid; j < sizeof(Ctl) / sizeof(uint64_t); j += nthreads)
+    ctl[j] = j == offsetof(Ctl, t_deliver) / sizeof(uint64_t) ? a.t_deliver : 0ull;
+  for (uint64_t j = tid; j < a.n_input; j += nthreads) a.input[j] = 0;
+}
+
 }  // namespace
 
 // One launch, through hipExtLaunchKernel when timing events are requested.
@@ -1042,6 +1075,11 @@ hipError_t launch_lazy(const LazyArgs &a, uint32_t grid, hipStream_t s, const La
 
 hipError_t launch_lazy_flush(const LazyArgs &a, uint64_t t, uint32_t grid, hipStream_t s) {
   k_lazy_flush<<<grid, kLazyBlock, 0, s>>>(a, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_window(const StageArgs &a, hipStream_t s) {
+  k_stage_window<<<1024, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

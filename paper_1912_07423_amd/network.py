@@ -277,6 +277,19 @@ class Network:
                                             C.byref(ms), C.byref(ev)))
         return ms.value, ev.value
 
+    def time_delivery_static(self, ids, reps=10, steps=0, step_counts=None):
+        """time_delivery with every device buffer in the library's fixed device array (no
+        device allocation; the mean runs over back-to-back launches)."""
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        counts = None if step_counts is None else np.ascontiguousarray(step_counts, dtype=np.uint32)
+        if counts is not None and steps == 0:
+            steps = len(counts)
+        ms = C.c_double()
+        ev = C.c_uint64()
+        L.check(self._lib.snn_time_delivery_static(self._h, _ptr(ids), len(ids), _ptr(counts), steps, reps,
+                                                   C.byref(ms), C.byref(ev)))
+        return ms.value, ev.value
+
 
 class Batch:
     """Many independent static networks stepped together by one persistent launch per
