@@ -281,8 +281,8 @@ typedef struct {
     uint64_t events_per_launch;             /* synaptic events of the sample */
 } snn_delivery_tuning;
 
-/* Time the atomic variant and the tiled one over base tiles of about 3072, 4608 and
- * 6144 targets x 512/1024-thread workgroups x 1, 2 and 3 workgroups per CU, each on the
+/* Time the atomic variant and the tiled one over base tiles of about 384, 576 and
+ * 768 targets (ranges of up to 32) x 512/1024-thread workgroups x 1, 2 and 3 workgroups per CU, each on the
  * spikes of the network's latest window (taken from its raster), `reps` launches each;
  * keep the fastest and return it.  The simulation state is unchanged.  SNN_E_STATE if
  * fewer than `window` steps have run. */

@@ -88,6 +88,22 @@ __device__ __forceinline__ T wave_inclusive_scan(T x) {
   return x;
 }
 
+// 32-bit inclusive scan over the wave by DPP lane shifts (one VALU operation per step
+// instead of an LDS permute): shifts by 1, 2, 4 and 8 inside each row of 16 lanes, then
+// the last lane of rows 0 and 2 added into rows 1 and 3, then lane 31 into rows 2 and 3.
+// Every lane of the wave must be active.
+template <>
+__device__ __forceinline__ uint32_t wave_inclusive_scan<uint32_t>(uint32_t x) {
+  int v = (int)x;
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false); // row_bcast:15, rows 1 and 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false); // row_bcast:31, rows 2 and 3
+  return (uint32_t)v;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T x) {
 #pragma unroll

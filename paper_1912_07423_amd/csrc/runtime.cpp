@@ -338,20 +338,24 @@ void choose_delivery(snn_network *net) {
     // largest base tile is set by the workgroup LDS limit (160 KB on gfx950, less the
     // kernel's static arrays); the default base tile is kDefaultTile targets, so that a
     // range holds up to 18,432 targets (the fastest range size of the launch-shape sweep
-    // on the 1e9-synapse network, with 1,024-thread workgroups and one per CU).
+    // on the 1e9-synapse network, with 1,024-thread workgroups and one per CU).  Small
+    // base tiles let the schedule size ranges in steps of 1/32 of that.
     size_t lds_dyn = 0;
     check(snn::prepare_deliver_tiled(net->block, &lds_dyn), "tiled delivery LDS limit");
-    const uint32_t tile_cap = (uint32_t)(lds_dyn / 4 / snn::kTileGroupMax);
-    constexpr uint32_t kDefaultTile = 2304;
-    const uint32_t min_tiles = (net->n + tile_cap - 1) / tile_cap;
+    // a range's accumulators fit the LDS, and the delivery reads 16-bit targets, which
+    // identify a target only inside a range of fewer than 65,536 targets
+    const uint64_t range_cap = std::min<uint64_t>(lds_dyn / 4, 65535);
+    constexpr uint32_t kDefaultTile = 576;
+    const uint32_t tile_cap = (uint32_t)(range_cap / snn::kTileGroupMax);
+    const uint32_t min_tiles = net->n <= range_cap ? 1u : (net->n + tile_cap - 1) / tile_cap;
     uint32_t tiles = net->prm.tiles ? net->prm.tiles : (net->n + kDefaultTile - 1) / kDefaultTile;
     tiles = std::max(std::min(tiles, std::max(1u, net->n / 16u)), min_tiles);
-    net->tile_size = (net->n + tiles - 1) / tiles;
+    // a multiple of 4 targets, so that ranges start on 16-byte boundaries of a row of
+    // accumulators (the range flush then stores 16 bytes at a time)
+    net->tile_size = ((net->n + tiles - 1) / tiles + 3) & ~3u;
     net->tiles = (net->n + net->tile_size - 1) / net->tile_size;
-    if (net->tile_size > tile_cap) fail(SNN_E_INVALID, "tile too large for LDS");
-    // the delivery reads 16-bit targets, which identify a target only inside a range of
-    // fewer than 65,536 targets
-    if ((uint64_t)net->tile_size * snn::kTileGroupMax >= 65536) fail(SNN_E_INVALID, "tile range reaches 65,536 targets");
+    if ((uint64_t)std::min(net->tiles, snn::kTileGroupMax) * net->tile_size > range_cap)
+      fail(SNN_E_INVALID, "tile range too large for LDS or for 16-bit targets");
     // one 1,024-thread workgroup per CU (the kernel's registers allow one resident)
     net->grid = net->prm.grid ? net->prm.grid : net->cu_count * (net->block == 1024 ? 1u : 2u);
   } else if (net->delivery == SNN_DELIVERY_ATOMIC) {
@@ -1200,7 +1204,7 @@ snn_delivery_tuning autotune_delivery(snn_network *net, uint32_t reps) {
   std::vector<Cand> cands;
   cands.push_back({SNN_DELIVERY_ATOMIC, 0, 0, 0});
   if (!net->plastic && net->n >= 1024) {
-    for (uint32_t tile : {1536u, 2304u, 3072u})
+    for (uint32_t tile : {384u, 576u, 768u})
       for (uint32_t block : {512u, 1024u})
         for (uint32_t grid : {net->cu_count, 2 * net->cu_count, 3 * net->cu_count})
           cands.push_back({SNN_DELIVERY_TILED, std::max(1u, (net->n + tile - 1) / tile), block, grid});

@@ -240,7 +240,7 @@ hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t 
                                  hipStream_t s, const LaunchEvents &ev = {});
 hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t block,
                                 uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});
-constexpr uint32_t kTileGroupMax = 8;  // base tiles one tiled-delivery workgroup may own
+constexpr uint32_t kTileGroupMax = 32;  // base tiles one tiled-delivery workgroup may own
 hipError_t prepare_deliver_tiled(uint32_t block, size_t *max_dynamic_lds);
 hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});
 hipError_t launch_stdp_ltd(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});

@@ -377,7 +377,9 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
 // 16-byte groups per lane per batch (8 targets each; with weights stored per synapse,
 // also their 32 bytes of weights).  A wave's share of a step is short (about 14 groups
 // per lane on the 1e9-synapse network), so two per batch, with the next two in flight,
-// beat three or four: the last, partly filled batch is shorter.
+// beat three or four: the last, partly filled batch is shorter.  Three or four batches
+// in flight instead of two measured no faster: the stream then runs at the rate the
+// memory system gives pieces of a few hundred bytes at random addresses.
 template <bool kSrcW>
 constexpr int tiled_groups() { return 2; }
 
@@ -441,100 +443,66 @@ __device__ __forceinline__ void tiled_accumulate(int32_t *acc, const TiledGroup 
 }
 
 // Balanced schedule of one window, derived by every workgroup from the step counts
-// c_w: step w is cut into ceil(P / m_w) target ranges of m_w consecutive base tiles,
-// one workgroup each, with m_w in [1, kTileGroupMax].  The work of a range is about
-// c_w * m_w sub-rows; the schedule takes the smallest bound X on it for which the
-// ranges fit the grid, m_w = clamp(X / c_w, 1, kTileGroupMax).
+// c_w with the same operations on the same values, so that all derive one schedule.
+// Step w is cut into r_w ranges of consecutive base tiles, one workgroup each; range j
+// covers tiles [floor(j P / r_w), floor((j + 1) P / r_w)) of the P tiles.  A range's
+// work is about c_w P / r_w sub-rows, so the schedule takes
+//   r_w(X) = clamp(ceil(c_w P / X), r_min, P),   r_min = ceil(P / kTileGroupMax),
+// for (close to) the smallest work bound X at which sum_w r_w(X) fits the grid.  r_min
+// keeps every range within kTileGroupMax tiles (the LDS accumulators); the host sizes
+// the grid to at least steps * r_min, where an infinite X (every r_w = r_min) fits.
 struct TileSchedule {
-  uint32_t m[kWave];          // base tiles per range, per step
-  uint32_t first[kWave + 1];  // first workgroup of each step
+  uint32_t r[kWave];          // ranges of each step
+  uint32_t first[kWave + 1];  // first work unit of each step
 };
 
-// Scaled reciprocal of a step count, for group_for (0 for an empty step).  The factor
-// 1 + 2^-40 keeps an exact quotient x / c = m from rounding down to m - 1: for c < 2^32
-// and quotients below kTileGroupMax + 1 the product's floor is then the exact one.
-__device__ __forceinline__ double schedule_inv(uint32_t c) {
-  return c ? (1.0 + 0x1p-40) / (double)c : 0.0;
+// r_w at the bound X = 1 / inv_x (inv_x = 0: X infinite) for work = c_w * P.
+__device__ __forceinline__ uint32_t ranges_at(float work, float inv_x, uint32_t r_min, uint32_t tiles) {
+  const float q = ceilf(work * inv_x);
+  return (uint32_t)fminf(fmaxf(q, (float)r_min), (float)tiles);
 }
 
-// Base tiles per range of a step under the work bound x: clamp(floor(x / c), 1,
-// kTileGroupMax), with inv = schedule_inv(c); an empty step takes maximal ranges.
-// Every workgroup evaluates the same operations on the same counts, so all derive one
-// schedule; any m in [1, kTileGroupMax] still covers every tile.
-__device__ __forceinline__ uint32_t group_for(uint64_t x, double inv) {
-  if (inv == 0.0) return kTileGroupMax;
-  const double q = fmin(fmax((double)x * inv, 1.0), (double)kTileGroupMax);
-  return (uint32_t)q;
-}
-
-// ceil(P / m) for the range sizes m = 1..8, uniform (scalar registers).
-struct RangeCounts {
-  uint32_t r1, r2, r3, r4, r5, r6, r7, r8;
-};
-static_assert(kTileGroupMax == 8, "RangeCounts holds one count per range size");
-
-__device__ __forceinline__ RangeCounts range_counts(uint32_t tiles) {
-  RangeCounts r;
-  r.r1 = tiles;
-  r.r2 = (tiles + 1) / 2;
-  r.r3 = (tiles + 2) / 3;
-  r.r4 = (tiles + 3) / 4;
-  r.r5 = (tiles + 4) / 5;
-  r.r6 = (tiles + 5) / 6;
-  r.r7 = (tiles + 6) / 7;
-  r.r8 = (tiles + 7) / 8;
-  return r;
-}
-
-// The count for a per-lane m in [1, 8], by a select tree on the bits of m - 1 (VALU only:
-// no table in memory).
-__device__ __forceinline__ uint32_t ranges_of(uint32_t m, const RangeCounts &r) {
-  const uint32_t k = m - 1;
-  const bool b0 = k & 1u, b1 = k & 2u, b2 = k & 4u;
-  const uint32_t t0 = b0 ? r.r2 : r.r1, t1 = b0 ? r.r4 : r.r3;
-  const uint32_t t2 = b0 ? r.r6 : r.r5, t3 = b0 ? r.r8 : r.r7;
-  const uint32_t u0 = b1 ? t1 : t0, u1 = b1 ? t3 : t2;
-  return b2 ? u1 : u0;
-}
-
-// Smallest feasible work bound, searched by the whole workgroup.  Thread t scores the pair
-// (candidate bound x_k = c_w' * m, step w), with w = t mod S (S = steps rounded up to a
-// power of two) and one candidate per group of S lanes: the ranges of step w under x_k.
-// A sum over the S lanes gives need(x_k), the ranges all steps take; the smallest x_k with
-// need(x_k) <= grid is taken by an LDS minimum into *s_best (~0 if none: every step then
-// takes maximal ranges, which the host sizes the grid for).
-template <int kBlock>
-__device__ void schedule_bound(const uint32_t *s_cnt, uint32_t steps, uint32_t tiles, uint32_t grid,
-                               unsigned long long *s_best) {
-  uint32_t S = 1;
-  while (S < steps) S <<= 1;
-  const uint32_t w = threadIdx.x & (S - 1), slot = threadIdx.x / S, per_round = kBlock / S;
-  const RangeCounts rc = range_counts(tiles);
-  const double iw = schedule_inv(w < steps ? s_cnt[w] : 0u);
-  const uint32_t cands = steps * kTileGroupMax;
-  uint64_t best = ~0ull;
-  for (uint32_t k0 = 0; k0 < cands; k0 += per_round) {
-    const uint32_t k = k0 + slot;
-    const bool live = k < cands;
-    const uint64_t x = live ? (uint64_t)s_cnt[k / kTileGroupMax] * (k % kTileGroupMax + 1) : 0ull;
-    uint32_t need = w < steps ? ranges_of(group_for(x, iw), rc) : 0u;
-    for (uint32_t d = S >> 1; d > 0; d >>= 1) need += (uint32_t)__shfl_xor((int)need, (int)d, (int)S);
-    if (live && need <= grid && x < best) best = x;
+// sum_w r_w at this lane's bound; c is lane w's count (zero past `steps`).
+__device__ __forceinline__ uint32_t ranges_needed(uint32_t c, uint32_t steps, float p_f, float inv_x,
+                                                  uint32_t r_min, uint32_t tiles) {
+  uint32_t sum = 0;
+  for (uint32_t w = 0; w < steps; ++w) {
+    const float work = (float)(uint32_t)__builtin_amdgcn_readlane((int)c, (int)w) * p_f;
+    sum += ranges_at(work, inv_x, r_min, tiles);
   }
-  if (w == 0 && best != ~0ull) atomicMin(s_best, (unsigned long long)best);
+  return sum;
 }
 
-// Wave 0: lane w takes the tiles per range and the range count of step w under the bound;
-// their prefix over the steps gives each step's first workgroup.
-__device__ void make_schedule(uint32_t c, uint64_t best, uint32_t tiles, uint32_t steps, TileSchedule &sch) {
+// Wave 0 (lane w holds c_w, zero past `steps`): the bound by two parallel rounds over
+// the 64 lanes, then each step's range count and their prefix.  Round 1 tries
+// X_j = X_lb 2^(j/4), X_lb = sum_w c_w P / grid (below it no schedule fits unless ranges
+// are clamped to single tiles; round 2 then still finds the bound); round 2 tries 64
+// evenly spaced bounds in (X_{j-1}, X_j] for the first feasible X_j, the last being X_j
+// itself.  Without a feasible X_j every step takes r_min ranges.
+__device__ void make_schedule(uint32_t c, uint32_t steps, uint32_t tiles, uint32_t grid, TileSchedule &sch) {
   const uint32_t lane = lane_id();
-  uint32_t g = 0, r = 0;
-  if (lane < steps) {
-    g = best == ~0ull ? kTileGroupMax : group_for(best, schedule_inv(c));
-    r = ranges_of(g, range_counts(tiles));
+  const uint32_t r_min = (tiles + kTileGroupMax - 1) / kTileGroupMax;
+  const float p_f = (float)tiles;
+  const uint32_t total = wave_sum(c);
+  float inv_best = 0.f;
+  if (total > 0 && grid > steps * r_min) {
+    const float x_lb = (float)total * p_f / (float)grid;
+    const float x1 = x_lb * exp2f(0.25f * (float)lane);
+    const uint64_t ok1 = __ballot(ranges_needed(c, steps, p_f, 1.0f / x1, r_min, tiles) <= grid);
+    if (ok1) {
+      const uint32_t j = (uint32_t)__builtin_ctzll(ok1);
+      const float hi = x_lb * exp2f(0.25f * (float)j);
+      const float lo = j ? x_lb * exp2f(0.25f * (float)(j - 1)) : 0.f;
+      const float x2 = lane == kWave - 1 ? hi : lo + (hi - lo) * ((float)(lane + 1) * (1.0f / kWave));
+      const float inv2 = 1.0f / x2;
+      const uint64_t ok2 = __ballot(ranges_needed(c, steps, p_f, inv2, r_min, tiles) <= grid);
+      const uint32_t k = ok2 ? (uint32_t)__builtin_ctzll(ok2) : kWave - 1;  // lane 63 fits: x2 = X_j
+      inv_best = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(inv2), (int)k));
+    }
   }
+  const uint32_t r = lane < steps ? ranges_at((float)c * p_f, inv_best, r_min, tiles) : 0u;
   const uint32_t incl = wave_inclusive_scan(r);
-  sch.m[lane] = g;
+  sch.r[lane] = r;
   sch.first[lane + 1] = incl;
   if (lane == 0) sch.first[0] = 0;
 }
@@ -562,7 +530,7 @@ __device__ __forceinline__ uint32_t xcd_unit(uint32_t b, uint32_t grid, uint32_t
 // the next batch's loads issued before the current batch's LDS atomics.
 template <int kBlock, bool kSrcW>
 __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_t steps) {
-  extern __shared__ int32_t acc[];
+  extern __shared__ __align__(16) int32_t acc[];
   constexpr int kWaves = kBlock / kWave;
   constexpr int kU = tiled_groups<kSrcW>();
   __shared__ uint64_t s_lo[kBlock];
@@ -571,17 +539,16 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
   __shared__ int32_t s_w[kSrcW ? kBlock : 1];
   __shared__ unsigned long long s_ev;
   __shared__ uint32_t s_wave[kWaves];
-  __shared__ uint32_t s_cnt[kWave];
   __shared__ uint32_t s_qpre[kWave][kQueueGroups + 1];
   __shared__ uint32_t s_slot[kWave];
-  __shared__ unsigned long long s_best;
   __shared__ TileSchedule sch;
-  const uint64_t t0 = a.ctl->t_deliver;
-  close_window(a, t0, steps);
   const uint32_t lane = lane_id();
   const uint32_t wave = threadIdx.x / kWave;
+  const uint64_t t0 = a.ctl->t_deliver;
+  close_window(a, t0, steps);
 
-  // ---- the window's queue lengths and the balanced schedule ----
+  // ---- the window's queue lengths and the balanced schedule (wave 0), while the
+  // other waves clear the accumulators ----
   if (wave == 0) {
     uint32_t qp[kQueueGroups + 1] = {};
     uint32_t slot = 0;
@@ -593,22 +560,19 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
     s_slot[lane] = slot;
 #pragma unroll
     for (uint32_t g = 0; g <= kQueueGroups; ++g) s_qpre[lane][g] = qp[g];
-    s_cnt[lane] = qp[kQueueGroups];
-    if (lane == 0) s_best = ~0ull;
+    make_schedule(qp[kQueueGroups], steps, a.tiles, gridDim.x, sch);
+  } else {
+    const uint32_t acc_n = min(kTileGroupMax, a.tiles) * a.tile_size;
+    for (uint32_t j = threadIdx.x - kWave; j < acc_n; j += kBlock - kWave) acc[j] = 0;
   }
-  __syncthreads();
-  for (uint32_t j = threadIdx.x; j < kTileGroupMax * a.tile_size; j += kBlock) acc[j] = 0;
-  schedule_bound<kBlock>(s_cnt, steps, a.tiles, gridDim.x, &s_best);
-  __syncthreads();
-  if (wave == 0) make_schedule(lane < steps ? s_cnt[lane] : 0u, s_best, a.tiles, steps, sch);
   __syncthreads();
   const uint32_t unit = xcd_unit(blockIdx.x, gridDim.x, sch.first[steps]);
   if (unit >= sch.first[steps]) return;  // more workgroups than ranges this window
   uint32_t w = 0;
   while (sch.first[w + 1] <= unit) ++w;
-  const uint32_t m = sch.m[w];
-  const uint32_t tile_a = (unit - sch.first[w]) * m;
-  const uint32_t tile_b = min(tile_a + m, a.tiles);
+  const uint32_t r_w = sch.r[w], jr = unit - sch.first[w];
+  const uint32_t tile_a = (uint32_t)((uint64_t)jr * a.tiles / r_w);
+  const uint32_t tile_b = (uint32_t)((uint64_t)(jr + 1) * a.tiles / r_w);
   const uint32_t tile_lo = tile_a * a.tile_size;
   const uint32_t tile_n = min(tile_b * a.tile_size, a.n) - tile_lo;
 
@@ -697,7 +661,15 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
   if (lane == 0 && ev) atomicAdd(&s_ev, (unsigned long long)ev);
   __syncthreads();
   int32_t *out = a.input + (size_t)ring_add((uint32_t)(t0 % a.n_inbuf), w, a.n_inbuf) * a.n + tile_lo;
-  for (uint32_t j = threadIdx.x; j < tile_n; j += kBlock) out[j] = acc[j];
+  if ((reinterpret_cast<uintptr_t>(out) & 15u) == 0) {
+    // 16-byte stores over whole quads (acc is 16-byte aligned), the rest one by one
+    const uint32_t quads = tile_n / 4;
+    for (uint32_t j = threadIdx.x; j < quads; j += kBlock)
+      reinterpret_cast<int4 *>(out)[j] = reinterpret_cast<const int4 *>(acc)[j];
+    for (uint32_t j = 4 * quads + threadIdx.x; j < tile_n; j += kBlock) out[j] = acc[j];
+  } else {
+    for (uint32_t j = threadIdx.x; j < tile_n; j += kBlock) out[j] = acc[j];
+  }
   if (threadIdx.x == 0) {
     add_part(a.ctl->events, blockIdx.x, s_ev);
     if (tile_a == 0) add_part(a.ctl->spikes, blockIdx.x, cnt);
@@ -1038,7 +1010,7 @@ hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t b
   // the schedule always fits when every step uses maximal ranges
   const uint32_t floor_grid = steps * ((a.tiles + kTileGroupMax - 1) / kTileGroupMax);
   if (grid < floor_grid) grid = floor_grid;
-  const size_t lds = (size_t)kTileGroupMax * a.tile_size * sizeof(int32_t);
+  const size_t lds = (size_t)min(kTileGroupMax, a.tiles) * a.tile_size * sizeof(int32_t);
   const bool src_w = a.w_src != nullptr;
   switch (block) {
     case 256:

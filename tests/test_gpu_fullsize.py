@@ -44,7 +44,7 @@ def test_brunel_200k_1e9_synapses():
     print(f"[full] brunel_fixed_out n=200000 k=5000: {steps} steps", flush=True)
     rg, inf = compare_run(spec, steps, raster_steps=4096)
     assert inf["nnz"] == 200_000 * 5000
-    assert inf["delivery"] == 2 and inf["tiles"] == 87 and inf["window"] == 15 and inf["source_weights"] == 1
+    assert inf["delivery"] == 2 and inf["tiles"] == 348 and inf["window"] == 15 and inf["source_weights"] == 1
     assert inf["tile_offset_bytes"] == 2
     print(f"[full] brunel: {int(np.unpackbits(rg.view(np.uint8)).sum())} spikes, "
           f"{inf['events']} events", flush=True)

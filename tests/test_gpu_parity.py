@@ -118,8 +118,8 @@ def test_tiled_wide_tile_offsets():
     synapses, so the tile boundaries are stored as 4-byte offsets."""
     spec = W.cuba_lif_4k(n_exc=66_000, n_inh=4_000, p=0.001, steps=100)
     print("[tiles] 4-byte boundaries, n=70000", flush=True)
-    rg, inf = _compare_run(spec, 100, delivery="tiled", tiles=40)
-    assert inf["tile_offset_bytes"] == 4 and inf["tiles"] == 40
+    rg, inf = _compare_run(spec, 100, delivery="tiled", tiles=70)
+    assert inf["tile_offset_bytes"] == 4 and inf["tiles"] == 70
     assert rg.any()
 
 
