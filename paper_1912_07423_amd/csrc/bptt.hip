@@ -101,32 +101,60 @@ __device__ __forceinline__ float ordered_gather_sum(float acc, uint64_t e0, uint
   return acc;
 }
 
-// The same ordered sum for the per-step kernels, where one wavefront per neuron is all
-// the parallelism a step has and each memory round trip is on the critical path: the
-// edges are taken kWide at a time, their sources and weights read by the lanes (two
-// edges per lane), and all kWide presynaptic values requested before the first term is
-// added.  The terms are added one at a time in edge order, exactly as above.
-constexpr int kWide = 128;
-__device__ __forceinline__ float ordered_gather_wide(float acc, uint64_t e0, uint64_t e1, const int32_t *src,
+// The same ordered sum with two chunks of presynaptic values in flight: the values of
+// chunk c + 1 are requested before the terms of chunk c are added, so that a chunk costs
+// about half a memory round trip.  For the per-step kernels, where one wavefront per
+// neuron is all the parallelism a step has.
+__device__ __forceinline__ float ordered_gather_pipe(float acc, uint64_t e0, uint64_t e1, const int32_t *src,
                                                      const float *w, const float *val, uint32_t b) {
-  for (uint64_t e = e0; e < e1; e += kWide) {
-    const uint32_t n = (uint32_t)min((uint64_t)kWide, e1 - e);  // wave-uniform
-    const int32_t s0 = b < n ? src[e + b] : 0, s1 = b + 64 < n ? src[e + 64 + b] : 0;
-    const float w0 = b < n ? w[e + b] : 0.0f, w1 = b + 64 < n ? w[e + 64 + b] : 0.0f;
-    float xv[kWide];
+  uint64_t e = e0;
+  if (e + 2 * kChunk <= e1) {
+    int32_t sa[kChunk], sb[kChunk];
+    float wa[kChunk], wb[kChunk], xa[kChunk], xb[kChunk];
 #pragma unroll
-    for (int k = 0; k < kWide; ++k) {
-      const int32_t sk = __builtin_amdgcn_readlane(k < 64 ? s0 : s1, k & 63);
-      xv[k] = (uint32_t)k < n ? val[(size_t)sk * 64 + b] : 0.0f;
+    for (int u = 0; u < kChunk; ++u) {
+      sa[u] = src[e + u];
+      wa[u] = w[e + u];
     }
 #pragma unroll
-    for (int k = 0; k < kWide; ++k) {
-      if ((uint32_t)k < n) {
-        const float wk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(k < 64 ? w0 : w1), k & 63));
-        acc = acc + wk * xv[k];
+    for (int u = 0; u < kChunk; ++u) xa[u] = val[(size_t)sa[u] * 64 + b];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      sb[u] = src[e + kChunk + u];
+      wb[u] = w[e + kChunk + u];
+    }
+    // invariant: chunk e is in (wa, xa), chunk e + kChunk (whole) has its sources in sb
+    while (true) {
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) xb[u] = val[(size_t)sb[u] * 64 + b];
+      const bool more = e + 3 * kChunk <= e1;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          sa[u] = src[e + 2 * kChunk + u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) acc = acc + wa[u] * xa[u];
+      e += kChunk;
+      // chunk e is in (wb, xb)
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        wa[u] = wb[u];
+        xa[u] = xb[u];
+      }
+      if (!more) break;
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        sb[u] = sa[u];
+        wb[u] = w[e + kChunk + u];
       }
     }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) acc = acc + wa[u] * xa[u];
+    e += kChunk;
   }
+  for (; e < e1; ++e) acc = acc + w[e] * val[(size_t)src[e] * 64 + b];
   return acc;
 }
 
@@ -154,7 +182,7 @@ __global__ __launch_bounds__(256) void k_hidden_step(BpttArgs a, uint32_t t, con
   if (j >= a.H) return;
   const uint32_t b = lane_id();
   float acc = a.iin[((size_t)t * a.H + j) * 64 + b];
-  if (sprev) acc = ordered_gather_wide(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t, sprev, b);
+  if (sprev) acc = ordered_gather_pipe(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t, sprev, b);
   const float vp = vprev ? vprev[(size_t)j * 64 + b] : 0.0f;
   const float sp = sprev ? sprev[(size_t)j * 64 + b] : 0.0f;
   float v = a.beta * vp;
@@ -162,6 +190,41 @@ __global__ __launch_bounds__(256) void k_hidden_step(BpttArgs a, uint32_t t, con
   v = v - a.theta * sp;
   v_out[(size_t)j * 64 + b] = v;
   if (s_out) s_out[(size_t)j * 64 + b] = spike_fn(v - a.theta, a.slope, a.smooth != 0);
+}
+
+// Backward recomputation of one checkpoint segment [t0, t0 + len).  The spikes of every
+// step are stored, so the currents of all the segment's steps are independent: this
+// kernel computes them in parallel (a wavefront per (k, j)), each exactly as
+// k_hidden_step does (input part, then the recurrent in-edges over s_{t-1} in ascending
+// source order), into cur[k][j][b].
+__global__ __launch_bounds__(256) void k_seg_current(BpttArgs a, uint32_t t0, uint32_t len, float *cur) {
+  const uint64_t w = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (w >= (uint64_t)len * a.H) return;
+  const uint32_t k = (uint32_t)(w / a.H), j = (uint32_t)(w % a.H), t = t0 + k;
+  const uint32_t b = lane_id();
+  float acc = a.iin[((size_t)t * a.H + j) * 64 + b];
+  if (t > 0)
+    acc = ordered_gather_sum(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t,
+                             a.s + (size_t)(t - 1) * a.H * 64, b);
+  cur[w * 64 + b] = acc;
+}
+
+// ... then the membranes of the segment from the checkpoint before it (vprev; nullptr at
+// step 0), one lane per (j, b), with k_hidden_step's operations in its order; vseg[k]
+// holds the current of step t0 + k on entry and V_{t0+k} on return.
+__global__ void k_seg_scan(BpttArgs a, uint32_t t0, uint32_t len, const float *vprev, float *vseg) {
+  const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;  // j * 64 + b
+  if (x >= a.H * 64) return;
+  float v = vprev ? vprev[x] : 0.0f;
+  for (uint32_t k = 0; k < len; ++k) {
+    const uint32_t t = t0 + k;
+    const float sp = t ? a.s[(size_t)(t - 1) * a.H * 64 + x] : 0.0f;
+    float vn = a.beta * v;
+    vn = vn + vseg[(size_t)k * a.H * 64 + x];
+    vn = vn - a.theta * sp;
+    vseg[(size_t)k * a.H * 64 + x] = vn;
+    v = vn;
+  }
 }
 
 // Readout drive of every step: ro[t][o][b] = sum_i s[t][i][b] w_out[i][o], ascending i;
@@ -261,7 +324,7 @@ __global__ __launch_bounds__(256) void k_adjoint_step(BpttArgs a, uint32_t t, co
   const float *lu = a.lamu + (size_t)t * a.O * 64 + b;
   float ds = 0.0f;
   for (uint32_t o = 0; o < a.O; ++o) ds = ds + a.w_out[(size_t)i * a.O + o] * lu[(size_t)o * 64];
-  ds = ordered_gather_wide(ds, a.rec_ptr[i], a.rec_ptr[i + 1], a.rec_col, a.w_rec, lam_next, b);
+  ds = ordered_gather_pipe(ds, a.rec_ptr[i], a.rec_ptr[i + 1], a.rec_col, a.w_rec, lam_next, b);
   const float ln = lam_next[(size_t)i * 64 + b];
   if (!a.detach_reset) ds = ds - a.theta * ln;
   const float z = v_t[(size_t)i * 64 + b] - a.theta;
@@ -472,15 +535,12 @@ hipError_t bptt_backward_body(const BpttArgs &g, hipStream_t s) {
   for (int32_t seg = (int32_t)n_seg - 1; seg >= 0; --seg) {
     const uint32_t t0 = (uint32_t)seg * g.K, len = std::min(g.K, g.T - t0);
     // recompute the segment's membranes from the checkpoint before it and the stored
-    // spikes (the same kernel and operations as the forward pass)
+    // spikes (the forward pass's operations): all its currents at once, then the scan
     const float *vprev = seg ? g.vck + (size_t)(seg - 1) * g.H * 64 : nullptr;
-    for (uint32_t k = 0; k < len; ++k) {
-      const uint32_t t = t0 + k;
-      float *v_out = g.vseg + (size_t)k * g.H * 64;
-      const float *sprev = t ? g.s + (size_t)(t - 1) * g.H * 64 : nullptr;
-      hipLaunchKernelGGL(k_hidden_step, grid, dim3(256), 0, s, g, t, vprev, sprev, v_out, (float *)nullptr);
-      vprev = v_out;
-    }
+    hipLaunchKernelGGL(k_seg_current, dim3(blocks_for((uint64_t)len * g.H, 4)), dim3(256), 0, s, g, t0, len,
+                       g.vseg);
+    hipLaunchKernelGGL(k_seg_scan, dim3(blocks_for((uint64_t)g.H * 64, 256)), dim3(256), 0, s, g, t0, len, vprev,
+                       g.vseg);
     for (int32_t k = (int32_t)len - 1; k >= 0; --k) {
       const uint32_t t = t0 + (uint32_t)k;
       const float *lam_next = t + 1 < g.T ? g.lamv + (size_t)(t + 1) * g.H * 64 : g.lam_carry;
