@@ -15,12 +15,14 @@ paper's runs simulate 10 s).  Then `--warmup` untimed bench steps, then exactly
 `--steps` timed bench steps (defaults 1 and 5).
 
 Prints one JSON line: synaptic events/s over the timed steps (inputs resident in HBM,
-network built before the clock starts), wall time per simulated second, the delivery
-kernel's achieved HBM bandwidth (algorithmic bytes / mean launch duration, each timed
-launch stamped with its own begin and end by HIP events on the simulator's stream)
-against the 8 TB/s peak, its measured HBM traffic when a counter summary of the same
-kernel source at the same operating point exists under profiles/, and the CPU oracle's
-rate on a bounded sample of the same workload with the host it ran on.
+network built before the clock starts; the simulator runs as in production, windows
+replayed from captured HIP graphs), wall time per simulated second, the delivery
+kernel's achieved HBM bandwidth (algorithmic bytes / mean launch duration, from a pass
+of the same length that follows the timed region with every launch stamped by HIP
+events on the simulator's stream) against the 8 TB/s peak, its measured HBM traffic
+when a counter summary of the same kernel source at the same operating point exists
+under profiles/, and the CPU oracle's rate on a bounded sample of the same workload
+with the host it ran on.
 
 Other workloads (`--workload`, one JSON line each, not the headline):
   stdp   100,000-neuron plastic network (2e8 synapses, STDP on E->E), 2,000 steps
@@ -173,18 +175,15 @@ def bench_brunel(args):
     print(f"[bench] built in {build_s:.2f}s: {info}", file=sys.stderr, flush=True)
     K, Wb = args.steps, args.warmup
     sim_steps = K * SIM_STEPS
-    # every launch is stamped with its own begin and end (profiling); the warm-up runs the
-    # same way, so the timed run reuses its events
-    net.set_profiling(True)
     net.run(SETTLE_STEPS)
     net.run(Wb * SIM_STEPS)
     net.sync()
     W = info["window"]
-    before = launches_for(SETTLE_STEPS, W) + launches_for(Wb * SIM_STEPS, W)
-    print(f"[bench] settled {SETTLE_STEPS} + warm-up {Wb} x {SIM_STEPS} steps ({before} delivery launches); "
-          f"timing {K} x {SIM_STEPS} steps", file=sys.stderr, flush=True)
+    print(f"[bench] settled {SETTLE_STEPS} + warm-up {Wb} x {SIM_STEPS} steps; timing {K} x {SIM_STEPS} steps",
+          file=sys.stderr, flush=True)
 
-    net.reset_profile()
+    # (1) the timed region: the simulator as it runs in production, windows replayed from
+    # captured HIP graphs, no per-launch timing
     i0 = net.info()
     torch.cuda.synchronize()
     net.sync()
@@ -193,19 +192,34 @@ def bench_brunel(args):
     net.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    prof = net.profile()
     i1 = net.info()
-    net.set_profiling(False)
-
     events = i1["events"] - i0["events"]
     spikes = i1["spikes"] - i0["spikes"]
+
+    # (2) the kernel durations: the same number of steps again, continuing the run, every
+    # launch issued on its own and stamped with its begin and end by HIP events on the
+    # simulator's stream (stamping serialises the launches, which would add about 0.4 us
+    # per step to the timed region, so it gets a pass of its own)
+    before = (launches_for(SETTLE_STEPS, W) + launches_for(Wb * SIM_STEPS, W) +
+              launches_for(sim_steps, W))
+    net.set_profiling(True)
+    net.reset_profile()
+    j0 = net.info()
+    net.run(sim_steps)
+    net.sync()
+    prof = net.profile()
+    j1 = net.info()
+    net.set_profiling(False)
+    p_events = j1["events"] - j0["events"]
+    p_spikes = j1["spikes"] - j0["spikes"]
+
     dt_ms = spec["params"]["dt_ms"]
     launches = max(1, prof["deliver_launches"])
     deliver_avg_ms = prof["deliver_ms"] / launches
     b_ev, b_spk = delivery_bytes(info)
-    bytes_per_launch = (events * b_ev + spikes * b_spk) / launches
+    bytes_per_launch = (p_events * b_ev + p_spikes * b_spk) / launches
     achieved = bytes_per_launch / (deliver_avg_ms * 1e-3) / 1e9 if deliver_avg_ms > 0 else 0.0
-    print(f"[bench] {sim_steps} steps in {wall * 1e3:.3f} ms; {events} events; "
+    print(f"[bench] {sim_steps} steps in {wall * 1e3:.3f} ms; {events} events; stamped pass: "
           f"deliver {deliver_avg_ms * 1e3:.2f} us x {launches}; update "
           f"{prof['update_ms'] / max(1, prof['update_launches']) * 1e3:.2f} us x "
           f"{prof['update_launches']}", file=sys.stderr, flush=True)
@@ -230,7 +244,7 @@ def bench_brunel(args):
                    "host": host_info()}
     kernel = "k_deliver_tiled" if info["delivery_name"] == "tiled" else "k_deliver_atomic"
     point = {"workload": WORKLOAD, "settle_steps": SETTLE_STEPS, "warmup": Wb,
-             "steps": K, "sim_steps_per_step": SIM_STEPS, "events": events, "spikes": spikes,
+             "steps": K, "sim_steps_per_step": SIM_STEPS, "events": p_events, "spikes": p_spikes,
              "delivery": info["delivery_name"], "tiles": info["tiles"], "window": W,
              "delivery_launches": prof["deliver_launches"]}
     traffic = measured_traffic(point) if kernel == "k_deliver_tiled" else None
@@ -247,7 +261,10 @@ def bench_brunel(args):
          wall_s_per_sim_s=wall / sim_s, us_per_sim_step=wall * 1e6 / sim_steps, events=events,
          spikes_delivered=spikes, rate_hz=spikes / info["n"] / sim_s,
          build_s=build_s,
-         kernels={"deliver_ms_mean": deliver_avg_ms, "deliver_launches": prof["deliver_launches"],
+         kernels={"measured_over": f"a stamped pass of the same {sim_steps} steps following the timed region "
+                                   f"(every launch stamped by HIP events on the simulator's stream; "
+                                   f"{p_events} events)",
+                  "deliver_ms_mean": deliver_avg_ms, "deliver_launches": prof["deliver_launches"],
                   "update_ms_mean": prof["update_ms"] / max(1, prof["update_launches"]),
                   "update_launches": prof["update_launches"],
                   "delivery_launches_before_timed": before},
@@ -270,27 +287,33 @@ def bench_stdp(args):
     net.run(warm)
     net.sync()
     i0 = net.info()   # with lazy plasticity this brings every row current
-    net.set_profiling(True)
-    net.reset_profile()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    net.run(steps)
+    net.run(steps)    # launches replayed from captured HIP graphs, no per-launch timing
     i1 = net.info()   # the timed region ends with every row current (weights, touches)
     wall = time.perf_counter() - t0
-    prof = net.profile()
     events, touches = i1["events"] - i0["events"], i1["touches"] - i0["touches"]
-    spikes = i1["spikes"] - i0["spikes"]
+    # kernel durations: a second pass of the same length, every launch stamped
+    net.set_profiling(True)
+    net.reset_profile()
+    j0 = net.info()
+    net.run(steps)
+    j1 = net.info()
+    prof = net.profile()
+    net.set_profiling(False)
+    spikes = j1["spikes"] - j0["spikes"]
+    p_events = j1["events"] - j0["events"]
     dmean = prof["deliver_ms"] / max(1, prof["deliver_launches"])
     smean = prof["stdp_ms"] / max(1, prof["stdp_launches"])
     b_ev, b_spk = delivery_bytes(i1)
-    dbytes = (events * b_ev + spikes * b_spk) / max(1, prof["deliver_launches"])
+    dbytes = (p_events * b_ev + spikes * b_spk) / max(1, prof["deliver_launches"])
     # atomic throughput: one device-scope int32 add per synaptic event.  The run's rate
     # inside the delivery kernel, against the same kernel saturated by one step of
     # 20,000 spikes (about 4e7 events) over the same rows
     import numpy as np
     ids = np.random.default_rng(7).choice(i1["n"], 20_000, replace=False).astype(np.uint32)
     ms_sat, ev_sat = net.time_delivery(ids, reps=5, steps=1)
-    achieved = events / (prof["deliver_ms"] * 1e-3) if prof["deliver_ms"] > 0 else 0.0
+    achieved = p_events / (prof["deliver_ms"] * 1e-3) if prof["deliver_ms"] > 0 else 0.0
     saturated = ev_sat / (ms_sat * 1e-3) if ms_sat > 0 else 0.0
     line("STDP network: synaptic events/sec, STDP synapse touches/sec, 1 GPU", events / wall, "events/s",
          steps, warm, wall * 1e3 / steps, "fp32",
@@ -298,7 +321,8 @@ def bench_stdp(args):
           "delay_steps": i1["delay"], "delivery": i1["delivery_name"], "plasticity": args.plasticity,
           "parallelism": "single-gpu"},
          touches_per_s=touches / wall, events=events, touches=touches,
-         kernels={"deliver_ms_mean": dmean, "stdp_ms_mean": smean,
+         kernels={"measured_over": f"a stamped pass of the same {steps} steps following the timed region",
+                  "deliver_ms_mean": dmean, "stdp_ms_mean": smean,
                   "update_ms_mean": prof["update_ms"] / max(1, prof["update_launches"]),
                   "launches_per_kernel": prof["deliver_launches"]},
          roofline={"bound": "hbm", "achieved": dbytes / (dmean * 1e-3) / 1e9 if dmean > 0 else 0.0,
@@ -448,11 +472,12 @@ def bench_bptt(args):
 
 def summarize_pmc(fetch_dir, write_dir, lines, copy_mib, command):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) of
-    the same bench command into HBM bytes per tiled-delivery launch of its timed region,
+    the same bench command into HBM bytes per tiled-delivery launch of its stamped pass,
     each counter scaled by what it reads for the plain device copy of `copy_mib` MiB in
     the same run.  `lines` are the two runs' JSON lines: they must report the same
     operating point (the simulation is deterministic), which is recorded with the
-    summary, and they say which delivery dispatches precede the timed ones."""
+    summary, and they say how many delivery dispatches the stamped pass made (the run's
+    last ones)."""
     import csv
     import glob
 
@@ -460,7 +485,6 @@ def summarize_pmc(fetch_dir, write_dir, lines, copy_mib, command):
     points = [r["operating_point"] for r in recs]
     if points[0] != points[1]:
         raise SystemExit(f"the two runs differ: {points}")
-    skip = recs[0]["kernels"]["delivery_launches_before_timed"]
     timed = points[0]["delivery_launches"]
 
     def read(d, counter):
@@ -484,10 +508,12 @@ def summarize_pmc(fetch_dir, write_dir, lines, copy_mib, command):
         # runtime's copy kernel also serves the small copies of the simulator's setup)
         copies = sorted((v for k, v in rows if "copy" in k.lower()), reverse=True)[:3]
         deliver = [v for k, v in rows if "k_deliver_tiled" in k]
-        if len(copies) < 3 or len(deliver) < skip + timed:
-            raise SystemExit(f"{counter}: need 3 copy and {skip + timed} k_deliver_tiled dispatches, "
+        if len(copies) < 3 or len(deliver) < timed:
+            raise SystemExit(f"{counter}: need 3 copy and {timed} k_deliver_tiled dispatches, "
                              f"found {len(copies)} and {len(deliver)}")
-        deliver = deliver[skip:skip + timed]
+        # the stamped pass is the run's last delivery work (launches replayed from graphs
+        # before it may or may not be listed, so the count from the end is what is sure)
+        deliver = deliver[len(deliver) - timed:]
         copy_kib = copies[1]
         factor = known / (copy_kib * 1024.0)
         out[f"{key}_copy_kib"] = copy_kib

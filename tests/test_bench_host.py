@@ -39,14 +39,14 @@ def test_traffic_summary_scales_by_the_copy(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
     copy = "void at::native::direct_copy_kernel_cuda(...)"
     d = "snn::k_deliver_tiled<512>"
-    # the copy of 1 MiB reads 1024 KiB and the counter says 512: factor 2.  One delivery
-    # dispatch precedes the timed region, two are timed, one follows (not counted)
+    # the copy of 1 MiB reads 1024 KiB and the counter says 512: factor 2.  The stamped
+    # pass made the run's last two delivery dispatches; the ones before are not counted
     _csv(str(tmp_path / "f" / "x" / "run_counter_collection.csv"), "FETCH_SIZE",
-         [(copy, 512.0), (copy, 512.0), (copy, 512.0), (copy, 3.0), (d, 999.0), (d, 100.0),
-          (d, 300.0), ("snn::k_update", 7.0), (d, 777.0)])
+         [(copy, 512.0), (copy, 512.0), (copy, 512.0), (copy, 3.0), (d, 777.0), (d, 999.0), (d, 100.0),
+          ("snn::k_update", 7.0), (d, 300.0)])
     _csv(str(tmp_path / "w" / "run_counter_collection.csv"), "WRITE_SIZE",
-         [(copy, 1024.0), (copy, 1024.0), (copy, 1024.0), (copy, 0.0), (d, 55.0), (d, 10.0), (d, 10.0),
-          (d, 66.0)])
+         [(copy, 1024.0), (copy, 1024.0), (copy, 1024.0), (copy, 0.0), (d, 66.0), (d, 55.0), (d, 10.0),
+          (d, 10.0)])
     point = {"workload": bench.WORKLOAD, "settle_steps": 300, "warmup": 5, "steps": 20, "events": 123,
              "spikes": 4, "delivery": "tiled", "tiles": 87, "window": 15, "delivery_launches": 2}
     _bench_line(str(tmp_path / "a.json"), point, 1)
