@@ -5,7 +5,7 @@
 //   * V and the refractory counters live in registers (kPer neurons per lane);
 //   * the delay ring of Q16 input accumulators ([delay][n] int32) lives in LDS, so
 //     Receive Spikes is an LDS atomic add per synaptic event and the CSR rows are the
-//     only HBM stream;
+//     only HBM stream, read as 16-byte groups of 4 targets, several per lane in flight;
 //   * the step's spike queue is compacted with one ballot per wavefront and one LDS
 //     counter reservation per wavefront, into the network's queue buffer;
 //   * two workgroup barriers per step separate update, delivery and the next update.
@@ -18,13 +18,28 @@
 namespace snn {
 namespace {
 
-template <int kBlock, int kPer>
+// 16-byte groups of a row per lane per round: four, except where 1,024-thread
+// workgroups (at most 128 registers per lane) hold many neurons per lane, where more
+// groups in flight would spill
+constexpr int groups_in_flight(int block, int per) { return block == 1024 ? (per >= 16 ? 1 : 2) : 4; }
+
+// LDS atomic adds of the elements [lo, hi) of one 16-byte group starting at edge e0.
+__device__ __forceinline__ void add_group(int32_t *in, const int4 &c, const int4 &w, uint64_t e0, uint64_t lo,
+                                          uint64_t hi) {
+  const int32_t cv[4] = {c.x, c.y, c.z, c.w}, wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (e0 + q >= lo && e0 + q < hi) atomicAdd(&in[cv[q]], wv[q]);
+}
+
+template <int kBlock, int kPer, bool kDrive>
 __global__ __launch_bounds__(kBlock) void k_batch(const BatchNet *nets, const uint32_t *order,
                                                   uint32_t steps, uint32_t flags) {
   extern __shared__ int32_t s_dyn[];  // [delay][n] accumulators, then the drive thresholds
   __shared__ uint32_t s_qn[2];
   __shared__ unsigned long long s_count[2];
 
+  constexpr int kGroupsInFlight = groups_in_flight(kBlock, kPer);
   const BatchNet d = nets[order[blockIdx.x]];
   const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
   const uint32_t n = d.n, delay = d.delay;
@@ -42,7 +57,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchNet *nets, const ui
     ref[k] = i < n ? d.ref[i] : 0;
   }
   for (uint32_t j = tid; j < delay * n; j += kBlock) acc[j] = d.input[j];
-  for (uint32_t j = tid; j < d.below; j += kBlock) tbl[j] = d.table32[j];
+  if (kDrive)
+    for (uint32_t j = tid; j < d.below; j += kBlock) tbl[j] = d.table32[j];
   if (tid < 2) {
     s_qn[tid] = 0;
     s_count[tid] = 0;
@@ -68,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchNet *nets, const ui
       bool spike = false;
       if (i < n) {
         int32_t kk = 0;
-        if (d.below && ref[k] <= 0) {
+        if (kDrive && d.below && ref[k] <= 0) {
           const Words4 r4 = philox(i, (uint32_t)(t >> 2), (uint32_t)(t >> 34), kStreamPoisson, d.key0, d.key1);
           const uint32_t r = word_of(r4, (uint32_t)t & 3u);
           while (kk < (int32_t)d.below && tbl[kk] <= r) ++kk;
@@ -99,30 +115,27 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchNet *nets, const ui
         events += hi - lo;
         spikes += 1;
       }
-      uint64_t e = lo + gl;
-      if (d.w_src) {  // one weight per source: only the targets are streamed
-        const int32_t ws = d.w_src[src];
-        for (; e + 3u * lanes < hi; e += 4u * lanes) {
-          const int32_t c0 = d.col[e], c1 = d.col[e + lanes];
-          const int32_t c2 = d.col[e + 2u * lanes], c3 = d.col[e + 3u * lanes];
-          atomicAdd(&in[c0], ws);
-          atomicAdd(&in[c1], ws);
-          atomicAdd(&in[c2], ws);
-          atomicAdd(&in[c3], ws);
+      // the row as 16-byte groups of 4 targets (the arrays are padded to whole groups),
+      // up to kGroupsInFlight groups per lane requested before their adds; elements
+      // outside the row are masked
+      const uint64_t g_lo = lo >> 2, g_hi = (hi + 3) >> 2;
+      const int4 *col4 = reinterpret_cast<const int4 *>(d.col);
+      const int4 *w4 = reinterpret_cast<const int4 *>(d.w_q16);
+      const int32_t ws = d.w_src ? d.w_src[src] : 0;  // one weight per source: targets only
+      for (uint64_t g0 = g_lo + gl; g0 < g_hi; g0 += (uint64_t)kGroupsInFlight * lanes) {
+        int4 c[kGroupsInFlight], w[kGroupsInFlight];
+#pragma unroll
+        for (int u = 0; u < kGroupsInFlight; ++u) {
+          const uint64_t g = g0 + (uint64_t)u * lanes;
+          c[u] = g < g_hi ? col4[g] : make_int4(0, 0, 0, 0);
+          w[u] = make_int4(ws, ws, ws, ws);
+          if (!d.w_src && g < g_hi) w[u] = w4[g];
         }
-        for (; e < hi; e += lanes) atomicAdd(&in[d.col[e]], ws);
-      } else {
-        for (; e + 3u * lanes < hi; e += 4u * lanes) {
-          const int32_t c0 = d.col[e], c1 = d.col[e + lanes];
-          const int32_t c2 = d.col[e + 2u * lanes], c3 = d.col[e + 3u * lanes];
-          const int32_t w0 = d.w_q16[e], w1 = d.w_q16[e + lanes];
-          const int32_t w2 = d.w_q16[e + 2u * lanes], w3 = d.w_q16[e + 3u * lanes];
-          atomicAdd(&in[c0], w0);
-          atomicAdd(&in[c1], w1);
-          atomicAdd(&in[c2], w2);
-          atomicAdd(&in[c3], w3);
+#pragma unroll
+        for (int u = 0; u < kGroupsInFlight; ++u) {
+          const uint64_t g = g0 + (uint64_t)u * lanes;
+          if (g < g_hi) add_group(in, c[u], w[u], 4 * g, lo, hi);
         }
-        for (; e < hi; e += lanes) atomicAdd(&in[d.col[e]], d.w_q16[e]);
       }
     }
     __syncthreads();
@@ -157,10 +170,13 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchNet *nets, const ui
 template <int kBlock, int kPer>
 hipError_t launch_one(const BatchNet *nets, const uint32_t *order, uint32_t n_nets, uint32_t steps,
                       uint32_t flags, size_t lds, hipStream_t s) {
-  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<kBlock, kPer>),
+  // without a Poisson drive in any member the kernel is built without the drive's code
+  // (Philox and the threshold scan), which would otherwise take registers
+  auto k = (flags & kBatchDrive) ? k_batch<kBlock, kPer, true> : k_batch<kBlock, kPer, false>;
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_batch<kBlock, kPer>), dim3(n_nets), dim3(kBlock), lds, s, nets, order, steps, flags);
+  hipLaunchKernelGGL(k, dim3(n_nets), dim3(kBlock), lds, s, nets, order, steps, flags);
   return hipGetLastError();
 }
 

@@ -1286,6 +1286,8 @@ void batch_apply_tuning(snn_batch *b, const snn_batch_tuning &t) {
 }
 
 void batch_launch(snn_batch *b, uint32_t steps, uint32_t flags) {
+  for (const snn::BatchNet &d : b->desc)
+    if (d.below) flags |= snn::kBatchDrive;
   check(snn::launch_batch(b->d_desc, b->d_order, (uint32_t)b->nets.size(), steps, b->tuning.block,
                           b->tuning.per_lane, flags, b->lds_need, b->pool.stream), "batch launch");
 }

@@ -183,6 +183,7 @@ struct BatchNet {
 };
 constexpr uint32_t kBatchCommit = 1u;       // write state, counters and t back
 constexpr uint32_t kBatchWriteRaster = 2u;  // write the raster rows
+constexpr uint32_t kBatchDrive = 4u;        // some member has a Poisson drive
 bool batch_variant_supported(uint32_t block, uint32_t per);
 uint32_t batch_per_lane(uint32_t block, uint32_t n_max);  // 0: n_max too large for block
 hipError_t launch_batch(const BatchNet *nets, const uint32_t *order, uint32_t n_nets, uint32_t steps,
