@@ -67,6 +67,7 @@ __device__ __forceinline__ void add_part(uint64_t *counter, uint32_t part, uint6
 
 constexpr int kUpdateWaves = kUpdateBlock / kWave;
 constexpr int kPrefetch = 16;  // steps of input in flight (4 quads)
+constexpr int kShortQuads = 5;  // windows of up to this many quads take the batched path
 
 // Update Neurons for `steps` (<= 64) consecutive steps.  The LIF arithmetic is
 // sequential per neuron; the rest is batched.  Steps are processed in quads aligned
@@ -155,6 +156,58 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
 
   uint64_t my_mask = 0;    // lane w: ballot of step w
   uint64_t my_spikes = 0;  // bit w: this neuron spiked at step w
+  // One LIF step at window position p (step w = p - off) with drive count k.
+  auto lif_step = [&](int32_t p, int32_t x, int32_t k) {
+    const int32_t w = p - (int32_t)off;
+    const bool spike = lif_advance(v, ref, x, k, lif) && active;
+    if (a.plastic) {
+      xp = xp * a.beta_plus;
+      xq = xq * a.beta_minus;
+    }
+    const uint64_t mask = __ballot(spike);
+    if (lane == (uint32_t)w) my_mask = mask;
+    if (spike) my_spikes |= 1ull << w;
+  };
+  if (n_quads <= kShortQuads) {
+    // A window of at most kShortQuads quads (a 15-step window spans 4 or 5): its Philox
+    // blocks and all its drive lookups are independent of the membrane, so they are
+    // issued side by side first (their latencies overlap), then the LIF steps run.
+    int32_t xs[4 * kShortQuads];
+#pragma unroll
+    for (int j = 0; j < kPrefetch; ++j) xs[j] = acc[j];
+#pragma unroll
+    for (int j = kPrefetch; j < 4 * kShortQuads; ++j) xs[j] = load_input(j);
+    int32_t kd[4 * kShortQuads];
+    if (drive) {
+      Words4 rnd[kShortQuads];
+#pragma unroll
+      for (int q = 0; q < kShortQuads; ++q) {
+        const uint64_t qa = quad0 + (uint64_t)q;
+        rnd[q] = (uint32_t)q < n_quads ? philox(i, (uint32_t)qa, (uint32_t)(qa >> 32), kStreamPoisson, a.key0, a.key1)
+                                       : Words4{};
+      }
+      uint32_t gk[4 * kShortQuads];
+#pragma unroll
+      for (int j = 0; j < 4 * kShortQuads; ++j)
+        gk[j] = (uint32_t)(j >> 2) < n_quads ? guide[rnd[j >> 2].w[j & 3] >> (32 - kGuideBits)] : 0u;
+#pragma unroll
+      for (int j = 0; j < 4 * kShortQuads; ++j) {
+        const uint32_t r = rnd[j >> 2].w[j & 3];
+        int32_t k = (int32_t)(gk[j] & 0xFFu);
+        const int32_t k_hi = (int32_t)(gk[j] >> 8);
+        while (k < k_hi && tbl[k] <= r) ++k;
+        kd[j] = k;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4 * kShortQuads; ++j) kd[j] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4 * kShortQuads; ++j) {
+      const int32_t w = j - (int32_t)off;
+      if (w >= 0 && w < (int32_t)steps) lif_step(j, xs[j], kd[j]);  // uniform
+    }
+  } else {
   for (uint32_t qq = 0; qq < n_quads; ++qq) {
     Words4 rnd{};
     if (drive)
@@ -171,20 +224,14 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
         const int32_t k_hi = (int32_t)(gk >> 8);
         while (k < k_hi && tbl[k] <= r) ++k;
       }
-      const bool spike = lif_advance(v, ref, acc[u], k, lif) && active;
-      if (a.plastic) {
-        xp = xp * a.beta_plus;
-        xq = xq * a.beta_minus;
-      }
-      const uint64_t mask = __ballot(spike);
-      if (lane == (uint32_t)w) my_mask = mask;
-      if (spike) my_spikes |= 1ull << w;
+      lif_step((int32_t)(4 * qq + u), acc[u], k);
     }
     // roll the input window by one quad and request the quad kPrefetch / 4 ahead
 #pragma unroll
     for (int j = 0; j < kPrefetch - 4; ++j) acc[j] = acc[j + 4];
 #pragma unroll
     for (int j = kPrefetch - 4; j < kPrefetch; ++j) acc[j] = load_input((int32_t)(4 * (qq + 1)) + j);
+  }
   }
   if (active) {
     a.v[i] = v;
