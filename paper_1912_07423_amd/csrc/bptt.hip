@@ -259,15 +259,24 @@ __global__ void k_readout_scan(BpttArgs a, const float *ro) {
   if (b >= a.B) return;
   float u = 0.0f, m = 0.0f;
   uint32_t tm = 0;
-  for (uint32_t t = 0; t < a.T; ++t) {
+  auto step = [&](uint32_t t, float r) {
     float ut = a.beta_out * u;
-    ut = ut + ro[((size_t)t * a.O + o) * 64 + b];
+    ut = ut + r;
     u = ut;
     if (t == 0 || ut > m) {
       m = ut;
       tm = t;
     }
+  };
+  uint32_t t = 0;
+  for (; t + 8 <= a.T; t += 8) {  // eight drives requested before the eight steps
+    float r[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] = ro[((size_t)(t + q) * a.O + o) * 64 + b];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) step(t + q, r[q]);
   }
+  for (; t < a.T; ++t) step(t, ro[((size_t)t * a.O + o) * 64 + b]);
   a.m[(size_t)b * a.O + o] = m;
   a.tmax[(size_t)b * a.O + o] = (int32_t)tm;
 }
@@ -322,8 +331,20 @@ __global__ __launch_bounds__(256) void k_adjoint_step(BpttArgs a, uint32_t t, co
   if (i >= a.H) return;
   const uint32_t b = lane_id();
   const float *lu = a.lamu + (size_t)t * a.O * 64 + b;
+  // the readout term, in ascending o, eight loads issued before their terms are added
   float ds = 0.0f;
-  for (uint32_t o = 0; o < a.O; ++o) ds = ds + a.w_out[(size_t)i * a.O + o] * lu[(size_t)o * 64];
+  uint32_t o = 0;
+  for (; o + 8 <= a.O; o += 8) {
+    float wv[8], lv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      wv[u] = a.w_out[(size_t)i * a.O + o + u];
+      lv[u] = lu[(size_t)(o + u) * 64];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ds = ds + wv[u] * lv[u];
+  }
+  for (; o < a.O; ++o) ds = ds + a.w_out[(size_t)i * a.O + o] * lu[(size_t)o * 64];
   ds = ordered_gather_pipe(ds, a.rec_ptr[i], a.rec_ptr[i + 1], a.rec_col, a.w_rec, lam_next, b);
   const float ln = lam_next[(size_t)i * 64 + b];
   if (!a.detach_reset) ds = ds - a.theta * ln;
