@@ -99,7 +99,8 @@ typedef struct {
     double a_minus;        /* depression step per unit trace (mV) */
     double w_max_mV;       /* plastic weights are clipped to [0, w_max] */
     uint64_t seed;         /* key of every counter-based random stream */
-    uint32_t raster_steps; /* spike-raster ring capacity in steps (0: 1024) */
+    uint32_t raster_steps; /* spike-raster ring capacity in steps (0: 1024; at least delay + 1 for
+                              plastic networks, whose plasticity pass reads step t - delay) */
     uint32_t window;       /* max steps per update launch (0: auto, <= delay) */
     uint32_t delivery;     /* SNN_DELIVERY_* */
     uint32_t tiles;        /* target tiles of the tiled delivery (0: auto) */

@@ -320,6 +320,8 @@ void choose_schedule(snn_network *net) {
     net->delivery = p.delivery;
   }
   net->raster_cap = p.raster_steps ? p.raster_steps : 1024u;
+  // eager STDP reads the spike bits of step t - d from the raster ring
+  if (net->plastic) net->raster_cap = std::max(net->raster_cap, net->delay + 1);
   net->window = std::min(net->window, net->raster_cap);  // kernels step rings by one wrap
   net->slots = std::max(net->delay + 2, 2 * net->window);
   net->words = (net->n + 63) / 64;
@@ -691,6 +693,9 @@ snn::StdpArgs stdp_args(snn_network *net) {
   a.x_post = net->x_post;
   a.q = queue_ref(net);
   a.ctl = net->ctl;
+  a.raster = net->raster;
+  a.raster_cap = net->raster_cap;
+  a.words = net->words;
   a.n = net->n;
   a.slots = net->slots;
   a.delay = net->delay;
@@ -803,11 +808,15 @@ void issue_window(snn_network *net, uint32_t steps) {
     net->t_host += steps;
     return;
   }
+  snn::DeliverArgs d = deliver_args(net);
   if (net->plastic) {
+    // depression and potentiation in one pass; the delivery then adds the arrivals to
+    // x_pre and S_t to x_post
     const snn::StdpArgs sa = stdp_args(net);
-    timed(net, 2, [&](const snn::LaunchEvents &ev) { return snn::launch_stdp(sa, net->cu_count * 4, net->stream, ev); });
+    timed(net, 2, [&](const snn::LaunchEvents &ev) { return snn::launch_stdp_fused(sa, net->cu_count * 4, net->stream, ev); });
+    d.x_pre = net->x_pre;
+    d.x_post = net->x_post;
   }
-  const snn::DeliverArgs d = deliver_args(net);
   timed(net, 1, [&](const snn::LaunchEvents &ev) { return launch_delivery(net, d, steps, ev); });
   net->t_host += steps;
 }

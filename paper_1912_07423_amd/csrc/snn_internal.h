@@ -126,6 +126,7 @@ struct DeliverArgs {
   uint32_t tiles, tile_size;
   uint32_t off16;
   uint32_t advance;       // this launch closes the window: advance the step counter
+  float *x_pre, *x_post;  // eager STDP: here x_pre += 1 for S_{t-d}, x_post += 1 for S_t (else null)
 };
 
 // The lazy plasticity kernel of one step t: rows of S_{t-d+1} transmit (pending
@@ -156,6 +157,8 @@ struct StdpArgs {
   float *x_pre, *x_post;
   QueueRef q;
   Ctl *ctl;
+  const uint64_t *raster;  // [raster_cap][words] spike bits (the fused pass tests S_t, S_{t-d})
+  uint32_t raster_cap, words;
   uint32_t n, slots, delay;
   float a_plus, a_minus, w_max;
 };
@@ -243,8 +246,8 @@ hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t b
                                 uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});
 constexpr uint32_t kTileGroupMax = 32;  // base tiles one tiled-delivery workgroup may own
 hipError_t prepare_deliver_tiled(uint32_t block, size_t *max_dynamic_lds);
-hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});
 hipError_t launch_stdp_ltd(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});
+hipError_t launch_stdp_fused(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});
 hipError_t launch_lazy(const LazyArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev = {});
 // Brings every plastic row current at step boundary t (pending potentiation applied,
 // age t, trace at age rebuilt from x_pre and the arrivals of step t).

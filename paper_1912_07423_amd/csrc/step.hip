@@ -67,7 +67,7 @@ __device__ __forceinline__ void add_part(uint64_t *counter, uint32_t part, uint6
 
 constexpr int kUpdateWaves = kUpdateBlock / kWave;
 constexpr int kPrefetch = 16;  // steps of input in flight (4 quads)
-constexpr int kShortQuads = 5;  // windows of up to this many quads take the batched path
+constexpr int kShortQuads = 5;  // windows of 4 or 5 quads take the batched path
 
 // Update Neurons for `steps` (<= 64) consecutive steps.  The LIF arithmetic is
 // sequential per neuron; the rest is batched.  Steps are processed in quads aligned
@@ -168,10 +168,11 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
     if (lane == (uint32_t)w) my_mask = mask;
     if (spike) my_spikes |= 1ull << w;
   };
-  if (n_quads <= kShortQuads) {
-    // A window of at most kShortQuads quads (a 15-step window spans 4 or 5): its Philox
-    // blocks and all its drive lookups are independent of the membrane, so they are
-    // issued side by side first (their latencies overlap), then the LIF steps run.
+  if (n_quads >= kShortQuads - 1 && n_quads <= kShortQuads) {
+    // A window of 4 or 5 quads (a 15-step window): its Philox blocks and all its drive
+    // lookups are independent of the membrane, so they are issued side by side first
+    // (their latencies overlap), then the LIF steps run.  Shorter and longer windows
+    // take the rolling loop below.
     int32_t xs[4 * kShortQuads];
 #pragma unroll
     for (int j = 0; j < kPrefetch; ++j) xs[j] = acc[j];
@@ -183,8 +184,9 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
 #pragma unroll
       for (int q = 0; q < kShortQuads; ++q) {
         const uint64_t qa = quad0 + (uint64_t)q;
-        rnd[q] = (uint32_t)q < n_quads ? philox(i, (uint32_t)qa, (uint32_t)(qa >> 32), kStreamPoisson, a.key0, a.key1)
-                                       : Words4{};
+        rnd[q] = Words4{};
+        if ((uint32_t)q < n_quads)  // uniform
+          rnd[q] = philox(i, (uint32_t)qa, (uint32_t)(qa >> 32), kStreamPoisson, a.key0, a.key1);
       }
       uint32_t gk[4 * kShortQuads];
 #pragma unroll
@@ -341,6 +343,28 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
   __shared__ uint32_t s_step[kWave + 1];               // prefix of the per-step totals
   const uint64_t t0 = a.ctl->t_deliver;
   close_window(a, t0, steps);
+  // eager STDP (one step t per launch), after the step's plasticity pass has read the
+  // traces: the last workgroup adds the arrivals S_{t-d} to x_pre and S_t to x_post,
+  // beside the delivery of the others
+  const bool trace_wg = a.x_post != nullptr && blockIdx.x + 1 == gridDim.x && gridDim.x > 1;
+  if (trace_wg) {
+    const uint32_t slot_t = (uint32_t)(t0 % a.slots);
+    const bool has_d = t0 >= a.delay;
+    const uint32_t slot_d = has_d ? (uint32_t)((t0 - a.delay) % a.slots) : 0u;
+    uint32_t pt[kQueueGroups + 1], pd[kQueueGroups + 1] = {};
+    queue_prefix(a.q, slot_t, pt);
+    if (has_d) queue_prefix(a.q, slot_d, pd);
+    for (uint32_t f = threadIdx.x; f < pt[kQueueGroups]; f += kAtomicBlock) {
+      const int32_t j = queue_entry(a.q, slot_t, pt, f);
+      if ((uint32_t)j < a.n) a.x_post[j] = a.x_post[j] + 1.0f;
+    }
+    for (uint32_t f = threadIdx.x; f < pd[kQueueGroups]; f += kAtomicBlock) {
+      const int32_t i = queue_entry(a.q, slot_d, pd, f);
+      if ((uint32_t)i < a.n) a.x_pre[i] = a.x_pre[i] + 1.0f;
+    }
+    return;
+  }
+  const uint32_t deliver_grid = a.x_post != nullptr && gridDim.x > 1 ? gridDim.x - 1 : gridDim.x;
   const int64_t e0 = emission_step(a, t0, 0);
   const uint32_t eslot0 = ring_of(e0, a.slots);
   const uint32_t in0 = (uint32_t)(t0 % a.n_inbuf);
@@ -364,7 +388,7 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
   __syncthreads();
   const uint32_t total = s_step[kWave];
   const uint32_t gwave = blockIdx.x * kAtomicWaves + threadIdx.x / kWave;
-  const uint32_t n_gwaves = gridDim.x * kAtomicWaves;
+  const uint32_t n_gwaves = deliver_grid * kAtomicWaves;
   uint64_t ev = 0, n_spk = 0;
   const uint32_t parts = parts_for(total, n_gwaves, kAtomicMaxParts);
   for (uint64_t item = gwave; item < (uint64_t)total * parts; item += n_gwaves) {
@@ -762,33 +786,76 @@ __global__ __launch_bounds__(kStdpBlock) void k_stdp_ltd(StdpArgs a) {
   if (lane == 0) add_part(a.ctl->touches, gwave, touched);
 }
 
-__global__ __launch_bounds__(kStdpBlock) void k_stdp_ltp(StdpArgs a) {
+// Depression and potentiation of step t in one pass.  Work items are the rows of
+// S_{t-d} (depression over each row's plastic prefix) and the in-edge lists of S_t
+// (potentiation), each cut into disjoint parts.  A synapse i -> j with i in S_{t-d}
+// and j in S_t takes both updates, depression first: its row part skips it and its
+// in-edge part applies both, so every synapse still has one writer.  The traces are
+// not written here (the delivery that follows adds the arrivals S_{t-d} to x_pre and
+// S_t to x_post): potentiation reads x_pre[i] + 1 for a source i in S_{t-d}, which is
+// the value the two-kernel order gives.  Membership of S_t and S_{t-d} is read from
+// the raster.
+__global__ __launch_bounds__(kStdpBlock) void k_stdp_fused(StdpArgs a) {
   const uint64_t t = a.ctl->t;
-  const uint32_t slot = (uint32_t)(t % a.slots);
-  uint32_t pre[kQueueGroups + 1];
-  queue_prefix(a.q, slot, pre);
-  const uint32_t cnt = pre[kQueueGroups];
+  const bool has_d = t >= a.delay;
+  const uint32_t slot_d = has_d ? (uint32_t)((t - a.delay) % a.slots) : 0u;
+  const uint32_t slot_p = (uint32_t)(t % a.slots);
+  uint32_t pd[kQueueGroups + 1] = {}, pp[kQueueGroups + 1];
+  if (has_d) queue_prefix(a.q, slot_d, pd);
+  queue_prefix(a.q, slot_p, pp);
+  const uint32_t cnt_d = pd[kQueueGroups], cnt_p = pp[kQueueGroups];
+  const uint64_t *row_p = a.raster + (size_t)(t % a.raster_cap) * a.words;
+  const uint64_t *row_d = a.raster + (size_t)(has_d ? (t - a.delay) % a.raster_cap : 0) * a.words;
   const uint32_t lane = lane_id();
   const uint32_t gwave = blockIdx.x * kStdpWaves + threadIdx.x / kWave;
   const uint32_t n_gwaves = gridDim.x * kStdpWaves;
-  const uint32_t split = parts_for(cnt, n_gwaves, kStdpMaxSplit);
+  const uint32_t split = parts_for(cnt_d + cnt_p, n_gwaves, kStdpMaxSplit);
   uint64_t touched = 0;
-  for (uint64_t item = gwave; item < (uint64_t)cnt * split; item += n_gwaves) {
+  for (uint64_t item = gwave; item < (uint64_t)(cnt_d + cnt_p) * split; item += n_gwaves) {
     const uint32_t s = (uint32_t)(item / split), part = (uint32_t)(item % split);
-    const int32_t j = queue_entry(a.q, slot, pre, s);
-    if ((uint32_t)j >= a.n) continue;
-    if (part == 0 && lane == 0) a.x_post[j] = a.x_post[j] + 1.0f;
-    const uint64_t lo = a.in_ptr[j], len = a.in_ptr[j + 1] - lo;
-    const uint64_t chunk = (len + split - 1) / split;
-    const uint64_t m0 = lo + part * chunk, m1 = min(lo + len, m0 + chunk);
-    for (uint64_t m = m0 + lane; m < m1; m += kWave) {
-      const uint32_t e = a.in_edge[m];
-      const float dw = a.a_plus * a.x_pre[a.in_src[m]];
-      float wv = a.w_f32[e] + dw;
-      if (wv > a.w_max) wv = a.w_max;
-      a.w_f32[e] = wv;
+    if (s < cnt_d) {
+      const int32_t i = queue_entry(a.q, slot_d, pd, s);
+      if ((uint32_t)i >= a.n) continue;
+      const uint64_t lo = a.row_ptr[i] + a.plast_rel[i];
+      const uint32_t len = a.plast_len[i];
+      const uint32_t chunk = (len + split - 1) / split;
+      const uint32_t k0 = part * chunk, k1 = min(len, k0 + chunk);
+      for (uint32_t k = k0 + lane; k < k1; k += kWave) {
+        const uint64_t e = lo + k;
+        const int32_t j = a.col[e];
+        if ((row_p[(uint32_t)j >> 6] >> ((uint32_t)j & 63u)) & 1u) continue;  // its in-edge part
+        const float dw = a.a_minus * a.x_post[j];
+        float wv = a.w_f32[e] - dw;
+        if (wv < 0.0f) wv = 0.0f;
+        a.w_f32[e] = wv;
+      }
+      touched += k1 > k0 ? k1 - k0 : 0;
+    } else {
+      const int32_t j = queue_entry(a.q, slot_p, pp, s - cnt_d);
+      if ((uint32_t)j >= a.n) continue;
+      const uint64_t lo = a.in_ptr[j], len = a.in_ptr[j + 1] - lo;
+      const uint64_t chunk = (len + split - 1) / split;
+      const uint64_t m0 = lo + part * chunk, m1 = min(lo + len, m0 + chunk);
+      const float xq = a.x_post[j];
+      for (uint64_t m = m0 + lane; m < m1; m += kWave) {
+        const uint32_t e = a.in_edge[m];
+        const int32_t i = a.in_src[m];
+        float wv = a.w_f32[e];
+        float xpi = a.x_pre[i];
+        if (has_d && ((row_d[(uint32_t)i >> 6] >> ((uint32_t)i & 63u)) & 1u)) {
+          const float dm = a.a_minus * xq;
+          wv = wv - dm;
+          if (wv < 0.0f) wv = 0.0f;
+          xpi = xpi + 1.0f;  // its arrival of step t
+        }
+        const float dp = a.a_plus * xpi;
+        wv = wv + dp;
+        if (wv > a.w_max) wv = a.w_max;
+        a.w_f32[e] = wv;
+      }
+      // the synapses taking depression here were counted by their row's part
+      touched += m1 > m0 ? m1 - m0 : 0;
     }
-    touched += m1 > m0 ? m1 - m0 : 0;
   }
   if (lane == 0) add_part(a.ctl->touches, gwave, touched);
 }
@@ -1015,6 +1082,7 @@ hipError_t launch_update(const UpdateArgs &a, uint32_t steps, hipStream_t s, con
 hipError_t launch_deliver_atomic(const DeliverArgs &a, uint32_t steps, uint32_t grid, hipStream_t s,
                                  const LaunchEvents &ev) {
   auto k = a.w_f32 ? k_deliver_atomic<kWeightF32> : a.w_src ? k_deliver_atomic<kWeightSrc> : k_deliver_atomic<kWeightQ16>;
+  if (a.x_post && grid < 2) grid = 2;  // the last workgroup advances the traces
   launch_kernel(k, grid, kAtomicBlock, 0, s, ev.start, ev.stop, a, steps);
   return hipGetLastError();
 }
@@ -1076,9 +1144,8 @@ hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t b
   return hipGetLastError();
 }
 
-hipError_t launch_stdp(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev) {
-  launch_kernel(k_stdp_ltd, grid, kStdpBlock, 0, s, ev.start, nullptr, a);
-  launch_kernel(k_stdp_ltp, grid, kStdpBlock, 0, s, nullptr, ev.stop, a);
+hipError_t launch_stdp_fused(const StdpArgs &a, uint32_t grid, hipStream_t s, const LaunchEvents &ev) {
+  launch_kernel(k_stdp_fused, grid, kStdpBlock, 0, s, ev.start, ev.stop, a);
   return hipGetLastError();
 }
 
