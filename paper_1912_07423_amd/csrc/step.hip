@@ -82,6 +82,9 @@ constexpr int kShortQuads = 5;  // windows of 4 or 5 quads take the batched path
 // The drive and the LIF arithmetic run on every lane without branching on the neuron's
 // state: a refractory neuron discards its drive inside lif_advance, and a lane past n
 // never reports a spike or stores.
+// kShort: the launch's windows span 4 or 5 quads (13 to 17 steps) and take the batched
+// path; other window lengths are built without it (fewer registers and less code).
+template <bool kShort>
 __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t steps) {
   __shared__ __align__(16) uint32_t tbl[kTableCap];
   __shared__ __align__(16) uint16_t guide[kGuideBuckets];
@@ -168,7 +171,7 @@ __global__ __launch_bounds__(kUpdateBlock) void k_update(UpdateArgs a, uint32_t 
     if (lane == (uint32_t)w) my_mask = mask;
     if (spike) my_spikes |= 1ull << w;
   };
-  if (n_quads >= kShortQuads - 1 && n_quads <= kShortQuads) {
+  if (kShort && n_quads >= kShortQuads - 1 && n_quads <= kShortQuads) {
     // A window of 4 or 5 quads (a 15-step window): its Philox blocks and all its drive
     // lookups are independent of the membrane, so they are issued side by side first
     // (their latencies overlap), then the LIF steps run.  Shorter and longer windows
@@ -1075,7 +1078,11 @@ void launch_kernel(void (*kernel)(KArgs...), uint32_t grid, uint32_t block, size
 
 hipError_t launch_update(const UpdateArgs &a, uint32_t steps, hipStream_t s, const LaunchEvents &ev) {
   const uint32_t grid = (a.n + kUpdateBlock - 1) / kUpdateBlock;
-  launch_kernel(k_update, grid, kUpdateBlock, 0, s, ev.start, ev.stop, a, steps);
+  // windows of 13 to 17 steps always span 4 or 5 quads, whatever their first step
+  if (steps >= 4 * (kShortQuads - 1) - 3 && steps <= 4 * kShortQuads - 3)
+    launch_kernel(k_update<true>, grid, kUpdateBlock, 0, s, ev.start, ev.stop, a, steps);
+  else
+    launch_kernel(k_update<false>, grid, kUpdateBlock, 0, s, ev.start, ev.stop, a, steps);
   return hipGetLastError();
 }
 
