@@ -283,7 +283,8 @@ def bench_stdp(args):
     from paper_1912_07423_amd import workloads as W
     spec = W.stdp_er()
     steps = args.steps or spec["steps"]
-    net = Network(spec, raster_steps=4096, plasticity=args.plasticity)
+    delivery = args.delivery if args.plasticity == "eager" else "auto"
+    net = Network(spec, raster_steps=4096, plasticity=args.plasticity, delivery=delivery)
     net.run(warm)
     net.sync()
     i0 = net.info()   # with lazy plasticity this brings every row current
@@ -307,14 +308,17 @@ def bench_stdp(args):
     smean = prof["stdp_ms"] / max(1, prof["stdp_launches"])
     b_ev, b_spk = delivery_bytes(i1)
     dbytes = (p_events * b_ev + spikes * b_spk) / max(1, prof["deliver_launches"])
-    # atomic throughput: one device-scope int32 add per synaptic event.  The run's rate
-    # inside the delivery kernel, against the same kernel saturated by one step of
-    # 20,000 spikes (about 4e7 events) over the same rows
+    # add throughput: one int32 add per synaptic event (device-scope atomics in global
+    # memory for the atomic delivery, in LDS for the tiled one).  The run's rate inside
+    # the delivery kernel, against the same kernel saturated by one step of 20,000 spikes
+    # (about 4e7 events) over the same rows
     import numpy as np
     ids = np.random.default_rng(7).choice(i1["n"], 20_000, replace=False).astype(np.uint32)
     ms_sat, ev_sat = net.time_delivery(ids, reps=5, steps=1)
     achieved = p_events / (prof["deliver_ms"] * 1e-3) if prof["deliver_ms"] > 0 else 0.0
     saturated = ev_sat / (ms_sat * 1e-3) if ms_sat > 0 else 0.0
+    tiled = i1["delivery_name"] == "tiled"
+    dkernel = "k_deliver_tiled" if tiled else "k_deliver_atomic"
     line("STDP network: synaptic events/sec, STDP synapse touches/sec, 1 GPU", events / wall, "events/s",
          steps, warm, wall * 1e3 / steps, "fp32",
          {"workload": "stdp_er_100k_p0.02_d10_poisson10hz", "neurons": i1["n"], "synapses": i1["nnz"],
@@ -328,8 +332,9 @@ def bench_stdp(args):
          roofline={"bound": "hbm", "achieved": dbytes / (dmean * 1e-3) / 1e9 if dmean > 0 else 0.0,
                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
                    "frac": dbytes / (dmean * 1e-3) / 1e9 / HBM_PEAK_GBS if dmean > 0 else 0.0,
-                   "traffic": None, "kernel": "k_deliver_atomic"},
-         atomics={"kernel": "k_deliver_atomic", "per_event": "one device-scope int32 add",
+                   "traffic": None, "kernel": dkernel},
+         atomics={"kernel": dkernel,
+                  "per_event": "one int32 add in LDS" if tiled else "one device-scope int32 add",
                   "achieved_per_s": achieved, "saturated_per_s": saturated,
                   "frac": achieved / saturated if saturated > 0 else None,
                   "saturated_by": f"one step of {len(ids)} spikes ({ev_sat} events)"})

@@ -47,9 +47,11 @@ typedef int32_t snn_status;
 #define SNN_PROJ_ER 0u        /* each ordered pair (i, j), j != i, independently w.p. p */
 #define SNN_PROJ_FIXED_OUT 1u /* every source has exactly k distinct targets (Fig. 2) */
 
-#define SNN_DELIVERY_AUTO 0u   /* choose by the autotuner */
+#define SNN_DELIVERY_AUTO 0u   /* tiled for networks of >= 16,384 neurons and a mean
+                                  out-degree >= 64, else atomic */
 #define SNN_DELIVERY_ATOMIC 1u /* wavefront(s) per spike, int32 atomics in global memory */
-#define SNN_DELIVERY_TILED 2u  /* per (target tile, step) workgroup, int32 atomics in LDS */
+#define SNN_DELIVERY_TILED 2u  /* per (target tile, step) workgroup, int32 atomics in LDS;
+                                  static and eagerly plastic networks (not lazy ones) */
 
 /* Update Synapses with STDP (Sec. III-A.1).  Both forms give the same weights, traces
  * and spikes at every step. */
@@ -271,8 +273,9 @@ snn_status snn_time_delivery_static(snn_network *net, const uint32_t *ids_host, 
 
 /* Switch a network's delivery variant (SNN_DELIVERY_*; AUTO picks by size and
  * degree), its base tiles, workgroup size and grid (0 = auto), from the next step on.
- * Rebuilds the tile boundaries; the simulation state is unchanged.  Plastic networks
- * accept the atomic variant only.  SNN_E_INVALID for an impossible configuration. */
+ * Rebuilds the tile boundaries; the simulation state is unchanged.  SNN_E_INVALID for
+ * an impossible configuration; SNN_E_STATE for a network with lazy plasticity, which
+ * delivers inside its own kernel. */
 snn_status snn_set_delivery(snn_network *net, uint32_t delivery, uint32_t tiles, uint32_t block,
                             uint32_t grid);
 

@@ -308,8 +308,11 @@ void choose_schedule(snn_network *net) {
     // at step t into a single accumulator (the paper's schedule).
     net->window = 1;
     net->n_inbuf = 1;
-    if (p.delivery == SNN_DELIVERY_TILED) fail(SNN_E_INVALID, "tiled delivery needs static weights");
-    net->delivery = SNN_DELIVERY_ATOMIC;
+    // lazy plasticity delivers inside its own kernel (the atomic kernel serves only
+    // delivery timing); eager plasticity takes either delivery, one step per launch
+    if (net->lazy && p.delivery == SNN_DELIVERY_TILED)
+      fail(SNN_E_INVALID, "lazy plasticity delivers inside its own kernel; tiled delivery needs eager plasticity");
+    net->delivery = net->lazy ? SNN_DELIVERY_ATOMIC : p.delivery;
   } else {
     // Static weights: a spike of step e may be delivered any time between the updates
     // of e and e + d; one accumulator per pending arrival step lets a window of up to
@@ -928,7 +931,6 @@ void dev_free(snn_network *net, void *p) {
 void set_delivery(snn_network *net, uint32_t delivery, uint32_t tiles, uint32_t block, uint32_t grid) {
   if (net->lazy) fail(SNN_E_STATE, "lazy plasticity delivers inside its own kernel; there is no variant to choose");
   if (delivery > SNN_DELIVERY_TILED) fail(SNN_E_INVALID, "unknown delivery variant");
-  if (net->plastic && delivery == SNN_DELIVERY_TILED) fail(SNN_E_INVALID, "tiled delivery needs static weights");
   check(hipStreamSynchronize(net->stream), "sync");
   struct Saved {
     uint32_t p_delivery, p_tiles, p_block, p_grid, delivery, block, tiles, tile_size, grid;
@@ -944,7 +946,7 @@ void set_delivery(snn_network *net, uint32_t delivery, uint32_t tiles, uint32_t 
     net->prm.tiles = tiles;
     net->prm.block = block;
     net->prm.grid = grid;
-    net->delivery = net->plastic ? SNN_DELIVERY_ATOMIC : delivery;
+    net->delivery = delivery;
     choose_delivery(net);
     if (net->delivery == SNN_DELIVERY_TILED) {
       net->tile_off = nullptr;  // a fresh index; the old one stays valid until this succeeds
@@ -1212,7 +1214,7 @@ snn_delivery_tuning autotune_delivery(snn_network *net, uint32_t reps) {
   };
   std::vector<Cand> cands;
   cands.push_back({SNN_DELIVERY_ATOMIC, 0, 0, 0});
-  if (!net->plastic && net->n >= 1024) {
+  if (net->n >= 1024) {
     for (uint32_t tile : {384u, 576u, 768u})
       for (uint32_t block : {512u, 1024u})
         for (uint32_t grid : {net->cu_count, 2 * net->cu_count, 3 * net->cu_count})

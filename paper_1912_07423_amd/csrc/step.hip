@@ -5,16 +5,21 @@
 //                    the ballot of each step is both the step's raster word and the
 //                    compaction mask of the spike queue (one queue reservation per
 //                    workgroup and step).
-//  k_deliver_atomic  Receive Spikes, one wavefront per dequeued spike, aligned 16-byte
-//                    loads of targets/weights, no-return int32 atomics into the Q16
-//                    input accumulators in global memory.
-//  k_deliver_tiled   Receive Spikes, one workgroup per (target tile, emission step):
-//                    the workgroup reads the tile's slice of every dequeued spike's
-//                    sorted row from the 16-bit copy of the targets, accumulates in
-//                    LDS with int32 atomics and writes the tile's input accumulators
-//                    with plain stores.
-//  k_stdp_ltd/ltp    Update Synapses: depression over S_{t-d}'s plastic out-edges,
+//  k_deliver_atomic  Receive Spikes, one or more wavefronts per dequeued spike,
+//                    aligned 16-byte loads of targets/weights, no-return int32 atomics
+//                    into the Q16 input accumulators in global memory.
+//  k_deliver_tiled   Receive Spikes, one workgroup per (range of target tiles, emission
+//                    step): the workgroup reads the range's slice of every dequeued
+//                    spike's sorted row from the 16-bit copy of the targets (weights
+//                    per source, per synapse in Q16, or plastic FP32 ones), accumulates
+//                    in LDS with int32 atomics and writes the range's input
+//                    accumulators with plain stores.  With eager STDP both deliveries
+//                    also advance the traces in one extra workgroup.
+//  k_stdp_fused      Update Synapses: depression over S_{t-d}'s plastic out-edges and
 //                    potentiation over S_t's plastic in-edges (transposed index).
+//  k_stdp_ltd, k_lazy  the lazy form: depression, then pending potentiation replayed
+//                    at transmission or expiry, with the delivery of the transmitting
+//                    rows.
 //
 // Step bookkeeping lives on the device (Ctl) so that a captured HIP graph replays
 // correctly; no kernel waits on another workgroup of its own launch.
@@ -324,6 +329,28 @@ __device__ __forceinline__ void close_window(const DeliverArgs &a, uint64_t t0, 
   }
 }
 
+// Eager STDP (one step t = t0 per launch): after the step's plasticity pass has read
+// the traces, the delivery launch's last workgroup adds the arrivals S_{t-d} to x_pre
+// and S_t to x_post, beside the delivery done by the others.  A spike appears once in
+// its step's queue, so every trace has one writer.
+template <int kThreads>
+__device__ void advance_traces(const DeliverArgs &a, uint64_t t0) {
+  const uint32_t slot_t = (uint32_t)(t0 % a.slots);
+  const bool has_d = t0 >= a.delay;
+  const uint32_t slot_d = has_d ? (uint32_t)((t0 - a.delay) % a.slots) : 0u;
+  uint32_t pt[kQueueGroups + 1], pd[kQueueGroups + 1] = {};
+  queue_prefix(a.q, slot_t, pt);
+  if (has_d) queue_prefix(a.q, slot_d, pd);
+  for (uint32_t f = threadIdx.x; f < pt[kQueueGroups]; f += kThreads) {
+    const int32_t j = queue_entry(a.q, slot_t, pt, f);
+    if ((uint32_t)j < a.n) a.x_post[j] = a.x_post[j] + 1.0f;
+  }
+  for (uint32_t f = threadIdx.x; f < pd[kQueueGroups]; f += kThreads) {
+    const int32_t i = queue_entry(a.q, slot_d, pd, f);
+    if ((uint32_t)i < a.n) a.x_pre[i] = a.x_pre[i] + 1.0f;
+  }
+}
+
 // Disjoint parts per queued spike, one wavefront each, so that a launch's wavefronts
 // cover the spikes about once: a step of a plastic network has only ~100 spikes, which
 // one wavefront each would leave most of the GPU idle and walk each row serially.
@@ -346,25 +373,9 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
   __shared__ uint32_t s_step[kWave + 1];               // prefix of the per-step totals
   const uint64_t t0 = a.ctl->t_deliver;
   close_window(a, t0, steps);
-  // eager STDP (one step t per launch), after the step's plasticity pass has read the
-  // traces: the last workgroup adds the arrivals S_{t-d} to x_pre and S_t to x_post,
-  // beside the delivery of the others
   const bool trace_wg = a.x_post != nullptr && blockIdx.x + 1 == gridDim.x && gridDim.x > 1;
   if (trace_wg) {
-    const uint32_t slot_t = (uint32_t)(t0 % a.slots);
-    const bool has_d = t0 >= a.delay;
-    const uint32_t slot_d = has_d ? (uint32_t)((t0 - a.delay) % a.slots) : 0u;
-    uint32_t pt[kQueueGroups + 1], pd[kQueueGroups + 1] = {};
-    queue_prefix(a.q, slot_t, pt);
-    if (has_d) queue_prefix(a.q, slot_d, pd);
-    for (uint32_t f = threadIdx.x; f < pt[kQueueGroups]; f += kAtomicBlock) {
-      const int32_t j = queue_entry(a.q, slot_t, pt, f);
-      if ((uint32_t)j < a.n) a.x_post[j] = a.x_post[j] + 1.0f;
-    }
-    for (uint32_t f = threadIdx.x; f < pd[kQueueGroups]; f += kAtomicBlock) {
-      const int32_t i = queue_entry(a.q, slot_d, pd, f);
-      if ((uint32_t)i < a.n) a.x_pre[i] = a.x_pre[i] + 1.0f;
-    }
+    advance_traces<kAtomicBlock>(a, t0);
     return;
   }
   const uint32_t deliver_grid = a.x_post != nullptr && gridDim.x > 1 ? gridDim.x - 1 : gridDim.x;
@@ -454,13 +465,12 @@ __global__ __launch_bounds__(kAtomicBlock) void k_deliver_atomic(DeliverArgs a, 
 // beat three or four: the last, partly filled batch is shorter.  Three or four batches
 // in flight instead of two measured no faster: the stream then runs at the rate the
 // memory system gives pieces of a few hundred bytes at random addresses.
-template <bool kSrcW>
 constexpr int tiled_groups() { return 2; }
 
 // One 16-byte group of the tiled delivery's target stream: 8 consecutive 16-bit
-// targets of the flattened sub-rows, the weights of those 8 synapses (w0: 0-3, w1: 4-7;
-// with source weights w0.x is the sub-row's weight), and the mask of the elements that
-// lie inside the sub-row.
+// targets of the flattened sub-rows, the Q16 weights of those 8 synapses (w0: 0-3,
+// w1: 4-7; with source weights w0.x is the sub-row's weight), and the mask of the
+// elements that lie inside the sub-row.
 struct TiledGroup {
   int4 c, w0, w1;
   uint32_t mask;
@@ -469,8 +479,9 @@ struct TiledGroup {
 // Sub-rows are streamed as 16-byte aligned groups of 8 synapses of the 16-bit target
 // array; the elements of a group outside its sub-row are masked off.  Loads kU groups of
 // the flattened group range, 64 apart, from this lane's group `first`; `o` is the lane's
-// current sub-row (monotone).
-template <int kU, bool kSrcW>
+// current sub-row (monotone).  FP32 weights (plastic synapses) are taken to Q16 with the
+// atomic delivery's rounding: round(w * 2^16), ties to even.
+template <int kU, int kW>
 __device__ __forceinline__ void tiled_load(const DeliverArgs &a, const uint64_t *s_lo,
                                            const uint32_t *s_len, const uint32_t *s_pre,
                                            const int32_t *s_w, uint32_t first, uint32_t end,
@@ -486,8 +497,15 @@ __device__ __forceinline__ void tiled_load(const DeliverArgs &a, const uint64_t 
       const uint64_t lo = s_lo[o], hi = lo + s_len[o];
       const uint64_t g = (lo >> 3) + (idx - s_pre[o]);
       gr[u].c = reinterpret_cast<const int4 *>(a.col16)[g];
-      if constexpr (kSrcW) {
+      if constexpr (kW == kWeightSrc) {
         gr[u].w0.x = s_w[o];
+      } else if constexpr (kW == kWeightF32) {
+        const float4 f0 = reinterpret_cast<const float4 *>(a.w_f32)[2 * g];
+        const float4 f1 = reinterpret_cast<const float4 *>(a.w_f32)[2 * g + 1];
+        gr[u].w0 = make_int4(__float2int_rn(f0.x * 65536.0f), __float2int_rn(f0.y * 65536.0f),
+                             __float2int_rn(f0.z * 65536.0f), __float2int_rn(f0.w * 65536.0f));
+        gr[u].w1 = make_int4(__float2int_rn(f1.x * 65536.0f), __float2int_rn(f1.y * 65536.0f),
+                             __float2int_rn(f1.z * 65536.0f), __float2int_rn(f1.w * 65536.0f));
       } else {
         gr[u].w0 = reinterpret_cast<const int4 *>(a.w_q16)[2 * g];
         gr[u].w1 = reinterpret_cast<const int4 *>(a.w_q16)[2 * g + 1];
@@ -503,7 +521,7 @@ __device__ __forceinline__ void tiled_load(const DeliverArgs &a, const uint64_t 
 // Adds the masked elements of one group into the range's LDS accumulators.  A range
 // spans fewer than 65,536 targets, so a target t of the range is recovered from its low
 // 16 bits: t - range_lo = (t16 - range_lo) mod 2^16.
-template <bool kSrcW>
+template <int kW>
 __device__ __forceinline__ void tiled_accumulate(int32_t *acc, const TiledGroup &g, uint32_t range_lo) {
   const uint32_t words[4] = {(uint32_t)g.c.x, (uint32_t)g.c.y, (uint32_t)g.c.z, (uint32_t)g.c.w};
   const int32_t w[8] = {g.w0.x, g.w0.y, g.w0.z, g.w0.w, g.w1.x, g.w1.y, g.w1.z, g.w1.w};
@@ -511,7 +529,7 @@ __device__ __forceinline__ void tiled_accumulate(int32_t *acc, const TiledGroup 
   for (int k = 0; k < 8; ++k) {
     if (g.mask & (1u << k)) {
       const uint32_t t16 = (k & 1) ? words[k >> 1] >> 16 : words[k >> 1];
-      atomicAdd(&acc[(t16 - range_lo) & 0xFFFFu], kSrcW ? w[0] : w[k]);
+      atomicAdd(&acc[(t16 - range_lo) & 0xFFFFu], kW == kWeightSrc ? w[0] : w[k]);
     }
   }
 }
@@ -602,11 +620,12 @@ __device__ __forceinline__ uint32_t xcd_unit(uint32_t b, uint32_t grid, uint32_t
 // the range), a block scan lays the sub-rows end to end, and each wave streams a
 // contiguous share of the flattened 16-byte groups, 64 x tiled_groups() at a time, with
 // the next batch's loads issued before the current batch's LDS atomics.
-template <int kBlock, bool kSrcW>
+template <int kBlock, int kW>
 __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_t steps) {
   extern __shared__ __align__(16) int32_t acc[];
   constexpr int kWaves = kBlock / kWave;
-  constexpr int kU = tiled_groups<kSrcW>();
+  constexpr int kU = tiled_groups();
+  constexpr bool kSrcW = kW == kWeightSrc;
   __shared__ uint64_t s_lo[kBlock];
   __shared__ uint32_t s_len[kBlock];
   __shared__ uint32_t s_pre[kBlock + 1];
@@ -620,6 +639,11 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
   const uint32_t wave = threadIdx.x / kWave;
   const uint64_t t0 = a.ctl->t_deliver;
   close_window(a, t0, steps);
+  if (a.x_post != nullptr && blockIdx.x + 1 == gridDim.x) {  // eager STDP: the traces
+    advance_traces<kBlock>(a, t0);
+    return;
+  }
+  const uint32_t grid = a.x_post != nullptr ? gridDim.x - 1 : gridDim.x;  // delivering workgroups
 
   // ---- the window's queue lengths and the balanced schedule (wave 0), while the
   // other waves clear the accumulators ----
@@ -634,13 +658,13 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
     s_slot[lane] = slot;
 #pragma unroll
     for (uint32_t g = 0; g <= kQueueGroups; ++g) s_qpre[lane][g] = qp[g];
-    make_schedule(qp[kQueueGroups], steps, a.tiles, gridDim.x, sch);
+    make_schedule(qp[kQueueGroups], steps, a.tiles, grid, sch);
   } else {
     const uint32_t acc_n = min(kTileGroupMax, a.tiles) * a.tile_size;
     for (uint32_t j = threadIdx.x - kWave; j < acc_n; j += kBlock - kWave) acc[j] = 0;
   }
   __syncthreads();
-  const uint32_t unit = xcd_unit(blockIdx.x, gridDim.x, sch.first[steps]);
+  const uint32_t unit = xcd_unit(blockIdx.x, grid, sch.first[steps]);
   if (unit >= sch.first[steps]) return;  // more workgroups than ranges this window
   uint32_t w = 0;
   while (sch.first[w + 1] <= unit) ++w;
@@ -717,14 +741,14 @@ __global__ __launch_bounds__(kBlock) void k_deliver_tiled(DeliverArgs a, uint32_
       }
       uint32_t o = lo_j;
       TiledGroup cur[kU], nxt[kU];
-      tiled_load<kU, kSrcW>(a, s_lo, s_len, s_pre, s_w, beg + lane, end, o, cur);
+      tiled_load<kU, kW>(a, s_lo, s_len, s_pre, s_w, beg + lane, end, o, cur);
       for (uint32_t b0 = beg; b0 < end; b0 += kWave * kU) {
         const uint32_t nb = b0 + kWave * kU;
 #pragma unroll
         for (int u = 0; u < kU; ++u) nxt[u].mask = 0;
-        if (nb < end) tiled_load<kU, kSrcW>(a, s_lo, s_len, s_pre, s_w, nb + lane, end, o, nxt);
+        if (nb < end) tiled_load<kU, kW>(a, s_lo, s_len, s_pre, s_w, nb + lane, end, o, nxt);
 #pragma unroll
-        for (int u = 0; u < kU; ++u) tiled_accumulate<kSrcW>(acc, cur[u], tile_lo);
+        for (int u = 0; u < kU; ++u) tiled_accumulate<kW>(acc, cur[u], tile_lo);
 #pragma unroll
         for (int u = 0; u < kU; ++u) cur[u] = nxt[u];
       }
@@ -1101,16 +1125,19 @@ hipError_t prepare_deliver_tiled(uint32_t block, size_t *max_dynamic_lds) {
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
-  const void *fns[2];
+  const void *fns[3];
   if (block == 256) {
-    fns[0] = reinterpret_cast<const void *>(&k_deliver_tiled<256, false>);
-    fns[1] = reinterpret_cast<const void *>(&k_deliver_tiled<256, true>);
+    fns[0] = reinterpret_cast<const void *>(&k_deliver_tiled<256, kWeightQ16>);
+    fns[1] = reinterpret_cast<const void *>(&k_deliver_tiled<256, kWeightF32>);
+    fns[2] = reinterpret_cast<const void *>(&k_deliver_tiled<256, kWeightSrc>);
   } else if (block == 512) {
-    fns[0] = reinterpret_cast<const void *>(&k_deliver_tiled<512, false>);
-    fns[1] = reinterpret_cast<const void *>(&k_deliver_tiled<512, true>);
+    fns[0] = reinterpret_cast<const void *>(&k_deliver_tiled<512, kWeightQ16>);
+    fns[1] = reinterpret_cast<const void *>(&k_deliver_tiled<512, kWeightF32>);
+    fns[2] = reinterpret_cast<const void *>(&k_deliver_tiled<512, kWeightSrc>);
   } else {
-    fns[0] = reinterpret_cast<const void *>(&k_deliver_tiled<1024, false>);
-    fns[1] = reinterpret_cast<const void *>(&k_deliver_tiled<1024, true>);
+    fns[0] = reinterpret_cast<const void *>(&k_deliver_tiled<1024, kWeightQ16>);
+    fns[1] = reinterpret_cast<const void *>(&k_deliver_tiled<1024, kWeightF32>);
+    fns[2] = reinterpret_cast<const void *>(&k_deliver_tiled<1024, kWeightSrc>);
   }
   size_t dyn = (size_t)limit;
   for (const void *fn : fns) {
@@ -1132,20 +1159,25 @@ hipError_t launch_deliver_tiled(const DeliverArgs &a, uint32_t steps, uint32_t b
   // the schedule always fits when every step uses maximal ranges
   const uint32_t floor_grid = steps * ((a.tiles + kTileGroupMax - 1) / kTileGroupMax);
   if (grid < floor_grid) grid = floor_grid;
+  if (a.x_post) ++grid;  // one more workgroup advances the STDP traces
   const size_t lds = (size_t)min(kTileGroupMax, a.tiles) * a.tile_size * sizeof(int32_t);
-  const bool src_w = a.w_src != nullptr;
+  const int kind = a.w_src ? kWeightSrc : a.w_f32 ? kWeightF32 : kWeightQ16;
+  auto pick = [kind](auto q16, auto f32, auto src) { return kind == kWeightSrc ? src : kind == kWeightF32 ? f32 : q16; };
   switch (block) {
     case 256:
-      launch_kernel(src_w ? k_deliver_tiled<256, true> : k_deliver_tiled<256, false>, grid, 256, lds, s,
-                    ev.start, ev.stop, a, steps);
+      launch_kernel(pick(k_deliver_tiled<256, kWeightQ16>, k_deliver_tiled<256, kWeightF32>,
+                         k_deliver_tiled<256, kWeightSrc>),
+                    grid, 256, lds, s, ev.start, ev.stop, a, steps);
       break;
     case 512:
-      launch_kernel(src_w ? k_deliver_tiled<512, true> : k_deliver_tiled<512, false>, grid, 512, lds, s,
-                    ev.start, ev.stop, a, steps);
+      launch_kernel(pick(k_deliver_tiled<512, kWeightQ16>, k_deliver_tiled<512, kWeightF32>,
+                         k_deliver_tiled<512, kWeightSrc>),
+                    grid, 512, lds, s, ev.start, ev.stop, a, steps);
       break;
     default:
-      launch_kernel(src_w ? k_deliver_tiled<1024, true> : k_deliver_tiled<1024, false>, grid, 1024, lds, s,
-                    ev.start, ev.stop, a, steps);
+      launch_kernel(pick(k_deliver_tiled<1024, kWeightQ16>, k_deliver_tiled<1024, kWeightF32>,
+                         k_deliver_tiled<1024, kWeightSrc>),
+                    grid, 1024, lds, s, ev.start, ev.stop, a, steps);
       break;
   }
   return hipGetLastError();

@@ -68,19 +68,21 @@ def test_brunel_200k_sampled_rows_match_generator():
 
 def test_stdp_100k_all_2000_steps_eager_and_lazy():
     """Both forms of Update Synapses on the 2e8-synapse plastic network against one run
-    of the oracle: raster, V, traces, every weight and the touch count after 2,000 steps."""
+    of the oracle: raster, V, traces, every weight and the touch count after 2,000 steps;
+    eager with the tiled delivery (the default at this size) and with the atomic one."""
     spec = W.stdp_er()
     T = spec["steps"]
     print(f"[full] stdp_er n=100000 p=0.02: {T} steps, oracle", flush=True)
     o = oracle.OracleNet(spec, raster_cap=T)
     o.run(T)
-    for mode in ("eager", "lazy"):
-        print(f"[full] stdp {mode}", flush=True)
-        g = net(spec, raster_steps=T, plasticity=mode)
+    for mode, delivery, want in (("eager", "auto", 2), ("eager", "atomic", 1), ("lazy", "auto", 1)):
+        print(f"[full] stdp {mode} {delivery}", flush=True)
+        g = net(spec, raster_steps=T, plasticity=mode, delivery=delivery)
         g.run(T)
         rg, inf = compare_net(g, o, T)
         assert inf["plastic"] and inf["touches"] > 0 and inf["plasticity"] == (mode == "lazy")
-        print(f"[full] stdp {mode}: {int(np.unpackbits(rg.view(np.uint8)).sum())} spikes, "
+        assert inf["delivery"] == want
+        print(f"[full] stdp {mode} {delivery}: {int(np.unpackbits(rg.view(np.uint8)).sum())} spikes, "
               f"{inf['events']} events, {inf['touches']} touches", flush=True)
         g.close()
 

@@ -95,6 +95,10 @@ def test_lazy_refuses_delivery_changes_and_long_delays():
     g = _net(spec, plasticity="lazy")
     with pytest.raises(SnnError):
         g.set_delivery("atomic")
+    with pytest.raises(SnnError):
+        g.set_delivery("tiled")
+    with pytest.raises(SnnError, match="lazy"):
+        _net(spec, plasticity="lazy", delivery="tiled")
     spec = W.stdp_er(n=500, p=0.05, delay_steps=65, steps=20)
     with pytest.raises(SnnError, match="delay"):
         _net(spec, plasticity="lazy")

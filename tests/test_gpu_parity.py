@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_1912_07423_amd import workloads as W
-from gpu_compare import bits as _bits, compare_run as _compare_run, net as _net
+from gpu_compare import bits as _bits, compare_net as _compare_net, compare_run as _compare_run, net as _net
 
 pytestmark = pytest.mark.gpu
 
@@ -256,6 +256,44 @@ def test_autotune_delivery_keeps_state_and_parity():
     o.run(150)
     assert np.array_equal(g.raster_bits(0, 150), o.raster_words()[:150])
     assert np.array_equal(_bits(g.state()["v"]), _bits(o.v()))
+
+
+def _plastic_specs():
+    return {
+        "d10": W.stdp_er(n=2000, p=0.05, delay_steps=10, steps=400),
+        "d1_ragged": W.stdp_er(n=777, p=0.08, delay_steps=1, rate_hz=40.0, seed=23, steps=350),
+        "d3_fast": W.stdp_er(n=600, p=0.1, delay_steps=3, rate_hz=400.0, n_ext=200, seed=21, steps=300),
+    }
+
+
+@pytest.mark.parametrize("tiles", [0, 1, 7])
+@pytest.mark.parametrize("name", list(_plastic_specs()))
+def test_plastic_tiled_delivery(name, tiles):
+    """Eager STDP with the tiled delivery (one step per launch): FP32 weights streamed in
+    16-byte groups and rounded to Q16 as the atomic kernel rounds them, the traces
+    advanced by the launch's extra workgroup.  Raster, V, traces, every weight and the
+    touch count equal the oracle's."""
+    spec = _plastic_specs()[name]
+    print(f"[plastic tiled] {name} tiles={tiles}", flush=True)
+    rg, inf = _compare_run(spec, spec["steps"], delivery="tiled", tiles=tiles)
+    assert inf["delivery"] == 2 and inf["plastic"] and inf["touches"] > 0
+    assert rg.any()
+
+
+def test_plastic_delivery_switched_between_steps():
+    """A plastic network switched from the atomic delivery (which adds into the input
+    accumulator the update cleared) to the tiled one (which overwrites it) and back."""
+    spec = W.stdp_er(n=2000, p=0.05, delay_steps=10, steps=300)
+    g = _net(spec, raster_steps=300, delivery="atomic")
+    g.run(100)
+    g.set_delivery("tiled", tiles=5)
+    assert g.info()["delivery"] == 2
+    g.run(100)
+    g.set_delivery("atomic")
+    g.run(100)
+    o = oracle.OracleNet(spec, raster_cap=300)
+    o.run(300)
+    _compare_net(g, o, 300)
 
 
 @pytest.mark.parametrize("delivery", ["atomic", "tiled"])
