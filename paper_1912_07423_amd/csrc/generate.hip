@@ -110,6 +110,32 @@ __device__ __forceinline__ uint64_t div_floor_u64(uint64_t num, uint64_t den, do
   return q;
 }
 
+// 64-bit inclusive scan over the wave by DPP lane shifts applied to both halves (the
+// same shifts as the 32-bit scan: 1, 2, 4, 8 inside rows of 16 lanes, then rows 0 and 2
+// into rows 1 and 3, then lane 31 into rows 2 and 3); every lane must be active.
+template <int kCtrl, int kRows, bool kZeroOutside>
+__device__ __forceinline__ uint64_t add_dpp_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, kCtrl, kRows, 0xf, kZeroOutside);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), kCtrl, kRows, 0xf, kZeroOutside);
+  return v + (((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint64_t wave_scan_u64(uint64_t x) {
+  x = add_dpp_u64<0x111, 0xf, true>(x);   // row_shr:1
+  x = add_dpp_u64<0x112, 0xf, true>(x);   // row_shr:2
+  x = add_dpp_u64<0x114, 0xf, true>(x);   // row_shr:4
+  x = add_dpp_u64<0x118, 0xf, true>(x);   // row_shr:8
+  x = add_dpp_u64<0x142, 0xa, false>(x);  // row_bcast:15, rows 1 and 3
+  x = add_dpp_u64<0x143, 0xc, false>(x);  // row_bcast:31, rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ uint64_t last_lane_u64(uint64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, kWave - 1);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), kWave - 1);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Gaps of one fixed out-degree row kept in LDS between the two passes (the first pass of
 // Sec. III-A.2 runs in shared memory): the first 4 x cache_blocks gaps of a row are
 // stored as uint32 (a gap is below 2^29: -ln(2^-24) 2^24 < 2.8e8) and read back by the
@@ -164,35 +190,49 @@ __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint
       }
     }
     const uint64_t lane_total = gap[0] + gap[1] + gap[2] + gap[3];
-    const uint64_t incl = wave_inclusive_scan(lane_total);
+    const uint64_t incl = wave_scan_u64(lane_total);
     uint64_t s = carry + (incl - lane_total);
+    int32_t tgt[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint32_t k = 4u * b + q;
       s += gap[q];  // S_{k+1}
-      if (b < n_blocks && k < k_out) {
-        uint64_t x = k;
-        if (total != 0) {
-          // q = floor(s spare / total + 1/2) < 2^32 from binary64: the six roundings
-          // below (s, total, fma, 1 / total, product) leave a relative error under
-          // 2^-50, i.e. under 2^-18 absolute, so the floor of the estimate is exact
-          // unless it lies that close to an integer; then the exact integer quotient.
-          const double est = fma((double)s, spare_d, half_total_d) * inv_total;
-          const double fl = floor(est), fr = est - fl;
-          const uint64_t q = (fr >= 0x1p-18 && fr <= 1.0 - 0x1p-18)
-                                 ? (uint64_t)fl
-                                 : div_floor_u64(2u * s * pj.spare + total, two_total, inv_two_total);
-          x = q + k;
+      uint32_t x = k;
+      if (total != 0) {
+        // q = floor(s spare / total + 1/2) <= spare < 2^32 from binary64: the six
+        // roundings below (s, total, fma, 1 / total, product) leave a relative error
+        // under 2^-50, i.e. under 2^-18 absolute, so the floor of the estimate is exact
+        // unless it lies that close to an integer; then the exact integer quotient.
+        const double est = fma((double)s, spare_d, half_total_d) * inv_total;
+        const double fl = floor(est), fr = est - fl;
+        const uint32_t q = (fr >= 0x1p-18 && fr <= 1.0 - 0x1p-18)
+                               ? (uint32_t)fl
+                               : (uint32_t)div_floor_u64(2u * s * pj.spare + total, two_total, inv_two_total);
+        x = q + k;
+      }
+      if (x >= self_local) x += 1;
+      tgt[q] = (int32_t)(pj.off + x);
+    }
+    // a whole block of four targets goes out as one 16-byte store when the row starts
+    // on a 16-byte boundary; the row's last, partial block element by element
+    const uint64_t p0 = pos + 4u * b;
+    if (b < n_blocks) {
+      if ((pos & 3u) == 0 && 4u * b + 3u < k_out) {
+        *reinterpret_cast<int4 *>(col + p0) = make_int4(tgt[0], tgt[1], tgt[2], tgt[3]);
+        if (w_q16) *reinterpret_cast<int4 *>(w_q16 + p0) = make_int4(pj.w_q16, pj.w_q16, pj.w_q16, pj.w_q16);
+        if (w_f32) *reinterpret_cast<float4 *>(w_f32 + p0) = make_float4(pj.w_f32, pj.w_f32, pj.w_f32, pj.w_f32);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (4u * b + q < k_out) {
+            col[p0 + q] = tgt[q];
+            if (w_q16) w_q16[p0 + q] = pj.w_q16;
+            if (w_f32) w_f32[p0 + q] = pj.w_f32;
+          }
         }
-        uint32_t local = (uint32_t)x;
-        if (local >= self_local) local += 1;
-        const uint64_t p = pos + k;
-        col[p] = (int32_t)(pj.off + local);
-        if (w_q16) w_q16[p] = pj.w_q16;
-        if (w_f32) w_f32[p] = pj.w_f32;
       }
     }
-    carry += __shfl(incl, kWave - 1, kWave);
+    carry += last_lane_u64(incl);
   }
 }
 
