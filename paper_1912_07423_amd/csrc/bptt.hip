@@ -323,15 +323,17 @@ __global__ void k_lam_u(BpttArgs a, const float *g_loss) {
   }
 }
 
-// Membrane adjoint of step t: one wavefront per hidden neuron i, lane = batch.
-// lam_next = lamV_{t+1} ([H][64], zeros for step T), v_t = V_t, lam_out = lamV_t.
-__global__ __launch_bounds__(256) void k_adjoint_step(BpttArgs a, uint32_t t, const float *v_t,
-                                                      const float *lam_next, float *lam_out) {
-  const uint32_t i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-  if (i >= a.H) return;
+// Readout part of the spike adjoint of every step, the first terms of the sum that
+// k_adjoint_step completes: dsr[t][i][b] = sum_o w_out[i][o] lamu[t][o][b], ascending o
+// from +0.  It does not depend on the membrane adjoint, so all steps run in parallel (a
+// wavefront per (t, i)), ahead of the sequential adjoint steps.
+__global__ __launch_bounds__(256) void k_readout_adjoint(BpttArgs a, float *dsr) {
+  const uint64_t w = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (w >= (uint64_t)a.T * a.H) return;
+  const uint32_t t = (uint32_t)(w / a.H), i = (uint32_t)(w % a.H);
   const uint32_t b = lane_id();
   const float *lu = a.lamu + (size_t)t * a.O * 64 + b;
-  // the readout term, in ascending o, eight loads issued before their terms are added
+  // in ascending o, eight loads issued before their terms are added
   float ds = 0.0f;
   uint32_t o = 0;
   for (; o + 8 <= a.O; o += 8) {
@@ -345,6 +347,19 @@ __global__ __launch_bounds__(256) void k_adjoint_step(BpttArgs a, uint32_t t, co
     for (int u = 0; u < 8; ++u) ds = ds + wv[u] * lv[u];
   }
   for (; o < a.O; ++o) ds = ds + a.w_out[(size_t)i * a.O + o] * lu[(size_t)o * 64];
+  dsr[w * 64 + b] = ds;
+}
+
+// Membrane adjoint of step t: one wavefront per hidden neuron i, lane = batch.
+// lam_next = lamV_{t+1} ([H][64], zeros for step T), v_t = V_t; lam_out = lamV_t holds
+// the readout part of the spike adjoint (k_readout_adjoint) on entry and receives
+// lamV_t.
+__global__ __launch_bounds__(256) void k_adjoint_step(BpttArgs a, uint32_t t, const float *v_t,
+                                                      const float *lam_next, float *lam_out) {
+  const uint32_t i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
+  if (i >= a.H) return;
+  const uint32_t b = lane_id();
+  float ds = lam_out[(size_t)i * 64 + b];  // the readout terms, in ascending o
   ds = ordered_gather_pipe(ds, a.rec_ptr[i], a.rec_ptr[i + 1], a.rec_col, a.w_rec, lam_next, b);
   const float ln = lam_next[(size_t)i * 64 + b];
   if (!a.detach_reset) ds = ds - a.theta * ln;
@@ -551,6 +566,9 @@ hipError_t bptt_backward_body(const BpttArgs &g, hipStream_t s) {
                      g.xbits, g.flags);
   hipLaunchKernelGGL(k_bits, dim3(blocks_for((uint64_t)g.T * g.H, 4)), dim3(256), 0, s, g.s, g.H, g.T, g.B,
                      g.sbits, g.flags + 1);
+  // the readout part of every step's spike adjoint, into lamv (each adjoint step reads
+  // its own entries, then overwrites them with lamV_t)
+  hipLaunchKernelGGL(k_readout_adjoint, dim3(blocks_for((uint64_t)g.T * g.H, 4)), dim3(256), 0, s, g, g.lamv);
   const dim3 grid(blocks_for(g.H, 4));
   const uint32_t n_seg = (g.T + g.K - 1) / g.K;
   for (int32_t seg = (int32_t)n_seg - 1; seg >= 0; --seg) {
