@@ -360,10 +360,13 @@ __global__ __launch_bounds__(256) void k_adjoint_step(BpttArgs a, uint32_t t, co
   if (i >= a.H) return;
   const uint32_t b = lane_id();
   float ds = lam_out[(size_t)i * 64 + b];  // the readout terms, in ascending o
-  ds = ordered_gather_pipe(ds, a.rec_ptr[i], a.rec_ptr[i + 1], a.rec_col, a.w_rec, lam_next, b);
+  // the neuron's own values are requested before the gather, so that they are not a
+  // round trip of their own after it (0.08 ms per iteration)
   const float ln = lam_next[(size_t)i * 64 + b];
+  const float vt = v_t[(size_t)i * 64 + b];
+  ds = ordered_gather_pipe(ds, a.rec_ptr[i], a.rec_ptr[i + 1], a.rec_col, a.w_rec, lam_next, b);
   if (!a.detach_reset) ds = ds - a.theta * ln;
-  const float z = v_t[(size_t)i * 64 + b] - a.theta;
+  const float z = vt - a.theta;
   lam_out[(size_t)i * 64 + b] = a.beta * ln + surrogate(z, a.slope, a.smooth != 0) * ds;
 }
 
