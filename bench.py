@@ -523,7 +523,9 @@ def summarize_pmc(fetch_dir, write_dir, lines, copy_mib, command):
         factor = known / (copy_kib * 1024.0)
         out[f"{key}_copy_kib"] = copy_kib
         out[f"{key}_factor"] = factor
-        out[f"{key}_kib_per_dispatch"] = deliver
+        # the per-dispatch counts summarised (min, mean, max KiB): the record stays short
+        out[f"{key}_kib_per_dispatch"] = {"min": min(deliver), "mean": sum(deliver) / len(deliver),
+                                          "max": max(deliver)}
         out[f"{key}_bytes_per_launch"] = sum(deliver) / len(deliver) * 1024.0 * factor
         out[f"{key}_dispatches"] = len(deliver)
     out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]

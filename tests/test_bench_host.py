@@ -58,6 +58,8 @@ def test_traffic_summary_scales_by_the_copy(tmp_path, monkeypatch):
     assert t["fetch_bytes_per_launch"] == pytest.approx(200.0 * 1024 * 2)
     assert t["write_bytes_per_launch"] == pytest.approx(10.0 * 1024)
     assert t["bytes_per_launch"] == pytest.approx(200.0 * 1024 * 2 + 10.0 * 1024)
+    assert t["fetch_kib_per_dispatch"] == {"min": 100.0, "mean": 200.0, "max": 300.0}
+    assert t["fetch_dispatches"] == 2 and t["write_dispatches"] == 2
     assert t["kernel_source_sha"] == bench.kernel_source_sha()
     assert bench.measured_traffic(point) == pytest.approx(t["bytes_per_launch"])
     # any other operating point gets no traffic figure
