@@ -296,6 +296,27 @@ def test_plastic_delivery_switched_between_steps():
     _compare_net(g, o, 300)
 
 
+def test_autotune_plastic_delivery_keeps_state_and_parity():
+    """The autotuner on an eagerly plastic network times both deliveries (the tiled one
+    with FP32 weights) on scratch buffers: weights, traces and the run that follows
+    stay the oracle's."""
+    spec = W.stdp_er(n=3000, p=0.05, delay_steps=10, steps=200)
+    g = _net(spec, raster_steps=200)
+    g.run(60)
+    before = g.state(weights=True)
+    t = g.autotune_delivery(reps=2)
+    print(f"[autotune plastic] {t}", flush=True)
+    assert t["delivery"] in ("atomic", "tiled") and t["ms_per_launch"] > 0 and t["events_per_launch"] > 0
+    after = g.state(weights=True)
+    for k in ("v", "x_pre", "x_post", "w_f32"):
+        assert np.array_equal(_bits(before[k]), _bits(after[k])), k
+    assert np.array_equal(before["input"], after["input"]) and g.t == 60
+    g.run(140)
+    o = oracle.OracleNet(spec, raster_cap=200)
+    o.run(200)
+    _compare_net(g, o, 200)
+
+
 @pytest.mark.parametrize("delivery", ["atomic", "tiled"])
 def test_network_without_synapses(delivery):
     """p = 0: every row is empty; the drive alone makes the neurons fire."""
