@@ -4,10 +4,12 @@ times: the whole HIP path against the oracle's complete run of the same network.
   * 4,000-neuron CUBA network (ER p = 0.02, no delays): all 10,000 steps.
   * 200,000-neuron Brunel network (fixed out-degree 5,000, 1e9 synapses, 15-step
     delay, Poisson drive): the benchmark's 300-step settle period, its warm-up bench step
-    and one timed bench step (1,000 simulation steps each), with the tiled delivery, 87 base tiles (2-byte boundaries), one weight per source, and the device-side
-    schedule, exactly as benchmarked.
+    and one timed bench step (1,000 simulation steps each), with the tiled delivery, 348
+    base tiles (2-byte boundaries), one weight per source, and the device-side schedule,
+    exactly as benchmarked.
   * 100,000-neuron plastic network (ER p = 0.02, 2e8 synapses, STDP on E->E, 10-step
-    delay): all 2,000 steps, final FP32 weights of every synapse compared bit for bit.
+    delay): all 2,000 steps, final FP32 weights of every synapse compared bit for bit,
+    eagerly with the tiled delivery (the default) and with the atomic one, and lazily.
   * the largest Eq. 1 Brunel network (400,000 neurons, 1.6e10 synapses): sampled rows,
     and two steps' deliveries (after 300 steps) recomputed by the oracle from the GPU's own spikes.
 
