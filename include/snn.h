@@ -286,10 +286,12 @@ typedef struct {
 } snn_delivery_tuning;
 
 /* Time the atomic variant and the tiled one over base tiles of about 384, 576 and
- * 768 targets (ranges of up to 32) x 512/1024-thread workgroups x 1, 2 and 3 workgroups per CU, each on the
- * spikes of the network's latest window (taken from its raster), `reps` launches each;
- * keep the fastest and return it.  The simulation state is unchanged.  SNN_E_STATE if
- * fewer than `window` steps have run. */
+ * 768 targets (ranges of up to 32) x 512/1024-thread workgroups x 1, 2 and 3
+ * workgroups per CU (the tiled ones for networks of at least 1,024 neurons), each on
+ * the spikes of the network's latest window (taken from its raster), `reps` launches
+ * each, on scratch queues and accumulators; keep the fastest and return it.  The
+ * simulation state (weights and traces included) is unchanged.  SNN_E_STATE if fewer
+ * than `window` steps have run, or for a network with lazy plasticity. */
 snn_status snn_autotune_delivery(snn_network *net, uint32_t reps, snn_delivery_tuning *chosen);
 
 void snn_destroy(snn_network *net);
