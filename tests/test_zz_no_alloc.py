@@ -2,8 +2,9 @@
 (snn_time_delivery_static, include/snn.h) against the allocating one
 (snn_time_delivery): the same events per launch on the same spike lists, for the tiled
 and the atomic delivery, with explicit step counts and round-robin ids, on two calls in
-a row (the second smaller); the network's own state untouched (a run afterwards still
-matches the oracle); a window too large for the fixed array refused with SNN_E_INVALID."""
+a row (the second smaller), on a static and on an eagerly plastic network; the
+network's own state untouched (a run afterwards still matches the oracle); a window too
+large for the fixed array refused with SNN_E_INVALID."""
 import numpy as np
 import pytest
 
@@ -61,6 +62,34 @@ def test_static_scratch_matches_allocating_timing(delivery):
     g.run(60)
     o.run(60)
     compare_net(g, o, 60)
+    g.close()
+
+
+@pytest.mark.parametrize("delivery", ["tiled", "atomic"])
+def test_static_scratch_plastic_network(delivery):
+    """An eagerly plastic network (one-step windows, FP32 weights): the same events as
+    the allocating call, weights and traces untouched."""
+    spec = W.stdp_er(n=3000, p=0.05, delay_steps=10, steps=80)
+    print(f"[no-alloc] stdp 3k p0.05 d10, {delivery}", flush=True)
+    g = _net(spec, raster_steps=80, delivery=delivery)
+    assert g.info()["delivery_name"] == delivery and g.info()["window"] == 1
+    g.run(40)
+    before = g.state(weights=True)
+    row_ptr = g.synapses()[0]
+    rng = np.random.default_rng(13)
+    for count in (400, 25):
+        ids = rng.choice(g.info()["n"], count, replace=False).astype(np.uint32)
+        want = _expected_events(row_ptr, ids)
+        _, ev_a = g.time_delivery(ids, reps=2)
+        _, ev_s = g.time_delivery_static(ids, reps=2)
+        assert ev_a == ev_s == want
+    after = g.state(weights=True)
+    for k in ("v", "x_pre", "x_post", "w_f32"):
+        assert np.array_equal(np.asarray(before[k]).view(np.uint32), np.asarray(after[k]).view(np.uint32)), k
+    g.run(40)
+    o = oracle.OracleNet(spec, raster_cap=80)
+    o.run(80)
+    compare_net(g, o, 80)
     g.close()
 
 
