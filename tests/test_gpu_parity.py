@@ -263,6 +263,7 @@ def _plastic_specs():
         "d10": W.stdp_er(n=2000, p=0.05, delay_steps=10, steps=400),
         "d1_ragged": W.stdp_er(n=777, p=0.08, delay_steps=1, rate_hz=40.0, seed=23, steps=350),
         "d3_fast": W.stdp_er(n=600, p=0.1, delay_steps=3, rate_hz=400.0, n_ext=200, seed=21, steps=300),
+        "d64": W.stdp_er(n=1000, p=0.05, delay_steps=64, rate_hz=40.0, seed=24, steps=400),
     }
 
 
