@@ -192,6 +192,17 @@ snn_status snn_build_network(const snn_params *prm, const snn_population *pops, 
                              const snn_projection *proj, uint32_t n_proj,
                              const snn_allocator *alloc, void *stream, snn_network **out);
 
+/* Step (b) of the generator of Fig. 2 (Sec. III-A.2) as the fixed out-degree fill
+ * evaluates it: gaps[k] = floor(-ln(u) 2^24) with u = ((words[k] >> 8) + 1) 2^-24 and
+ * -ln the library's fixed binary64 logarithm (2 atanh series after reduction to
+ * [sqrt(1/2), sqrt(2)), the same for every caller).  words and gaps are device
+ * pointers to n uint32 each (4-byte aligned; not overlapping), owned by the caller;
+ * the kernel is queued on `stream` (NULL: the default stream) and the call returns
+ * without waiting.  SNN_E_INVALID for NULL pointers with n > 0, SNN_E_HIP if the
+ * launch fails.  Exists so that the fill's gap evaluation can be checked on every one
+ * of its 2^24 inputs. */
+snn_status snn_spacing_gaps(const uint32_t *words, uint64_t n, uint32_t *gaps, void *stream);
+
 /* Advance one step t -> t+1 (Fig. 1: update neurons, FIFO, [update synapses],
  * receive spikes).  Asynchronous. */
 snn_status snn_step(snn_network *net);

@@ -125,6 +125,7 @@ SIGNATURES = {
                                 C.c_uint64, C.POINTER(C.c_uint64)]),
     "snn_get_synapses": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "snn_get_drive_table": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint32]),
+    "snn_spacing_gaps": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]),
     "snn_set_profiling": (C.c_int32, [C.c_void_p, C.c_int32]),
     "snn_get_profile": (C.c_int32, [C.c_void_p, C.POINTER(Profile)]),
     "snn_reset_profile": (C.c_int32, [C.c_void_p]),

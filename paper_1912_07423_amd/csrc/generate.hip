@@ -6,7 +6,9 @@
 //    regenerates the same words and compacts the hits in ascending target order.
 //  * fixed out-degree projections: the exponential-spacing generator of Fig. 2 with
 //    the gaps truncated to 2^-24 fixed point, so the prefix sum, normalisation,
-//    scaling, rounding and the +k step are exact integer arithmetic.
+//    scaling, rounding and the +k step are exact integer arithmetic.  Each gap is
+//    estimated from a 256-entry table and a short series; the few whose estimate lies
+//    too close to an integer evaluate the defined binary64 logarithm instead.
 #include <algorithm>
 
 #include "device_math.h"
@@ -136,16 +138,99 @@ __device__ __forceinline__ uint64_t last_lane_u64(uint64_t x) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// ---- the gaps of Fig. 2, step (b) ----
+// The gap of a 32-bit word is floor(-ln(u) 2^24) with u = ((word >> 8) + 1) 2^-24 and
+// -ln the fixed binary64 sequence neg_log, about 40 binary64 operations with a
+// correctly rounded division among them.  The fill estimates it instead (Tang's table
+// method): j = (word >> 8) + 1 = 2^e m with m in [1, 2), i = the kGapBits bits of m after
+// its leading one, c_i = 1 + (i + 1/2) 2^-kGapBits, F_i = 1/c_i rounded,
+// L_i = neg_log(F_i); then r = m F_i - 1 (|r| <= 2^-(kGapBits+1) up to rounding),
+// ln(1 + r) by its Taylor series to r^8, and -ln u = (24 - e) ln 2 - L_i - ln(1 + r).
+// Over all 2^24 values of j the estimate, in units of 2^-24, lies within 6e-8 of the
+// defined value, so it has the same floor unless its fractional part is within 2^-16 of
+// an integer; that happens for 528 of the 2^24 values, and those lanes evaluate neg_log.
+// The 16 entries fill the 64 LDS banks once, so a wave's table reads do not conflict
+// (a 256-entry table with a 4-term series issues fewer instructions but was slower).
+constexpr int kGapBits = 4;
+constexpr int kGapTable = 1 << kGapBits;
+constexpr int kGapTerms = 8;
+constexpr double kGapMargin = 0x1p-16;
+
+// Entry i = {F_i 2^-31, L_i}, written by the calling workgroup; ends with a barrier.
+__device__ void load_gap_table(double2 *tbl) {
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kGapTable; i += blockDim.x) {
+    const double f = 1.0 / (1.0 + ((double)i + 0.5) / (double)kGapTable);
+    tbl[i] = make_double2(f * 0x1p-31, neg_log(f));
+  }
+  __syncthreads();
+}
+
+// The table entry of a word: its index, with j = (word >> 8) + 1 normalised to
+// jn = m 2^31 and lz = 31 - e.
+__device__ __forceinline__ uint32_t gap_index(uint32_t word, uint32_t &jn, uint32_t &lz) {
+  const uint32_t j = (word >> 8) + 1u;
+  lz = (uint32_t)__builtin_clz(j);  // 7 ... 31
+  jn = j << lz;
+  return (jn >> (31 - kGapBits)) & (uint32_t)(kGapTable - 1);
+}
+
+// The estimate's floor in `gap` from the word's table entry t; false if the estimate is
+// too close to an integer.  Branch-free, so that a lane's four estimates overlap.
+__device__ __forceinline__ bool gap_estimate(uint32_t jn, uint32_t lz, double2 t, uint32_t &gap) {
+  constexpr double kLn2 = 0x1.62e42fefa39efp-1;
+  const double r = fma((double)jn, t.x, -1.0);
+  // ln(1 + r) = r + r^2 (-1/2 + r (1/3 + r (-1/4 + ...))), coefficients (-1)^(k+1) / k
+  double q = ((kGapTerms & 1) ? 1.0 : -1.0) / (double)kGapTerms;
+#pragma unroll
+  for (int k = kGapTerms - 1; k >= 2; --k) q = fma(r, q, ((k & 1) ? 1.0 : -1.0) / (double)k);
+  const double ln1p = fma(r * r, q, r);
+  // lz - 7 = 24 - e
+  const double y = (fma((double)(int32_t)(lz - 7u), kLn2, -t.y) - ln1p) * 16777216.0;
+  const double fr = y - floor(y);
+  gap = (uint32_t)fmax(y, 0.0);
+  return fr >= kGapMargin && fr <= 1.0 - kGapMargin;
+}
+
+__device__ __forceinline__ uint32_t gap_of(uint32_t word, const double2 *tbl) {
+  uint32_t jn, lz, gap;
+  const double2 t = tbl[gap_index(word, jn, lz)];
+  if (!gap_estimate(jn, lz, t, gap)) gap = (uint32_t)spacing_gap(word);
+  return gap;
+}
+
+// The four gaps of one Philox block; gaps past `last` (k > last) are 0.  The four table
+// entries are read before any estimate, so the LDS reads are in flight together.
+__device__ __forceinline__ void gaps4(const Words4 &r, uint32_t k0, uint32_t last, const double2 *tbl,
+                                      uint32_t g[4]) {
+  uint32_t jn[4], lz[4];
+  double2 t[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) t[q] = tbl[gap_index(r.w[q], jn[q], lz[q])];
+  bool ok[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ok[q] = gap_estimate(jn[q], lz[q], t[q], g[q]);
+  if (!(ok[0] && ok[1] && ok[2] && ok[3])) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (!ok[q]) g[q] = (uint32_t)spacing_gap(r.w[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) g[q] = k0 + q <= last ? g[q] : 0u;
+}
+
 // Gaps of one fixed out-degree row kept in LDS between the two passes (the first pass of
 // Sec. III-A.2 runs in shared memory): the first 4 x cache_blocks gaps of a row are
 // stored as uint32 (a gap is below 2^29: -ln(2^-24) 2^24 < 2.8e8) and read back by the
 // second pass; gaps past the cache are regenerated.  The cache is sized at launch to the
-// longest fixed out-degree row, at most kGapCacheMax gaps (20 KiB) per wavefront.
-constexpr uint32_t kGapCacheMax = 5120;
+// longest fixed out-degree row, at most kGapCacheMax gaps per wavefront: the most that
+// lets two workgroups, each with its log table, share one CU's 160 KiB.
+constexpr uint32_t kGapCacheMax =
+    (uint32_t)((160u * 1024u / 2u - kGapTable * sizeof(double2)) / (kGenWavesPerBlock * sizeof(uint4))) * 4u;
+static_assert(kGapCacheMax == 5104, "gap cache of 1,276 blocks of four per wavefront");
 
 __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint64_t pos,
                            int32_t *col, int32_t *w_q16, float *w_f32, uint4 *cache,
-                           uint32_t cache_blocks) {
+                           uint32_t cache_blocks, const double2 *tbl) {
   const uint32_t k_out = pj.k;
   if (k_out == 0) return;
   const uint32_t stream_word2 = 1u + pj.first_pop;
@@ -157,11 +242,8 @@ __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint
   for (uint32_t b = lane_id(); b < n_blocks; b += kWave) {
     const Words4 r = philox(i, b, stream_word2, kStreamConn, g.key0, g.key1);
     uint32_t gq[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      gq[q] = 4u * b + q <= k_out ? (uint32_t)spacing_gap(r.w[q]) : 0u;
-      part += gq[q];
-    }
+    gaps4(r, 4u * b, k_out, tbl, gq);
+    part += (uint64_t)(gq[0] + gq[1] + gq[2] + gq[3]);
     if (b < cache_blocks) cache[b] = make_uint4(gq[0], gq[1], gq[2], gq[3]);
   }
   const uint64_t total = wave_sum(part);
@@ -174,7 +256,7 @@ __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint
   uint64_t carry = 0;
   for (uint32_t it = 0; it < n_iter; ++it) {
     const uint32_t b = it * kWave + lane_id();
-    uint64_t gap[4] = {0, 0, 0, 0};
+    uint32_t gap[4] = {0, 0, 0, 0};
     if (b < n_blocks) {
       if (b < cache_blocks) {
         const uint4 c = cache[b];
@@ -184,30 +266,33 @@ __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint
         gap[3] = c.w;
       } else {
         const Words4 r = philox(i, b, stream_word2, kStreamConn, g.key0, g.key1);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (4u * b + q <= k_out) gap[q] = spacing_gap(r.w[q]);
+        gaps4(r, 4u * b, k_out, tbl, gap);
       }
     }
-    const uint64_t lane_total = gap[0] + gap[1] + gap[2] + gap[3];
+    // four gaps are below 2^31 together
+    const uint32_t lane_total = gap[0] + gap[1] + gap[2] + gap[3];
     const uint64_t incl = wave_scan_u64(lane_total);
-    uint64_t s = carry + (incl - lane_total);
+    const uint64_t s0 = carry + (incl - lane_total);
+    const double s0_d = (double)s0;
+    uint32_t in_lane = 0;
     int32_t tgt[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint32_t k = 4u * b + q;
-      s += gap[q];  // S_{k+1}
+      in_lane += gap[q];  // S_{k+1} = s0 + in_lane
       uint32_t x = k;
       if (total != 0) {
-        // q = floor(s spare / total + 1/2) <= spare < 2^32 from binary64: the six
-        // roundings below (s, total, fma, 1 / total, product) leave a relative error
-        // under 2^-50, i.e. under 2^-18 absolute, so the floor of the estimate is exact
-        // unless it lies that close to an integer; then the exact integer quotient.
-        const double est = fma((double)s, spare_d, half_total_d) * inv_total;
+        // q = floor(S_{k+1} spare / total + 1/2) <= spare < 2^32 from binary64: the
+        // roundings below (s0, s0 + in_lane, total, the fma, 1 / total, the product) add
+        // up to a relative error under 7 2^-53 < 2^-50, i.e. under 2^-18 absolute, so
+        // the floor of the estimate is exact unless it lies that close to an integer;
+        // then the exact integer quotient.
+        const double est = fma(s0_d + (double)in_lane, spare_d, half_total_d) * inv_total;
         const double fl = floor(est), fr = est - fl;
         const uint32_t q = (fr >= 0x1p-18 && fr <= 1.0 - 0x1p-18)
                                ? (uint32_t)fl
-                               : (uint32_t)div_floor_u64(2u * s * pj.spare + total, two_total, inv_two_total);
+                               : (uint32_t)div_floor_u64(2u * (s0 + in_lane) * pj.spare + total, two_total,
+                                                         inv_two_total);
         x = q + k;
       }
       if (x >= self_local) x += 1;
@@ -240,6 +325,8 @@ __global__ __launch_bounds__(kGenBlock) void k_fill_rows(GenArgs g, const uint64
                                                          int32_t *col, int32_t *w_q16,
                                                          float *w_f32, uint32_t cache_blocks) {
   extern __shared__ uint4 gap_cache[];  // [kGenWavesPerBlock][cache_blocks]
+  __shared__ double2 tbl[kGapTable];
+  load_gap_table(tbl);
   uint4 *cache = gap_cache + (threadIdx.x / kWave) * cache_blocks;
   const uint32_t wave = blockIdx.x * kGenWavesPerBlock + threadIdx.x / kWave;
   const uint32_t n_waves = gridDim.x * kGenWavesPerBlock;
@@ -251,10 +338,21 @@ __global__ __launch_bounds__(kGenBlock) void k_fill_rows(GenArgs g, const uint64
       if (pj.kind == SNN_PROJ_ER) {
         pos = er_fill(g, pj, i, pos, col, w_q16, w_f32);
       } else {
-        fixed_fill(g, pj, i, pos, col, w_q16, w_f32, cache, cache_blocks);
+        fixed_fill(g, pj, i, pos, col, w_q16, w_f32, cache, cache_blocks, tbl);
         pos += pj.k;
       }
     }
+  }
+}
+
+// The gaps of caller-given words, by the fill's own evaluation.
+__global__ __launch_bounds__(kGenBlock) void k_spacing_gaps(const uint32_t *words, uint64_t n,
+                                                            uint32_t *gaps) {
+  __shared__ double2 tbl[kGapTable];
+  load_gap_table(tbl);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+    gaps[k] = gap_of(words[k], tbl);
   }
 }
 
@@ -455,6 +553,13 @@ hipError_t launch_fill_rows(const GenArgs &g, uint32_t max_fixed_k, const uint64
     if (e != hipSuccess) return e;
   }
   k_fill_rows<<<row_grid(g.n), kGenBlock, lds, s>>>(g, row_ptr, col, w_q16, w_f32, cache_blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_spacing_gaps(const uint32_t *words, uint64_t n, uint32_t *gaps, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t blocks = (n + kGenBlock - 1) / kGenBlock;
+  k_spacing_gaps<<<(uint32_t)std::min<uint64_t>(blocks, 8192u), kGenBlock, 0, s>>>(words, n, gaps);
   return hipGetLastError();
 }
 

@@ -1671,6 +1671,13 @@ snn_status snn_build_network(const snn_params *prm, const snn_population *pops, 
   });
 }
 
+snn_status snn_spacing_gaps(const uint32_t *words, uint64_t n, uint32_t *gaps, void *stream) {
+  return guarded([&] {
+    if (n && (!words || !gaps)) fail(SNN_E_INVALID, "null argument");
+    check(snn::launch_spacing_gaps(words, n, gaps, (hipStream_t)stream), "spacing gaps launch");
+  });
+}
+
 snn_status snn_step(snn_network *net) {
   return guarded([&] {
     if (!net) fail(SNN_E_INVALID, "null network");

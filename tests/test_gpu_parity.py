@@ -52,9 +52,9 @@ def test_generated_synapses_match_oracle(name):
         assert np.array_equal(w, o.w_q16())
 
 
-@pytest.mark.parametrize("k", [5119, 5120, 6001, 12000])
+@pytest.mark.parametrize("k", [5102, 5103, 5104, 5120, 6001, 12000])
 def test_long_fixed_rows_match_oracle(k):
-    """Rows of k + 1 gaps around and past the generator's LDS gap cache (5,120 gaps per
+    """Rows of k + 1 gaps around and past the generator's LDS gap cache (5,104 gaps per
     row): the gaps beyond it are regenerated in the second pass."""
     spec = W.brunel_fixed_out(n=max(6400, k + 400), k=k, delay_steps=3, steps=10)
     print(f"[gen] fixed out-degree k={k}", flush=True)
@@ -65,6 +65,38 @@ def test_long_fixed_rows_match_oracle(k):
     assert np.array_equal(col, o.col())
     i = g.info()
     assert i["build_ms"] > 0 and i["gen_fill_ms"] > 0 and i["gen_rows_ms"] > 0 and i["index_ms"] >= 0
+
+
+def test_spacing_gaps_on_every_input():
+    """The fill's gap evaluation (a table estimate, the defined binary64 logarithm where
+    the estimate is near an integer) against the oracle's gaps (Fig. 2, step (b)) on all
+    2^24 distinct inputs; the word's low 8 bits, which the definition drops, vary."""
+    import ctypes as C
+    import torch
+    from paper_1912_07423_amd import _lib as L
+    j = np.arange(1 << 24, dtype=np.uint32)
+    words = (j << np.uint32(8)) | (j * np.uint32(2654435761) >> np.uint32(24))
+    S, _ = oracle.spacing_core((j.astype(np.float64) + 1.0) * 2.0 ** -24, spare=0)
+    want = np.diff(S).astype(np.uint32)
+    assert want.max() < (1 << 29) and want[-1] == 0
+    d_words = torch.from_numpy(words.view(np.int32)).cuda()
+    d_gaps = torch.full((1 << 24,), -1, dtype=torch.int32, device="cuda")
+    lib = L.load()
+    st = lib.snn_spacing_gaps(C.c_void_p(d_words.data_ptr()), 1 << 24, C.c_void_p(d_gaps.data_ptr()),
+                              C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == L.SNN_OK
+    got = d_gaps.cpu().numpy().view(np.uint32)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{bad.size} gaps differ, first at j = {bad[:5]}: {got[bad[:5]]} vs {want[bad[:5]]}"
+    # a ragged count, and n = 0 with NULL pointers
+    d_gaps.fill_(-1)
+    st = lib.snn_spacing_gaps(C.c_void_p(d_words.data_ptr()), 1001, C.c_void_p(d_gaps.data_ptr()),
+                              C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    got = d_gaps.cpu().numpy().view(np.uint32)
+    assert st == L.SNN_OK and np.array_equal(got[:1001], want[:1001]) and np.all(got[1001:] == 0xFFFFFFFF)
+    assert lib.snn_spacing_gaps(None, 0, None, None) == L.SNN_OK
+    assert lib.snn_spacing_gaps(None, 5, C.c_void_p(d_gaps.data_ptr()), None) == L.SNN_E_INVALID
 
 
 @pytest.mark.parametrize("name", list(_small_specs()))
