@@ -274,27 +274,37 @@ __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint
     const uint64_t incl = wave_scan_u64(lane_total);
     const uint64_t s0 = carry + (incl - lane_total);
     const double s0_d = (double)s0;
-    uint32_t in_lane = 0;
+    // q_k = floor(S_{k+1} spare / total + 1/2) <= spare < 2^32 from binary64: the
+    // roundings below (s0, s0 + in_lane, total, the fma, 1 / total, the product) add up
+    // to a relative error under 7 2^-53 < 2^-50, i.e. under 2^-18 absolute, so the floor
+    // of the estimate is exact unless it lies that close to an integer; then the exact
+    // integer quotient.  The four estimates come first and the rare exact quotients
+    // after them, so that the four chains overlap.  (total = 0 only if every gap is 0;
+    // then q_k = 0.)
+    uint32_t in_lane[4], qk[4] = {0, 0, 0, 0};
+    bool sure[4] = {true, true, true, true};
+    in_lane[0] = gap[0];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) in_lane[q] = in_lane[q - 1] + gap[q];  // S_{k+1} = s0 + in_lane
+    if (total != 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double est = fma(s0_d + (double)in_lane[q], spare_d, half_total_d) * inv_total;
+        const double fl = floor(est), fr = est - fl;
+        qk[q] = (uint32_t)fl;
+        sure[q] = fr >= 0x1p-18 && fr <= 1.0 - 0x1p-18;
+      }
+      if (!(sure[0] && sure[1] && sure[2] && sure[3])) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (!sure[q])
+            qk[q] = (uint32_t)div_floor_u64(2u * (s0 + in_lane[q]) * pj.spare + total, two_total, inv_two_total);
+      }
+    }
     int32_t tgt[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const uint32_t k = 4u * b + q;
-      in_lane += gap[q];  // S_{k+1} = s0 + in_lane
-      uint32_t x = k;
-      if (total != 0) {
-        // q = floor(S_{k+1} spare / total + 1/2) <= spare < 2^32 from binary64: the
-        // roundings below (s0, s0 + in_lane, total, the fma, 1 / total, the product) add
-        // up to a relative error under 7 2^-53 < 2^-50, i.e. under 2^-18 absolute, so
-        // the floor of the estimate is exact unless it lies that close to an integer;
-        // then the exact integer quotient.
-        const double est = fma(s0_d + (double)in_lane, spare_d, half_total_d) * inv_total;
-        const double fl = floor(est), fr = est - fl;
-        const uint32_t q = (fr >= 0x1p-18 && fr <= 1.0 - 0x1p-18)
-                               ? (uint32_t)fl
-                               : (uint32_t)div_floor_u64(2u * (s0 + in_lane) * pj.spare + total, two_total,
-                                                         inv_two_total);
-        x = q + k;
-      }
+      uint32_t x = qk[q] + 4u * b + q;
       if (x >= self_local) x += 1;
       tgt[q] = (int32_t)(pj.off + x);
     }
