@@ -228,38 +228,43 @@ constexpr uint32_t kGapCacheMax =
     (uint32_t)((160u * 1024u / 2u - kGapTable * sizeof(double2)) / (kGenWavesPerBlock * sizeof(uint4))) * 4u;
 static_assert(kGapCacheMax == 5104, "gap cache of 1,276 blocks of four per wavefront");
 
-__device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint64_t pos,
-                           int32_t *col, int32_t *w_q16, float *w_f32, uint4 *cache,
-                           uint32_t cache_blocks, const double2 *tbl) {
-  const uint32_t k_out = pj.k;
-  if (k_out == 0) return;
+// Pass 1 over the blocks [lo, hi) of a fixed out-degree row: the wavefront's total of
+// their gaps; the first cache_blocks of them go to `cache` (indexed from lo).  Each block
+// of four gaps is written and read back by the same lane, so no barrier.
+__device__ uint64_t fixed_pass1(const GenArgs &g, const GenProj &pj, uint32_t i, uint32_t lo,
+                                uint32_t hi, uint4 *cache, uint32_t cache_blocks, const double2 *tbl) {
   const uint32_t stream_word2 = 1u + pj.first_pop;
-  const uint32_t n_blocks = (k_out + 1 + 3) / 4;  // gaps 0..k_out
-  const uint32_t n_iter = (n_blocks + kWave - 1) / kWave;
-  // pass 1: total of the k_out + 1 gaps; the first kGapCache of them go to LDS.  Each
-  // block of four gaps is written and read back by the same lane, so no barrier.
   uint64_t part = 0;
-  for (uint32_t b = lane_id(); b < n_blocks; b += kWave) {
+  for (uint32_t b = lo + lane_id(); b < hi; b += kWave) {
     const Words4 r = philox(i, b, stream_word2, kStreamConn, g.key0, g.key1);
     uint32_t gq[4];
-    gaps4(r, 4u * b, k_out, tbl, gq);
+    gaps4(r, 4u * b, pj.k, tbl, gq);
     part += (uint64_t)(gq[0] + gq[1] + gq[2] + gq[3]);
-    if (b < cache_blocks) cache[b] = make_uint4(gq[0], gq[1], gq[2], gq[3]);
+    if (b - lo < cache_blocks) cache[b - lo] = make_uint4(gq[0], gq[1], gq[2], gq[3]);
   }
-  const uint64_t total = wave_sum(part);
+  return wave_sum(part);
+}
+
+// Pass 2 over the blocks [lo, hi): running sum S_{k+1} from `carry` (the gaps of the
+// blocks before lo), round-half-up of S_{k+1} * spare / total, + k; writes the targets.
+__device__ void fixed_pass2(const GenArgs &g, const GenProj &pj, uint32_t i, uint64_t pos,
+                            uint32_t lo, uint32_t hi, uint64_t carry, uint64_t total, int32_t *col,
+                            int32_t *w_q16, float *w_f32, const uint4 *cache, uint32_t cache_blocks,
+                            const double2 *tbl) {
+  const uint32_t k_out = pj.k;
+  const uint32_t stream_word2 = 1u + pj.first_pop;
+  const uint32_t n_iter = (hi - lo + kWave - 1) / kWave;
   const uint64_t two_total = 2u * total;
   const double inv_two_total = total != 0 ? 1.0 / (double)two_total : 0.0;
   const double inv_total = total != 0 ? 1.0 / (double)total : 0.0;
   const double half_total_d = 0.5 * (double)total, spare_d = (double)pj.spare;
   const uint32_t self_local = pj.self_in ? (i - pj.off) : 0xFFFFFFFFu;
-  // pass 2: running sum S_{k+1}, round-half-up of S_{k+1} * spare / total, + k
-  uint64_t carry = 0;
   for (uint32_t it = 0; it < n_iter; ++it) {
-    const uint32_t b = it * kWave + lane_id();
+    const uint32_t b = lo + it * kWave + lane_id();
     uint32_t gap[4] = {0, 0, 0, 0};
-    if (b < n_blocks) {
-      if (b < cache_blocks) {
-        const uint4 c = cache[b];
+    if (b < hi) {
+      if (b - lo < cache_blocks) {
+        const uint4 c = cache[b - lo];
         gap[0] = c.x;
         gap[1] = c.y;
         gap[2] = c.z;
@@ -311,7 +316,7 @@ __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint
     // a whole block of four targets goes out as one 16-byte store when the row starts
     // on a 16-byte boundary; the row's last, partial block element by element
     const uint64_t p0 = pos + 4u * b;
-    if (b < n_blocks) {
+    if (b < hi) {
       if ((pos & 3u) == 0 && 4u * b + 3u < k_out) {
         *reinterpret_cast<int4 *>(col + p0) = make_int4(tgt[0], tgt[1], tgt[2], tgt[3]);
         if (w_q16) *reinterpret_cast<int4 *>(w_q16 + p0) = make_int4(pj.w_q16, pj.w_q16, pj.w_q16, pj.w_q16);
@@ -329,6 +334,17 @@ __device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint
     }
     carry += last_lane_u64(incl);
   }
+}
+
+
+// One fixed out-degree row by one wavefront.
+__device__ void fixed_fill(const GenArgs &g, const GenProj &pj, uint32_t i, uint64_t pos,
+                           int32_t *col, int32_t *w_q16, float *w_f32, uint4 *cache,
+                           uint32_t cache_blocks, const double2 *tbl) {
+  if (pj.k == 0) return;
+  const uint32_t n_blocks = (pj.k + 1 + 3) / 4;  // gaps 0..k
+  const uint64_t total = fixed_pass1(g, pj, i, 0, n_blocks, cache, cache_blocks, tbl);
+  fixed_pass2(g, pj, i, pos, 0, n_blocks, 0, total, col, w_q16, w_f32, cache, cache_blocks, tbl);
 }
 
 __global__ __launch_bounds__(kGenBlock) void k_fill_rows(GenArgs g, const uint64_t *row_ptr,
@@ -351,6 +367,58 @@ __global__ __launch_bounds__(kGenBlock) void k_fill_rows(GenArgs g, const uint64
         fixed_fill(g, pj, i, pos, col, w_q16, w_f32, cache, cache_blocks, tbl);
         pos += pj.k;
       }
+    }
+  }
+}
+
+// Networks whose projections are all fixed out-degree, with rows of at least
+// kTeamMinK targets: one workgroup per row, each wavefront taking a contiguous quarter of
+// the row's blocks.  Pass 1 gives each wavefront the total of its quarter; one barrier
+// combines the four into the row's total and each wavefront's carry-in; pass 2 then runs
+// on the quarters independently.  A wavefront caches only its quarter's gaps, so four
+// times as many workgroups fit a CU (at K = 5,000: 20 KiB instead of 80 KiB each), and
+// rows of up to 4 x kTeamCacheMax blocks are generated once.  Shorter rows stay one per
+// wavefront: there the per-row latency and set-up, paid four times, outweigh the
+// occupancy (rows of 1,000 and 2,000 targets filled 20-35% slower by workgroups).
+constexpr uint32_t kTeamMinK = 4096;
+constexpr uint32_t kTeamCacheMax =
+    (uint32_t)((160u * 1024u / 2u - kGapTable * sizeof(double2) - 2u * kGenWavesPerBlock * sizeof(uint64_t)) /
+               (kGenWavesPerBlock * sizeof(uint4)));
+static_assert(kTeamCacheMax == 1275, "1,275 blocks of four gaps per wavefront");
+
+__global__ __launch_bounds__(kGenBlock) void k_fill_fixed_rows(GenArgs g, const uint64_t *row_ptr,
+                                                               int32_t *col, int32_t *w_q16,
+                                                               float *w_f32, uint32_t cache_blocks) {
+  extern __shared__ uint4 gap_cache[];  // [kGenWavesPerBlock][cache_blocks]
+  __shared__ double2 tbl[kGapTable];
+  __shared__ uint64_t sums[2][kGenWavesPerBlock];  // alternate per row segment
+  load_gap_table(tbl);
+  const uint32_t w = threadIdx.x / kWave;
+  uint4 *cache = gap_cache + w * cache_blocks;
+  uint32_t seg = 0;
+  for (uint32_t i = blockIdx.x; i < g.n; i += gridDim.x) {
+    const uint32_t a = population_of(g, i);
+    uint64_t pos = row_ptr[i];
+    for (uint32_t q = g.pop_proj[a]; q < g.pop_proj[a + 1]; ++q) {
+      const GenProj pj = g.proj[q];
+      if (pj.k == 0) continue;
+      const uint32_t n_blocks = (pj.k + 1 + 3) / 4;  // gaps 0..k
+      const uint32_t per = (n_blocks + kGenWavesPerBlock - 1) / kGenWavesPerBlock;
+      const uint32_t lo = min(w * per, n_blocks), hi = min(lo + per, n_blocks);
+      const uint64_t mine = fixed_pass1(g, pj, i, lo, hi, cache, cache_blocks, tbl);
+      // The slot written here was last read before the previous segment's barrier.
+      uint64_t *s = sums[seg & 1u];
+      if (lane_id() == 0) s[w] = mine;
+      __syncthreads();
+      uint64_t total = 0, before = 0;
+#pragma unroll
+      for (uint32_t v = 0; v < (uint32_t)kGenWavesPerBlock; ++v) {
+        total += s[v];
+        if (v < w) before += s[v];
+      }
+      fixed_pass2(g, pj, i, pos, lo, hi, before, total, col, w_q16, w_f32, cache, cache_blocks, tbl);
+      pos += pj.k;
+      ++seg;
     }
   }
 }
@@ -547,22 +615,29 @@ hipError_t launch_row_lengths(const GenArgs &g, uint32_t *len, uint32_t *plast_r
   return hipGetLastError();
 }
 
-hipError_t launch_fill_rows(const GenArgs &g, uint32_t max_fixed_k, const uint64_t *row_ptr,
+hipError_t launch_fill_rows(const GenArgs &g, uint32_t max_fixed_k, bool all_fixed, const uint64_t *row_ptr,
                             int32_t *col, int32_t *w_q16, float *w_f32, hipStream_t s) {
-  const uint32_t gaps = max_fixed_k ? std::min(max_fixed_k + 1, kGapCacheMax) : 0u;
-  uint32_t cache_blocks = (gaps + 3) / 4;
   int dev = 0, lds_max = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
+  const bool team = all_fixed && max_fixed_k >= kTeamMinK;
+  const uint32_t blocks = max_fixed_k ? (max_fixed_k + 1 + 3) / 4 : 0u;  // of the longest row
+  uint32_t cache_blocks = team ? std::min((blocks + kGenWavesPerBlock - 1) / kGenWavesPerBlock, kTeamCacheMax)
+                               : std::min(blocks, kGapCacheMax / 4);
   cache_blocks = std::min<uint32_t>(cache_blocks, (uint32_t)lds_max / (kGenWavesPerBlock * sizeof(uint4)));
   const size_t lds = (size_t)kGenWavesPerBlock * cache_blocks * sizeof(uint4);
+  const void *fn = team ? reinterpret_cast<const void *>(&k_fill_fixed_rows)
+                        : reinterpret_cast<const void *>(&k_fill_rows);
   if (lds > 65536) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fill_rows),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  k_fill_rows<<<row_grid(g.n), kGenBlock, lds, s>>>(g, row_ptr, col, w_q16, w_f32, cache_blocks);
+  if (team)
+    k_fill_fixed_rows<<<std::min(g.n ? g.n : 1u, 8192u), kGenBlock, lds, s>>>(g, row_ptr, col, w_q16, w_f32,
+                                                                              cache_blocks);
+  else
+    k_fill_rows<<<row_grid(g.n), kGenBlock, lds, s>>>(g, row_ptr, col, w_q16, w_f32, cache_blocks);
   return hipGetLastError();
 }
 

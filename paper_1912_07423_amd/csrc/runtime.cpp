@@ -502,10 +502,13 @@ void build(snn_network *net) {
     check(hipMemsetAsync(net->w_q16 + net->nnz, 0, pad_bytes, s), "clear w padding");
   }
   uint32_t max_fixed_k = 0;
-  for (const snn::GenProj &q : gp)
+  bool all_fixed = true;
+  for (const snn::GenProj &q : gp) {
     if (q.kind == SNN_PROJ_FIXED_OUT) max_fixed_k = std::max(max_fixed_k, q.k);
+    else all_fixed = false;
+  }
   check(hipEventRecord(ev[2], s), "hipEventRecord");
-  check(snn::launch_fill_rows(g, max_fixed_k, net->row_ptr, net->col, net->w_q16, net->w_f32, s),
+  check(snn::launch_fill_rows(g, max_fixed_k, all_fixed, net->row_ptr, net->col, net->w_q16, net->w_f32, s),
         "fill rows");
   check(hipEventRecord(ev[3], s), "hipEventRecord");
   check(hipEventRecord(ev[4], s), "hipEventRecord");

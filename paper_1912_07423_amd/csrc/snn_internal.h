@@ -268,7 +268,9 @@ struct StageArgs {
 hipError_t launch_stage_window(const StageArgs &a, hipStream_t s);
 hipError_t launch_row_lengths(const GenArgs &g, uint32_t *len, uint32_t *plast_rel,
                               uint32_t *plast_len, hipStream_t s);
-hipError_t launch_fill_rows(const GenArgs &g, uint32_t max_fixed_k, const uint64_t *row_ptr,
+// all_fixed: every projection is fixed out-degree (no ER rows), which allows one
+// workgroup per row for long rows.
+hipError_t launch_fill_rows(const GenArgs &g, uint32_t max_fixed_k, bool all_fixed, const uint64_t *row_ptr,
                             int32_t *col, int32_t *w_q16, float *w_f32, hipStream_t s);
 hipError_t launch_spacing_gaps(const uint32_t *words, uint64_t n, uint32_t *gaps, hipStream_t s);
 hipError_t launch_scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint32_t n,

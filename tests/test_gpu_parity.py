@@ -52,10 +52,11 @@ def test_generated_synapses_match_oracle(name):
         assert np.array_equal(w, o.w_q16())
 
 
-@pytest.mark.parametrize("k", [5102, 5103, 5104, 5120, 6001, 12000])
+@pytest.mark.parametrize("k", [4095, 4096, 5102, 5103, 5104, 5120, 6001, 12000])
 def test_long_fixed_rows_match_oracle(k):
-    """Rows of k + 1 gaps around and past the generator's LDS gap cache (5,104 gaps per
-    row): the gaps beyond it are regenerated in the second pass."""
+    """Networks of fixed out-degree projections only, with rows from just below the
+    length where a workgroup shares each row (4,096 targets) to rows past a wavefront's
+    own gap cache (5,104 gaps): every row byte-identical."""
     spec = W.brunel_fixed_out(n=max(6400, k + 400), k=k, delay_steps=3, steps=10)
     print(f"[gen] fixed out-degree k={k}", flush=True)
     g = _net(spec, raster_steps=16)
@@ -65,6 +66,22 @@ def test_long_fixed_rows_match_oracle(k):
     assert np.array_equal(col, o.col())
     i = g.info()
     assert i["build_ms"] > 0 and i["gen_fill_ms"] > 0 and i["gen_rows_ms"] > 0 and i["index_ms"] >= 0
+
+
+@pytest.mark.parametrize("k", [4500, 5300])
+def test_fixed_rows_beside_er_projections(k):
+    """A network with an ER projection besides its fixed out-degree ones keeps one
+    wavefront per row; at k = 5,300 its rows also pass the wavefront's gap cache."""
+    spec = W.brunel_fixed_out(n=8000, k=k, delay_steps=3, steps=10)
+    spec["projs"][1]["to_span"] = 1  # inhibitory rows: k fixed targets among the excitatory
+    spec["projs"].append({"from": 1, "to": 1, "to_span": 1, "kind": "er", "p": 0.05, "k": 0,
+                          "w_mV": -0.2, "plastic": 0})
+    print(f"[gen] fixed k={k} with an ER projection", flush=True)
+    g = _net(spec, raster_steps=16)
+    o = oracle.OracleNet(spec)
+    rp, col, _ = g.synapses()
+    assert np.array_equal(rp, o.row_ptr())
+    assert np.array_equal(col, o.col())
 
 
 def test_spacing_gaps_on_every_input():
@@ -378,11 +395,12 @@ def test_two_single_neuron_populations():
     assert inf["nnz"] == 2
 
 
-def test_fixed_out_degree_to_every_other_neuron():
+@pytest.mark.parametrize("n", [400, 4500])
+def test_fixed_out_degree_to_every_other_neuron(n):
     """K = n - 1 over all n neurons: no spare slot, every row is every other neuron
-    (the spacing generator's degenerate case)."""
-    spec = W.brunel_fixed_out(n=400, k=399, delay_steps=3, steps=150)
-    print("[edge] K = n - 1", flush=True)
+    (the spacing generator's degenerate case); at n = 4,500 a workgroup shares each row."""
+    spec = W.brunel_fixed_out(n=n, k=n - 1, delay_steps=3, steps=150)
+    print(f"[edge] K = n - 1, n = {n}", flush=True)
     g = _net(spec)
     o = oracle.OracleNet(spec)
     rp, col, _ = g.synapses()
