@@ -540,8 +540,10 @@ __device__ __forceinline__ uint32_t tile_of(uint32_t t, uint32_t tile_size, doub
 //    sorted, so element e is that boundary for every p in (tile(e - 1), tile(e)]; the
 //    entries past the last element's tile get the row length.  Stored as uint16 when
 //    every row is shorter than 65,536 synapses.
-// The padding of col16 past nnz (up to `count`) is cleared by the first thread.
-constexpr int kIndexUnroll = 4;
+// The padding of col16 past nnz (up to `count`) is cleared by the first thread.  A lane
+// takes groups of four consecutive targets: one 16-byte load and one 8-byte col16 store
+// each where the row starts on a 16-byte boundary, element by element otherwise.
+constexpr int kIndexGroups = 2;  // groups of four per lane in flight
 __global__ __launch_bounds__(kGenBlock) void k_tile_index(const uint64_t *row_ptr, const int32_t *col,
                                                           uint32_t n, uint64_t nnz, uint64_t count,
                                                           uint32_t tiles, uint32_t tile_size, double inv,
@@ -558,27 +560,50 @@ __global__ __launch_bounds__(kGenBlock) void k_tile_index(const uint64_t *row_pt
   for (uint32_t i = wave; i < n; i += n_waves) {
     const uint64_t lo = row_ptr[i], hi = row_ptr[i + 1];
     const uint64_t out = (uint64_t)i * (tiles + 1);
-    int32_t carry = -1;  // tile of the element before this pass (-1 at the row's start)
-    for (uint64_t base = lo; base < hi; base += kWave * kIndexUnroll) {
-      int32_t t[kIndexUnroll];
-      bool in[kIndexUnroll];
+    const bool aligned = (lo & 3u) == 0;
+    int32_t carry = -1;  // tile of the element before this group (-1 at the row's start)
+    for (uint64_t base = lo; base < hi; base += (uint64_t)kWave * 4u * kIndexGroups) {
+      int32_t t[kIndexGroups][4];
 #pragma unroll
-      for (int j = 0; j < kIndexUnroll; ++j) {
-        const uint64_t e = base + (uint64_t)j * kWave + lane;
-        in[j] = e < hi;
-        t[j] = in[j] ? col[e] : 0;
+      for (int gi = 0; gi < kIndexGroups; ++gi) {
+        const uint64_t e0 = base + ((uint64_t)gi * kWave + lane) * 4u;
+        if (aligned && e0 + 4u <= hi) {
+          const int4 v = *reinterpret_cast<const int4 *>(col + e0);
+          t[gi][0] = v.x;
+          t[gi][1] = v.y;
+          t[gi][2] = v.z;
+          t[gi][3] = v.w;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) t[gi][j] = e0 + j < hi ? col[e0 + j] : 0;
+        }
       }
 #pragma unroll
-      for (int j = 0; j < kIndexUnroll; ++j) {
-        const uint64_t e = base + (uint64_t)j * kWave + lane;
-        const int32_t tl = in[j] ? (int32_t)tile_of((uint32_t)t[j], tile_size, inv) : (int32_t)tiles;
-        const int32_t up = __shfl_up(tl, 1, kWave);
-        const int32_t prev = lane == 0 ? carry : up;
-        if (in[j]) {
-          col16[e] = (uint16_t)(uint32_t)t[j];
-          for (int32_t p = prev + 1; p <= tl; ++p) put(out + (uint32_t)p, (uint32_t)(e - lo));
+      for (int gi = 0; gi < kIndexGroups; ++gi) {
+        const uint64_t e0 = base + ((uint64_t)gi * kWave + lane) * 4u;
+        int32_t tl[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          tl[j] = e0 + j < hi ? (int32_t)tile_of((uint32_t)t[gi][j], tile_size, inv) : (int32_t)tiles;
+        const int32_t up = __shfl_up(tl[3], 1, kWave);
+        int32_t prev = lane == 0 ? carry : up;
+        if (aligned && e0 + 4u <= hi) {
+          *reinterpret_cast<uint2 *>(col16 + e0) =
+              make_uint2(((uint32_t)t[gi][0] & 0xFFFFu) | ((uint32_t)t[gi][1] << 16),
+                         ((uint32_t)t[gi][2] & 0xFFFFu) | ((uint32_t)t[gi][3] << 16));
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (e0 + j < hi) col16[e0 + j] = (uint16_t)(uint32_t)t[gi][j];
         }
-        carry = __shfl(tl, kWave - 1, kWave);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (e0 + j < hi) {
+            for (int32_t p = prev + 1; p <= tl[j]; ++p) put(out + (uint32_t)p, (uint32_t)(e0 + j - lo));
+            prev = tl[j];
+          }
+        }
+        carry = __shfl(tl[3], kWave - 1, kWave);
       }
     }
     // entries past the last element's tile: the row length
