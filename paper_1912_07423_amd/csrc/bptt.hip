@@ -11,6 +11,7 @@
 //   lamu  [T][O][64]         readout adjoint
 //   lamv  [T][H][64]         membrane adjoint of every step (+ zeros [H][64] for step T)
 //   xbits [C][T], sbits [H][T]  64-bit batch masks of the binary input and hidden spikes
+//                            (each followed by 8 readable entries)
 // Weights stay in the caller's CSR order (rows = presynaptic neuron, sorted targets);
 // the forward current is a gather over the transposed index (per target, sources in
 // ascending order, input projection first), the adjoint's dL/ds a gather over the
@@ -158,12 +159,142 @@ __device__ __forceinline__ float ordered_gather_pipe(float acc, uint64_t e0, uin
   return acc;
 }
 
+// The same ordered sum where every presynaptic value is 0 or 1, given as 64-bit batch
+// masks: masks[src * stride + col] has bit b set where the value of batch element b is 1.
+// A term then adds w[e] where the lane's bit is set and leaves the sum as it is where it
+// is clear; that is the sum's own value, since w * 1 = w exactly and, for finite weights,
+// adding w * 0 = +-0 leaves a sum that starts from +0 unchanged.  Lanes load the sources,
+// weights and masks of 64 edges at once (two chunks, all requested before any term is
+// added), and each edge's mask and weight reach the wavefront by lane reads, the mask as
+// the lane condition: about two dependent memory round trips per 128 edges.
+__device__ __forceinline__ uint64_t lane_read64(uint64_t x, uint32_t u) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (int)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), (int)u);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ float ordered_mask_sum(float acc, uint64_t e0, uint64_t e1, const int32_t *src,
+                                                  const float *w, const uint64_t *masks, uint64_t stride,
+                                                  uint32_t col) {
+  const uint32_t l = lane_id();
+  for (uint64_t base = e0; base < e1; base += 2u * kWave) {
+    // loads from indices clamped to the last edge, issued unconditionally so that they
+    // are all in flight together; the masks of lanes past e1 are then cleared
+    const uint64_t last = e1 - 1;
+    const uint64_t ea = std::min<uint64_t>(base + l, last), eb = std::min<uint64_t>(base + kWave + l, last);
+    const uint32_t sa = (uint32_t)src[ea], sb = (uint32_t)src[eb];
+    const float wa = w[ea], wb = w[eb];
+    uint64_t ma = masks[(uint64_t)sa * stride + col];
+    uint64_t mb = masks[(uint64_t)sb * stride + col];
+    if (base + l >= e1) ma = 0u;
+    if (base + kWave + l >= e1) mb = 0u;
+    // edges past e1 carry an empty mask, so whole groups of eight run unconditionally
+    const uint32_t na = (uint32_t)std::min<uint64_t>(e1 - base, kWave);
+#pragma unroll 8
+    for (uint32_t u = 0; u < ((na + 7u) & ~7u); ++u) {
+      const float sum = acc + __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wa), (int)u));
+      acc = __builtin_amdgcn_inverse_ballot_w64(lane_read64(ma, u)) ? sum : acc;
+    }
+    if (e1 - base > kWave) {
+      const uint32_t nb = (uint32_t)std::min<uint64_t>(e1 - base - kWave, kWave);
+#pragma unroll 8
+      for (uint32_t u = 0; u < ((nb + 7u) & ~7u); ++u) {
+        const float sum = acc + __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wb), (int)u));
+        acc = __builtin_amdgcn_inverse_ballot_w64(lane_read64(mb, u)) ? sum : acc;
+      }
+    }
+  }
+  return acc;
+}
+
+// The ordered mask sums of kSteps consecutive columns at once (acc[u] for column
+// col0 + u), for kernels with parallelism to spare: the edges are wave-uniform, so their
+// sources, weights and each source's kSteps masks (contiguous in a row) arrive by scalar
+// loads, and a mask serves directly as the lane condition.  A term costs one add and one
+// select.  The masks of a group of edges and the sources of the next group are requested
+// together.  Rows must hold kSteps - 1 readable entries past the last column used.
+constexpr int kMaskSteps = 8;
+constexpr int kMaskGroup = 4;
+__device__ __forceinline__ void ordered_mask_sum_steps(float (&acc)[kMaskSteps], uint64_t e0, uint64_t e1,
+                                                       const int32_t *src, const float *w,
+                                                       const uint64_t *masks, uint64_t stride, uint64_t col0) {
+  uint64_t e = e0;
+  if (e + kMaskGroup <= e1) {
+    uint32_t c[kMaskGroup];
+    float wv[kMaskGroup];
+#pragma unroll
+    for (int g = 0; g < kMaskGroup; ++g) {
+      c[g] = (uint32_t)src[e + g];
+      wv[g] = w[e + g];
+    }
+    while (true) {
+      uint64_t mk[kMaskGroup][kMaskSteps];
+#pragma unroll
+      for (int g = 0; g < kMaskGroup; ++g) {
+        const uint64_t *row = masks + (uint64_t)c[g] * stride + col0;
+#pragma unroll
+        for (int u = 0; u < kMaskSteps; ++u) mk[g][u] = row[u];
+      }
+      float wc[kMaskGroup];
+#pragma unroll
+      for (int g = 0; g < kMaskGroup; ++g) wc[g] = wv[g];
+      const bool more = e + 2 * kMaskGroup <= e1;
+      if (more) {
+#pragma unroll
+        for (int g = 0; g < kMaskGroup; ++g) {
+          c[g] = (uint32_t)src[e + kMaskGroup + g];
+          wv[g] = w[e + kMaskGroup + g];
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < kMaskGroup; ++g)
+#pragma unroll
+        for (int u = 0; u < kMaskSteps; ++u) {
+          const float sum = acc[u] + wc[g];
+          acc[u] = __builtin_amdgcn_inverse_ballot_w64(mk[g][u]) ? sum : acc[u];
+        }
+      e += kMaskGroup;
+      if (!more) break;
+    }
+  }
+  for (; e < e1; ++e) {
+    const uint64_t *row = masks + (uint64_t)(uint32_t)src[e] * stride + col0;
+    const float wv = w[e];
+#pragma unroll
+    for (int u = 0; u < kMaskSteps; ++u) {
+      const float sum = acc[u] + wv;
+      acc[u] = __builtin_amdgcn_inverse_ballot_w64(row[u]) ? sum : acc[u];
+    }
+  }
+}
+
 // Input-projection current of every step: iin[t][j][b] = sum over j's input in-edges,
 // sources ascending, from 0 -- the first part of the hidden current in its defined order.
-// It does not depend on the recurrent state, so all steps run in parallel (a wavefront
-// per (t, j)).
+// It does not depend on the recurrent state, so all steps run in parallel.  Two kernels,
+// of which the flag that k_bits set for the inputs lets one work: with binary inputs
+// (flags[0] clear) k_input_current takes the terms from the input masks, a wavefront per
+// (block of kMaskSteps steps, j); otherwise k_input_current_values gathers the values,
+// a wavefront per (t, j).
 __global__ __launch_bounds__(256) void k_input_current(BpttArgs a) {
+  if (a.flags[0] != 0) return;
   // wave-uniform index (readfirstlane lets the edge lists be read with scalar loads)
+  const uint64_t w = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const uint32_t n_blocks = (a.T + kMaskSteps - 1) / kMaskSteps;
+  if (w >= (uint64_t)n_blocks * a.H) return;
+  const uint32_t t0 = (uint32_t)(w / a.H) * kMaskSteps, j = (uint32_t)(w % a.H);
+  const uint32_t nt = std::min<uint32_t>(kMaskSteps, a.T - t0);
+  const uint32_t b = lane_id();
+  float acc[kMaskSteps];
+#pragma unroll
+  for (int u = 0; u < kMaskSteps; ++u) acc[u] = 0.0f;
+  ordered_mask_sum_steps(acc, a.in_t_ptr[j], a.in_t_ptr[j + 1], a.in_t_src, a.w_in_t, a.xbits, a.T, t0);
+#pragma unroll
+  for (int u = 0; u < kMaskSteps; ++u)
+    if ((uint32_t)u < nt) a.iin[((size_t)(t0 + u) * a.H + j) * 64 + b] = acc[u];
+}
+
+__global__ __launch_bounds__(256) void k_input_current_values(BpttArgs a) {
+  if (a.flags[0] == 0) return;
   const uint64_t w = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   if (w >= (uint64_t)a.T * a.H) return;
   const uint32_t t = (uint32_t)(w / a.H), j = (uint32_t)(w % a.H);
@@ -175,21 +306,35 @@ __global__ __launch_bounds__(256) void k_input_current(BpttArgs a) {
 // One step t of the hidden layer: one wavefront per hidden neuron j, lane = batch.  The
 // current continues the input part with j's recurrent in-edges (sources ascending).
 // vprev/sprev are step t-1 (nullptr at t = 0).  Writes v_out[j][b] and, if s_out is
-// set, s_out[j][b].
+// set, s_out[j][b].  In spiking mode the spikes are 0 or 1: the recurrent terms come
+// from the masks of step t-1, and the step writes its own masks (sbits[j][t]).
 __global__ __launch_bounds__(256) void k_hidden_step(BpttArgs a, uint32_t t, const float *vprev,
                                                      const float *sprev, float *v_out, float *s_out) {
   const uint32_t j = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   if (j >= a.H) return;
   const uint32_t b = lane_id();
+  const bool binary = a.smooth == 0;
   float acc = a.iin[((size_t)t * a.H + j) * 64 + b];
-  if (sprev) acc = ordered_gather_pipe(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t, sprev, b);
+  if (sprev) {
+    if (binary)
+      acc = ordered_mask_sum(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t, a.sbits, a.T, t - 1);
+    else
+      acc = ordered_gather_pipe(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t, sprev, b);
+  }
   const float vp = vprev ? vprev[(size_t)j * 64 + b] : 0.0f;
   const float sp = sprev ? sprev[(size_t)j * 64 + b] : 0.0f;
   float v = a.beta * vp;
   v = v + acc;
   v = v - a.theta * sp;
   v_out[(size_t)j * 64 + b] = v;
-  if (s_out) s_out[(size_t)j * 64 + b] = spike_fn(v - a.theta, a.slope, a.smooth != 0);
+  if (s_out) {
+    const float sv = spike_fn(v - a.theta, a.slope, a.smooth != 0);
+    s_out[(size_t)j * 64 + b] = sv;
+    if (binary) {
+      const uint64_t m = __ballot(b < a.B && sv != 0.0f);
+      if (b == 0) a.sbits[(size_t)j * a.T + t] = m;
+    }
+  }
 }
 
 // Backward recomputation of one checkpoint segment [t0, t0 + len).  The spikes of every
@@ -203,9 +348,14 @@ __global__ __launch_bounds__(256) void k_seg_current(BpttArgs a, uint32_t t0, ui
   const uint32_t k = (uint32_t)(w / a.H), j = (uint32_t)(w % a.H), t = t0 + k;
   const uint32_t b = lane_id();
   float acc = a.iin[((size_t)t * a.H + j) * 64 + b];
-  if (t > 0)
-    acc = ordered_gather_sum(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t,
-                             a.s + (size_t)(t - 1) * a.H * 64, b);
+  if (t > 0) {
+    if (a.smooth == 0)  // spiking mode: the forward pass wrote the spike masks
+      acc = ordered_mask_sum(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t, a.sbits, a.T,
+                             t - 1);
+    else
+      acc = ordered_gather_sum(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t,
+                               a.s + (size_t)(t - 1) * a.H * 64, b);
+  }
   cur[w * 64 + b] = acc;
 }
 
@@ -526,7 +676,14 @@ hipError_t bptt_forward_prologue(const BpttArgs &a, const float *x, hipStream_t 
 
 // g: the plan's arguments with w_out = w_out_c
 hipError_t bptt_forward_body(const BpttArgs &g, hipStream_t s) {
-  hipLaunchKernelGGL(k_input_current, dim3(blocks_for((uint64_t)g.T * g.H, 4)), dim3(256), 0, s, g);
+  // batch masks of the inputs (flags[0] set if some value is neither 0 nor 1); flags[1]
+  // is set only by the backward pass of a smooth-mode plan
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, reinterpret_cast<float *>(g.flags), (uint64_t)2, 0.0f);
+  hipLaunchKernelGGL(k_bits, dim3(blocks_for((uint64_t)g.T * g.C, 4)), dim3(256), 0, s, g.xt, g.C, g.T, g.B,
+                     g.xbits, g.flags);
+  hipLaunchKernelGGL(k_input_current, dim3(blocks_for((uint64_t)((g.T + kMaskSteps - 1) / kMaskSteps) * g.H, 4)),
+                     dim3(256), 0, s, g);
+  hipLaunchKernelGGL(k_input_current_values, dim3(blocks_for((uint64_t)g.T * g.H, 4)), dim3(256), 0, s, g);
   const dim3 grid(blocks_for(g.H, 4));
   float *vprev = nullptr;
   for (uint32_t t = 0; t < g.T; ++t) {
@@ -563,12 +720,12 @@ hipError_t bptt_backward_prologue(const BpttArgs &a, const float *g_loss, hipStr
 hipError_t bptt_backward_body(const BpttArgs &g, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(blocks_for((uint64_t)g.H * 64, 256)), dim3(256), 0, s, g.lam_carry,
                      (uint64_t)g.H * 64, 0.0f);
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, reinterpret_cast<float *>(g.flags), (uint64_t)2, 0.0f);
-  // batch masks of the binary trajectories, for the sparse-weight gradients
-  hipLaunchKernelGGL(k_bits, dim3(blocks_for((uint64_t)g.T * g.C, 4)), dim3(256), 0, s, g.xt, g.C, g.T, g.B,
-                     g.xbits, g.flags);
-  hipLaunchKernelGGL(k_bits, dim3(blocks_for((uint64_t)g.T * g.H, 4)), dim3(256), 0, s, g.s, g.H, g.T, g.B,
-                     g.sbits, g.flags + 1);
+  // batch masks of the hidden trajectory for the sparse-weight gradients: in spiking
+  // mode the forward pass wrote them (and flags[1] stayed clear); in smooth mode they are
+  // taken here, and flag that the values are not binary
+  if (g.smooth)
+    hipLaunchKernelGGL(k_bits, dim3(blocks_for((uint64_t)g.T * g.H, 4)), dim3(256), 0, s, g.s, g.H, g.T, g.B,
+                       g.sbits, g.flags + 1);
   // the readout part of every step's spike adjoint, into lamv (each adjoint step reads
   // its own entries, then overwrites them with lamV_t)
   hipLaunchKernelGGL(k_readout_adjoint, dim3(blocks_for((uint64_t)g.T * g.H, 4)), dim3(256), 0, s, g, g.lamv);

@@ -109,6 +109,16 @@ def test_smooth_mode_matches_oracle():
     _compare(_small(seed=6), 10, smooth=True)
 
 
+def test_inputs_other_than_0_and_1():
+    """Inputs that are not all 0 or 1 (some spikes scaled by 0.5 or 3) take the value
+    gathers instead of the batch masks, with the oracle's results."""
+    d = _small(seed=10)
+    rng = np.random.default_rng(10)
+    d["x"] = (d["x"] * rng.choice(np.array([0.5, 1.0, 3.0], np.float32), size=d["x"].shape)).astype(np.float32)
+    assert np.any((d["x"] != 0) & (d["x"] != 1))
+    _compare(d, 10)
+
+
 def test_batch_below_one_wavefront_and_single_step():
     _compare(_small(seed=7, B=3, T=1), 4)
     _compare(_small(seed=8, B=64, T=33, H=70), 32)
