@@ -11,7 +11,7 @@
 //   lamu  [T][O][64]         readout adjoint
 //   lamv  [T][H][64]         membrane adjoint of every step (+ zeros [H][64] for step T)
 //   xbits [C][T], sbits [H][T]  64-bit batch masks of the binary input and hidden spikes
-//                            (each followed by 8 readable entries)
+//                            (8 readable entries after each, and before sbits)
 // Weights stay in the caller's CSR order (rows = presynaptic neuron, sorted targets);
 // the forward current is a gather over the transposed index (per target, sources in
 // ascending order, input projection first), the adjoint's dL/ds a gather over the
@@ -217,7 +217,7 @@ constexpr int kMaskSteps = 8;
 constexpr int kMaskGroup = 4;
 __device__ __forceinline__ void ordered_mask_sum_steps(float (&acc)[kMaskSteps], uint64_t e0, uint64_t e1,
                                                        const int32_t *src, const float *w,
-                                                       const uint64_t *masks, uint64_t stride, uint64_t col0) {
+                                                       const uint64_t *masks, uint64_t stride, int64_t col0) {
   uint64_t e = e0;
   if (e + kMaskGroup <= e1) {
     uint32_t c[kMaskGroup];
@@ -231,7 +231,7 @@ __device__ __forceinline__ void ordered_mask_sum_steps(float (&acc)[kMaskSteps],
       uint64_t mk[kMaskGroup][kMaskSteps];
 #pragma unroll
       for (int g = 0; g < kMaskGroup; ++g) {
-        const uint64_t *row = masks + (uint64_t)c[g] * stride + col0;
+        const uint64_t *row = masks + (int64_t)((uint64_t)c[g] * stride) + col0;
 #pragma unroll
         for (int u = 0; u < kMaskSteps; ++u) mk[g][u] = row[u];
       }
@@ -258,7 +258,7 @@ __device__ __forceinline__ void ordered_mask_sum_steps(float (&acc)[kMaskSteps],
     }
   }
   for (; e < e1; ++e) {
-    const uint64_t *row = masks + (uint64_t)(uint32_t)src[e] * stride + col0;
+    const uint64_t *row = masks + (int64_t)((uint64_t)(uint32_t)src[e] * stride) + col0;
     const float wv = w[e];
 #pragma unroll
     for (int u = 0; u < kMaskSteps; ++u) {
@@ -338,24 +338,43 @@ __global__ __launch_bounds__(256) void k_hidden_step(BpttArgs a, uint32_t t, con
 }
 
 // Backward recomputation of one checkpoint segment [t0, t0 + len).  The spikes of every
-// step are stored, so the currents of all the segment's steps are independent: this
-// kernel computes them in parallel (a wavefront per (k, j)), each exactly as
-// k_hidden_step does (input part, then the recurrent in-edges over s_{t-1} in ascending
-// source order), into cur[k][j][b].
+// step are stored, so the currents of all the segment's steps are independent: these
+// kernels compute them in parallel, each exactly as k_hidden_step does (input part, then
+// the recurrent in-edges over s_{t-1} in ascending source order), into cur[k][j][b].  In
+// spiking mode k_seg_current takes the terms from the spike masks the forward pass
+// wrote, a wavefront per (block of kMaskSteps steps, j); in smooth mode
+// k_seg_current_values gathers the values, a wavefront per (k, j).
 __global__ __launch_bounds__(256) void k_seg_current(BpttArgs a, uint32_t t0, uint32_t len, float *cur) {
+  const uint64_t w = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const uint32_t n_blocks = (len + kMaskSteps - 1) / kMaskSteps;
+  if (w >= (uint64_t)n_blocks * a.H) return;
+  const uint32_t k0 = (uint32_t)(w / a.H) * kMaskSteps, j = (uint32_t)(w % a.H);
+  const uint32_t nt = std::min<uint32_t>(kMaskSteps, len - k0);
+  const uint32_t b = lane_id();
+  float acc[kMaskSteps];
+#pragma unroll
+  for (int u = 0; u < kMaskSteps; ++u)
+    acc[u] = (uint32_t)u < nt ? a.iin[((size_t)(t0 + k0 + u) * a.H + j) * 64 + b] : 0.0f;
+  const float first = acc[0];
+  // column t - 1 of step t; at t = 0 the masks read (entries before the array's start
+  // for j = 0) are not used: that step has no recurrent term
+  ordered_mask_sum_steps(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t, a.sbits, a.T,
+                         (int64_t)(t0 + k0) - 1);
+  if (t0 + k0 == 0) acc[0] = first;
+#pragma unroll
+  for (int u = 0; u < kMaskSteps; ++u)
+    if ((uint32_t)u < nt) cur[((size_t)(k0 + u) * a.H + j) * 64 + b] = acc[u];
+}
+
+__global__ __launch_bounds__(256) void k_seg_current_values(BpttArgs a, uint32_t t0, uint32_t len, float *cur) {
   const uint64_t w = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   if (w >= (uint64_t)len * a.H) return;
   const uint32_t k = (uint32_t)(w / a.H), j = (uint32_t)(w % a.H), t = t0 + k;
   const uint32_t b = lane_id();
   float acc = a.iin[((size_t)t * a.H + j) * 64 + b];
-  if (t > 0) {
-    if (a.smooth == 0)  // spiking mode: the forward pass wrote the spike masks
-      acc = ordered_mask_sum(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t, a.sbits, a.T,
-                             t - 1);
-    else
-      acc = ordered_gather_sum(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t,
-                               a.s + (size_t)(t - 1) * a.H * 64, b);
-  }
+  if (t > 0)
+    acc = ordered_gather_sum(acc, a.rec_t_ptr[j], a.rec_t_ptr[j + 1], a.rec_t_src, a.w_rec_t,
+                             a.s + (size_t)(t - 1) * a.H * 64, b);
   cur[w * 64 + b] = acc;
 }
 
@@ -736,8 +755,12 @@ hipError_t bptt_backward_body(const BpttArgs &g, hipStream_t s) {
     // recompute the segment's membranes from the checkpoint before it and the stored
     // spikes (the forward pass's operations): all its currents at once, then the scan
     const float *vprev = seg ? g.vck + (size_t)(seg - 1) * g.H * 64 : nullptr;
-    hipLaunchKernelGGL(k_seg_current, dim3(blocks_for((uint64_t)len * g.H, 4)), dim3(256), 0, s, g, t0, len,
-                       g.vseg);
+    if (g.smooth)
+      hipLaunchKernelGGL(k_seg_current_values, dim3(blocks_for((uint64_t)len * g.H, 4)), dim3(256), 0, s, g, t0,
+                         len, g.vseg);
+    else
+      hipLaunchKernelGGL(k_seg_current, dim3(blocks_for((uint64_t)((len + kMaskSteps - 1) / kMaskSteps) * g.H, 4)),
+                         dim3(256), 0, s, g, t0, len, g.vseg);
     hipLaunchKernelGGL(k_seg_scan, dim3(blocks_for((uint64_t)g.H * 64, 256)), dim3(256), 0, s, g, t0, len, vprev,
                        g.vseg);
     for (int32_t k = (int32_t)len - 1; k >= 0; --k) {

@@ -1580,9 +1580,11 @@ void build_bptt(snn_bptt *p, const uint64_t *in_ptr, const int32_t *in_col, cons
   a.rec_ptr = upload(pool, std::vector<uint64_t>(rec_ptr, rec_ptr + d.n_hidden + 1));
   a.rec_col = upload(pool, std::vector<int32_t>(rec_col, rec_col + nnz_rec));
   const size_t HB = (size_t)a.H * 64, n_seg = (a.T + a.K - 1) / a.K;
-  // 8 entries past the end: the input currents read 8 steps of masks per load
+  // 8 readable entries past the end, and for the spike masks 8 before the start: the
+  // forward's input currents and the backward's segment currents read 8 steps of masks
+  // per load, the latter from step t - 1 (whose values at t = 0 are not used)
   a.xbits = dev_array<uint64_t>(pool, (size_t)a.C * a.T + 8);
-  a.sbits = dev_array<uint64_t>(pool, (size_t)a.H * a.T + 8);
+  a.sbits = dev_array<uint64_t>(pool, (size_t)a.H * a.T + 16) + 8;
   a.flags = dev_array<uint32_t>(pool, 2);
   a.w_in_t = dev_array<float>(pool, std::max<uint64_t>(1, nnz_in));
   a.w_rec_t = dev_array<float>(pool, std::max<uint64_t>(1, nnz_rec));
