@@ -39,15 +39,26 @@ __device__ __forceinline__ float surrogate(float z, float slope, bool smooth) {
   return smooth ? 0.5f * slope * g : g;
 }
 
-// x [B][T][C] -> xt [T][C][64]; lanes >= B hold zeros.
-__global__ void k_transpose_x(const float *x, float *xt, uint32_t B, uint32_t T, uint32_t C) {
+// x [B][T][C] -> xt [T][C][64]; lanes >= B hold zeros.  A wavefront is one (t, c), so it
+// also writes that input's batch mask xbits[c][t] (bit b: x = 1 ... or any non-zero
+// value) and sets *flag if some value is neither 0 nor 1 (k_bits' rule).
+__global__ __launch_bounds__(256) void k_transpose_x(const float *x, float *xt, uint64_t *xbits, uint32_t *flag,
+                                                     uint32_t B, uint32_t T, uint32_t C) {
   const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t total = (uint64_t)T * C * 64;
-  if (idx >= total) return;
+  if (idx >= total) return;  // whole wavefronts: total is a multiple of 64
   const uint32_t b = (uint32_t)(idx & 63u);
   const uint64_t tc = idx >> 6;
   const uint32_t c = (uint32_t)(tc % C), t = (uint32_t)(tc / C);
-  xt[idx] = b < B ? x[((uint64_t)b * T + t) * C + c] : 0.0f;
+  const float v = b < B ? x[((uint64_t)b * T + t) * C + c] : 0.0f;
+  xt[idx] = v;
+  const bool on = b < B && v != 0.0f;
+  const uint64_t m = __ballot(on);
+  const uint64_t bad = __ballot(on && v != 1.0f);
+  if (b == 0) {
+    xbits[(size_t)c * T + t] = m;
+    if (bad) atomicOr(flag, 1u);
+  }
 }
 
 // Transposed-order copy of a CSR weight vector: w_t[e] = w[edge[e]].
@@ -293,14 +304,18 @@ __global__ __launch_bounds__(256) void k_input_current(BpttArgs a) {
     if ((uint32_t)u < nt) a.iin[((size_t)(t0 + u) * a.H + j) * 64 + b] = acc[u];
 }
 
+// (a bounded grid that strides over the (t, j) pairs, so that the launch costs little
+// when the flag sends it home)
+constexpr uint32_t kValuesGrid = 2048;
 __global__ __launch_bounds__(256) void k_input_current_values(BpttArgs a) {
   if (a.flags[0] == 0) return;
-  const uint64_t w = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  if (w >= (uint64_t)a.T * a.H) return;
-  const uint32_t t = (uint32_t)(w / a.H), j = (uint32_t)(w % a.H);
   const uint32_t b = lane_id();
-  const float *xt = a.xt + (size_t)t * a.C * 64;
-  a.iin[w * 64 + b] = ordered_gather_sum(0.0f, a.in_t_ptr[j], a.in_t_ptr[j + 1], a.in_t_src, a.w_in_t, xt, b);
+  const uint64_t first = (uint64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  for (uint64_t w = first; w < (uint64_t)a.T * a.H; w += (uint64_t)gridDim.x * 4) {
+    const uint32_t t = (uint32_t)(w / a.H), j = (uint32_t)(w % a.H);
+    const float *xt = a.xt + (size_t)t * a.C * 64;
+    a.iin[w * 64 + b] = ordered_gather_sum(0.0f, a.in_t_ptr[j], a.in_t_ptr[j + 1], a.in_t_src, a.w_in_t, xt, b);
+  }
 }
 
 // One step t of the hidden layer: one wavefront per hidden neuron j, lane = batch.  The
@@ -687,22 +702,22 @@ static void gather_weights(const BpttArgs &a, hipStream_t s) {
 
 hipError_t bptt_forward_prologue(const BpttArgs &a, const float *x, hipStream_t s) {
   gather_weights(a, s);
+  // flags[0] is set below if some input is neither 0 nor 1; flags[1] only by the backward
+  // pass of a smooth-mode plan
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, reinterpret_cast<float *>(a.flags), (uint64_t)2, 0.0f);
   hipLaunchKernelGGL(k_transpose_x, dim3(blocks_for((uint64_t)a.T * a.C * 64, 256)), dim3(256), 0, s, x,
-                     a.xt, a.B, a.T, a.C);
+                     a.xt, a.xbits, a.flags, a.B, a.T, a.C);
   const hipError_t e = hipMemcpyAsync(a.w_out_c, a.w_out, (size_t)a.H * a.O * 4, hipMemcpyDeviceToDevice, s);
   return e != hipSuccess ? e : hipGetLastError();
 }
 
 // g: the plan's arguments with w_out = w_out_c
 hipError_t bptt_forward_body(const BpttArgs &g, hipStream_t s) {
-  // batch masks of the inputs (flags[0] set if some value is neither 0 nor 1); flags[1]
-  // is set only by the backward pass of a smooth-mode plan
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, reinterpret_cast<float *>(g.flags), (uint64_t)2, 0.0f);
-  hipLaunchKernelGGL(k_bits, dim3(blocks_for((uint64_t)g.T * g.C, 4)), dim3(256), 0, s, g.xt, g.C, g.T, g.B,
-                     g.xbits, g.flags);
+  // the inputs' batch masks and flags[0] come from the prologue's transpose
   hipLaunchKernelGGL(k_input_current, dim3(blocks_for((uint64_t)((g.T + kMaskSteps - 1) / kMaskSteps) * g.H, 4)),
                      dim3(256), 0, s, g);
-  hipLaunchKernelGGL(k_input_current_values, dim3(blocks_for((uint64_t)g.T * g.H, 4)), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(k_input_current_values, dim3(std::min<uint32_t>(blocks_for((uint64_t)g.T * g.H, 4), kValuesGrid)),
+                     dim3(256), 0, s, g);
   const dim3 grid(blocks_for(g.H, 4));
   float *vprev = nullptr;
   for (uint32_t t = 0; t < g.T; ++t) {
