@@ -352,6 +352,81 @@ __global__ __launch_bounds__(256) void k_hidden_step(BpttArgs a, uint32_t t, con
   }
 }
 
+// The hidden step in spiking mode with the ELL copy of the recurrent in-edges: the row of
+// neuron j sits at j * ell_w, so its sources and weights are requested at once, together
+// with iin, the state and the previous step's masks of all H neurons, which the workgroup
+// stages in LDS (one memory round trip in all, where the CSR form needs the row bounds,
+// then the edges, then the masks).  Each lane then reads its edge's mask from LDS, and the
+// terms are added in row order, one add and one select each, as in ordered_mask_sum.
+// kChunks = ell_w / 64.  The step writes its masks in both layouts.
+template <int kChunks>
+__global__ __launch_bounds__(256) void k_hidden_step_ell(BpttArgs a, uint32_t t, const float *vprev,
+                                                         const float *sprev, float *v_out, float *s_out) {
+  extern __shared__ uint64_t prev_masks[];  // [H]: step t - 1
+  const uint32_t j = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
+  // every wave reaches the barrier; one past the last neuron loads neuron 0's data and
+  // stores nothing
+  const bool live = j < a.H;
+  const uint32_t jl = live ? j : 0u;
+  const uint32_t b = lane_id();
+  const size_t jb = (size_t)jl * 64 + b;
+  float acc = a.iin[(size_t)t * a.H * 64 + jb];
+  const float vp = vprev ? vprev[jb] : 0.0f;
+  const float sp = sprev ? sprev[jb] : 0.0f;
+  int32_t src[kChunks];
+  float wt[kChunks];
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    const size_t x = (size_t)jl * a.ell_w + (uint32_t)c * kWave + b;
+    src[c] = a.ell_src[x];
+    wt[c] = a.ell_wt[x];
+  }
+  const uint32_t len = a.ell_len[jl];
+  if (sprev) {
+    // four loads per thread in flight, from indices clamped into the row
+    const uint64_t *row = a.sbits_t + (size_t)(t - 1) * a.H;
+    for (uint32_t base = 0; base < a.H; base += 4u * 256u) {
+      uint64_t v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = row[std::min<uint32_t>(base + (uint32_t)q * 256u + threadIdx.x, a.H - 1)];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t i = base + (uint32_t)q * 256u + threadIdx.x;
+        if (i < a.H) prev_masks[i] = v[q];
+      }
+    }
+  }
+  __syncthreads();
+  if (sprev && live) {
+    uint64_t m[kChunks];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) m[c] = (uint32_t)c * kWave + b < len ? prev_masks[src[c]] : 0u;
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+      const uint32_t n = len > (uint32_t)c * kWave ? std::min<uint32_t>(len - (uint32_t)c * kWave, kWave) : 0u;
+#pragma unroll 8
+      for (uint32_t u = 0; u < ((n + 7u) & ~7u); ++u) {
+        const float sum = acc + __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wt[c]), (int)u));
+        acc = __builtin_amdgcn_inverse_ballot_w64(lane_read64(m[c], u)) ? sum : acc;
+      }
+    }
+  }
+  if (!live) return;
+  float v = a.beta * vp;
+  v = v + acc;
+  v = v - a.theta * sp;
+  v_out[jb] = v;
+  if (s_out) {
+    const float sv = spike_fn(v - a.theta, a.slope, false);
+    s_out[jb] = sv;
+    const uint64_t mk = __ballot(b < a.B && sv != 0.0f);
+    if (b == 0) {
+      a.sbits[(size_t)j * a.T + t] = mk;
+      a.sbits_t[(size_t)t * a.H + j] = mk;
+    }
+  }
+}
+
 // Backward recomputation of one checkpoint segment [t0, t0 + len).  The spikes of every
 // step are stored, so the currents of all the segment's steps are independent: these
 // kernels compute them in parallel, each exactly as k_hidden_step does (input part, then
@@ -686,7 +761,16 @@ uint32_t blocks_for(uint64_t n, uint32_t per) { return (uint32_t)((n + per - 1) 
 
 }  // namespace
 
+// ELL-order copy of the recurrent weights: w_ell[x] = w[edge[x]], 0 for padding.
+__global__ void k_gather_ell(const float *w, const uint32_t *edge, float *w_ell, uint64_t n) {
+  const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < n) w_ell[x] = edge[x] == 0xFFFFFFFFu ? 0.0f : w[edge[x]];
+}
+
 static void gather_weights(const BpttArgs &a, hipStream_t s) {
+  if (a.ell_w)
+    hipLaunchKernelGGL(k_gather_ell, dim3(blocks_for((uint64_t)a.H * a.ell_w, 256)), dim3(256), 0, s, a.w_rec,
+                       a.ell_edge, a.ell_wt, (uint64_t)a.H * a.ell_w);
   if (a.nnz_in)
     hipLaunchKernelGGL(k_gather_t, dim3(blocks_for(a.nnz_in, 256)), dim3(256), 0, s, a.w_in, a.in_t_edge,
                        a.w_in_t, a.nnz_in);
@@ -725,8 +809,18 @@ hipError_t bptt_forward_body(const BpttArgs &g, hipStream_t s) {
     float *v_out = (t % g.K == g.K - 1 || t == g.T - 1) ? g.vck + (size_t)(t / g.K) * g.H * 64
                                                           : g.vtmp + (size_t)(t & 1u) * g.H * 64;
     const float *sprev = t ? g.s + (size_t)(t - 1) * g.H * 64 : nullptr;
-    hipLaunchKernelGGL(k_hidden_step, grid, dim3(256), 0, s, g, t, vprev, sprev, v_out,
-                       g.s + (size_t)t * g.H * 64);
+    float *s_out = g.s + (size_t)t * g.H * 64;
+    if (!g.smooth && g.ell_w) {
+      const size_t lds = (size_t)g.H * sizeof(uint64_t);
+      switch (g.ell_w / kWave) {
+        case 1: hipLaunchKernelGGL(k_hidden_step_ell<1>, grid, dim3(256), lds, s, g, t, vprev, sprev, v_out, s_out); break;
+        case 2: hipLaunchKernelGGL(k_hidden_step_ell<2>, grid, dim3(256), lds, s, g, t, vprev, sprev, v_out, s_out); break;
+        case 3: hipLaunchKernelGGL(k_hidden_step_ell<3>, grid, dim3(256), lds, s, g, t, vprev, sprev, v_out, s_out); break;
+        default: hipLaunchKernelGGL(k_hidden_step_ell<4>, grid, dim3(256), lds, s, g, t, vprev, sprev, v_out, s_out); break;
+      }
+    } else {
+      hipLaunchKernelGGL(k_hidden_step, grid, dim3(256), 0, s, g, t, vprev, sprev, v_out, s_out);
+    }
     vprev = v_out;
   }
   hipLaunchKernelGGL(k_readout_drive, dim3(blocks_for((uint64_t)g.T * g.O * 64, 256)), dim3(256), 0, s, g,

@@ -1585,6 +1585,29 @@ void build_bptt(snn_bptt *p, const uint64_t *in_ptr, const int32_t *in_col, cons
   // per load, the latter from step t - 1 (whose values at t = 0 are not used)
   a.xbits = dev_array<uint64_t>(pool, (size_t)a.C * a.T + 8);
   a.sbits = dev_array<uint64_t>(pool, (size_t)a.H * a.T + 16) + 8;
+  a.sbits_t = dev_array<uint64_t>(pool, (size_t)a.T * a.H);
+  // ELL copy of the recurrent in-edges for the hidden steps (rows padded to a multiple of
+  // 64, at most 256 wide, and at most 8,192 neurons, whose masks a workgroup stages)
+  uint64_t max_deg = 0;
+  for (uint32_t j = 0; j < a.H; ++j) max_deg = std::max<uint64_t>(max_deg, rt_ptr[j + 1] - rt_ptr[j]);
+  a.ell_w = 0;
+  if (nnz_rec && max_deg <= snn::kEllMaxWidth && a.H <= snn::kEllMaxNeurons) {
+    const uint32_t wd = (uint32_t)((max_deg + 63) / 64 * 64);
+    std::vector<int32_t> es((size_t)a.H * wd, 0);
+    std::vector<uint32_t> ee((size_t)a.H * wd, 0xFFFFFFFFu), el(a.H);
+    for (uint32_t j = 0; j < a.H; ++j) {
+      el[j] = (uint32_t)(rt_ptr[j + 1] - rt_ptr[j]);
+      for (uint64_t e = rt_ptr[j]; e < rt_ptr[j + 1]; ++e) {
+        es[(size_t)j * wd + (e - rt_ptr[j])] = rt_src[e];
+        ee[(size_t)j * wd + (e - rt_ptr[j])] = rt_edge[e];
+      }
+    }
+    a.ell_w = wd;
+    a.ell_src = upload(pool, es);
+    a.ell_edge = upload(pool, ee);
+    a.ell_len = upload(pool, el);
+    a.ell_wt = dev_array<float>(pool, es.size());
+  }
   a.flags = dev_array<uint32_t>(pool, 2);
   a.w_in_t = dev_array<float>(pool, std::max<uint64_t>(1, nnz_in));
   a.w_rec_t = dev_array<float>(pool, std::max<uint64_t>(1, nnz_rec));

@@ -195,6 +195,10 @@ hipError_t launch_batch(const BatchNet *nets, const uint32_t *order, uint32_t n_
 // Surrogate-gradient BPTT plan as its kernels see it (bptt.hip).  Batch <= 64: lane b
 // of a wavefront is batch element b; sizes are B batch, T steps, C inputs, H hidden,
 // O readouts, K steps per checkpoint segment (<= 32).
+// Limits of the ELL form of the hidden steps: rows of at most 256 in-edges (four lane
+// loads), and at most 8,192 hidden neurons (their 64 KiB of spike masks in LDS).
+constexpr uint32_t kEllMaxWidth = 256;
+constexpr uint32_t kEllMaxNeurons = 8192;
 struct BpttArgs {
   uint32_t B, T, C, H, O, K;
   float beta, beta_out, theta, slope;
@@ -214,6 +218,12 @@ struct BpttArgs {
   float *w_out_c, *w_rec_c;    // the plan's copies of w_out and of w_rec in CSR order
   float *iin;                  // [T][H][64] input-projection current of every step
   uint64_t *xbits, *sbits;     // batch masks of the input and hidden spikes: [C][T], [H][T]
+  uint64_t *sbits_t;           // the hidden spike masks again, step-major: [T][H]
+  uint32_t ell_w;              // width of the ELL copy of W_rec's in-edges (0: none)
+  const int32_t *ell_src;      // [H][ell_w] sources, ascending, then 0-padding
+  const uint32_t *ell_edge;    // [H][ell_w] CSR edge index (padding: 0xFFFFFFFF)
+  const uint32_t *ell_len;     // [H] in-degree
+  float *ell_wt;               // [H][ell_w] weights gathered into that order (padding: 0)
   uint32_t *flags;             // [2]: a value of x / s is neither 0 nor 1 (masks not used)
   float *xt, *s, *vck, *vtmp, *vseg, *ro, *lamu, *lamv, *lam_carry, *m, *dm;
   int32_t *tmax;

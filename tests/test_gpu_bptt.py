@@ -119,6 +119,16 @@ def test_inputs_other_than_0_and_1():
     _compare(d, 10)
 
 
+def test_recurrent_rows_wider_than_the_ell_form():
+    """In-degrees above 256 (300 hidden neurons, p_rec = 0.95) leave the hidden steps on
+    the CSR form of the recurrent sums; the results are the oracle's all the same."""
+    d = W.bptt_inputs(batch=8, steps=30, n_in=20, n_hidden=300, n_out=5, p_in=0.4, p_rec=0.95,
+                      rate_lo=100.0, rate_hi=400.0, seed=11)
+    assert d["mask_rec"].sum(axis=0).max() > 256
+    plan, fw = _compare(d, 10)
+    assert fw["s"].sum() > 50
+
+
 def test_batch_below_one_wavefront_and_single_step():
     _compare(_small(seed=7, B=3, T=1), 4)
     _compare(_small(seed=8, B=64, T=33, H=70), 32)

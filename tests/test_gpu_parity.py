@@ -68,6 +68,23 @@ def test_long_fixed_rows_match_oracle(k):
     assert i["build_ms"] > 0 and i["gen_fill_ms"] > 0 and i["gen_rows_ms"] > 0 and i["index_ms"] >= 0
 
 
+def test_rows_of_several_fixed_projections():
+    """Rows made of several fixed out-degree segments filled by workgroups: excitatory
+    rows hold 4,500 targets among the excitatory neurons, then 37 among the inhibitory
+    ones (shorter than the four wavefronts), then 4,100 among both populations."""
+    spec = W.brunel_fixed_out(n=7500, k=4100, delay_steps=3, steps=10)
+    spec["projs"] = [
+        {"from": 0, "to": 0, "to_span": 1, "kind": "fixed", "p": 0.0, "k": 4500, "w_mV": 0.1, "plastic": 0},
+        {"from": 0, "to": 1, "to_span": 1, "kind": "fixed", "p": 0.0, "k": 37, "w_mV": 0.1, "plastic": 0},
+        {"from": 1, "to": 0, "to_span": 2, "kind": "fixed", "p": 0.0, "k": 4100, "w_mV": -0.5, "plastic": 0}]
+    print("[gen] several fixed segments per row", flush=True)
+    g = _net(spec, raster_steps=16)
+    o = oracle.OracleNet(spec)
+    rp, col, _ = g.synapses()
+    assert np.array_equal(rp, o.row_ptr())
+    assert np.array_equal(col, o.col())
+
+
 @pytest.mark.parametrize("k", [4500, 5300])
 def test_fixed_rows_beside_er_projections(k):
     """A network with an ER projection besides its fixed out-degree ones keeps one
