@@ -409,7 +409,7 @@ typedef struct snn_bptt snn_bptt;
 
 typedef struct {
     uint32_t batch;        /* 1..64 */
-    uint32_t steps, n_in, n_hidden, n_out;
+    uint32_t steps, n_in, n_hidden, n_out;  /* steps 1..65,535; n_out 1..1,024 */
     uint32_t checkpoint;   /* steps per checkpoint segment, 1..32 */
     float beta, beta_out, theta, slope;
     uint32_t smooth;       /* 0: spiking forward, surrogate backward; 1: smooth forward */

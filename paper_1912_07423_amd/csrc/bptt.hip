@@ -39,25 +39,30 @@ __device__ __forceinline__ float surrogate(float z, float slope, bool smooth) {
   return smooth ? 0.5f * slope * g : g;
 }
 
-// x [B][T][C] -> xt [T][C][64]; lanes >= B hold zeros.  A wavefront is one (t, c), so it
-// also writes that input's batch mask xbits[c][t] (bit b: x = 1 ... or any non-zero
-// value) and sets *flag if some value is neither 0 nor 1 (k_bits' rule).
+// x [B][T][C] -> xt [T][C][64]; lanes >= B hold zeros.  A workgroup per (step t, block of
+// 64 inputs) reads the 64 batch rows of its block (256 bytes each, coalesced) into LDS and
+// writes the block transposed; a wavefront per input c then also writes that input's
+// batch mask xbits[c][t] (bit b: x != 0) and sets *flag if some value is neither 0 nor 1
+// (k_bits' rule).
 __global__ __launch_bounds__(256) void k_transpose_x(const float *x, float *xt, uint64_t *xbits, uint32_t *flag,
                                                      uint32_t B, uint32_t T, uint32_t C) {
-  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t total = (uint64_t)T * C * 64;
-  if (idx >= total) return;  // whole wavefronts: total is a multiple of 64
-  const uint32_t b = (uint32_t)(idx & 63u);
-  const uint64_t tc = idx >> 6;
-  const uint32_t c = (uint32_t)(tc % C), t = (uint32_t)(tc / C);
-  const float v = b < B ? x[((uint64_t)b * T + t) * C + c] : 0.0f;
-  xt[idx] = v;
-  const bool on = b < B && v != 0.0f;
-  const uint64_t m = __ballot(on);
-  const uint64_t bad = __ballot(on && v != 1.0f);
-  if (b == 0) {
-    xbits[(size_t)c * T + t] = m;
-    if (bad) atomicOr(flag, 1u);
+  __shared__ float tile[64][65];
+  const uint32_t t = blockIdx.y, c0 = blockIdx.x * 64u;
+  const uint32_t l = threadIdx.x % 64u, r = threadIdx.x / 64u;
+  for (uint32_t b = r; b < 64u; b += 4u)
+    tile[b][l] = b < B && c0 + l < C ? x[((uint64_t)b * T + t) * C + c0 + l] : 0.0f;
+  __syncthreads();
+  for (uint32_t k = r; k < 64u && c0 + k < C; k += 4u) {
+    const uint32_t c = c0 + k;
+    const float v = tile[l][k];
+    xt[((uint64_t)t * C + c) * 64u + l] = v;
+    const bool on = l < B && v != 0.0f;
+    const uint64_t m = __ballot(on);
+    const uint64_t bad = __ballot(on && v != 1.0f);
+    if (l == 0) {
+      xbits[(size_t)c * T + t] = m;
+      if (bad) atomicOr(flag, 1u);
+    }
   }
 }
 
@@ -789,8 +794,8 @@ hipError_t bptt_forward_prologue(const BpttArgs &a, const float *x, hipStream_t 
   // flags[0] is set below if some input is neither 0 nor 1; flags[1] only by the backward
   // pass of a smooth-mode plan
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, reinterpret_cast<float *>(a.flags), (uint64_t)2, 0.0f);
-  hipLaunchKernelGGL(k_transpose_x, dim3(blocks_for((uint64_t)a.T * a.C * 64, 256)), dim3(256), 0, s, x,
-                     a.xt, a.xbits, a.flags, a.B, a.T, a.C);
+  hipLaunchKernelGGL(k_transpose_x, dim3((a.C + 63) / 64, a.T), dim3(256), 0, s, x, a.xt, a.xbits, a.flags, a.B,
+                     a.T, a.C);
   const hipError_t e = hipMemcpyAsync(a.w_out_c, a.w_out, (size_t)a.H * a.O * 4, hipMemcpyDeviceToDevice, s);
   return e != hipSuccess ? e : hipGetLastError();
 }

@@ -1544,6 +1544,7 @@ void build_bptt(snn_bptt *p, const uint64_t *in_ptr, const int32_t *in_col, cons
   const snn_bptt_desc &d = p->desc;
   if (d.batch < 1 || d.batch > 64) fail(SNN_E_INVALID, "batch must be 1..64");
   if (d.steps < 1 || d.n_in < 1 || d.n_hidden < 1 || d.n_out < 1) fail(SNN_E_INVALID, "empty dimension");
+  if (d.steps > 65535) fail(SNN_E_INVALID, "at most 65,535 steps");
   if (d.checkpoint < 1 || d.checkpoint > 32) fail(SNN_E_INVALID, "checkpoint interval must be 1..32");
   if (d.n_out > 1024) fail(SNN_E_INVALID, "at most 1024 readouts");
   if (!(d.slope > 0.f) || !(d.beta >= 0.f) || !(d.beta_out >= 0.f)) fail(SNN_E_INVALID, "invalid constants");
